@@ -1,0 +1,252 @@
+"""Benchmark: FP32 FFT-demag + RK4 LLG steps on one MI355X.
+
+Workload ``cube128``: a 128^3 cube of 2 nm cells (padded FFT grid 256^3),
+Ms 1e6 A/m, A 1.5e-11 J/m, Ku 5e4 J/m^3 along x, alpha 0.1, gamma0 2.211e5,
+dt 1e-14 s, isotropic random initial M (seed 3128); synthetic data.  A step
+is one classical RK4 step: four demag evaluations (five FFT passes each) and
+four fused field + LLG stage kernels, all on the GPU with the state resident
+in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube128]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def pass_bytes(nx, ny, nz):
+    """Algorithmic bytes per launch of each kernel kind (compulsory reads and
+    writes of the pruned five-pass schedule; neighbour re-reads not counted)."""
+    N = nx * ny * nz
+    nc = 3 * nz * ny * (nx + 1)           # X1 complex elements
+    nc2 = 3 * nz * 2 * ny * (nx + 1)      # X2 complex elements
+    nK = 6 * (nz + 1 if nz > 1 else 1) * (ny + 1) * (nx + 1)
+    b = {
+        "xfwd": 4 * 3 * N + 8 * nc,
+        "xinv": 8 * nc + 4 * 3 * N,
+    }
+    if nz > 1:
+        b["yfwd"] = 8 * nc + 8 * nc2
+        b["zconv"] = 8 * nc2 * 2 + 4 * nK
+        b["yinv"] = 8 * nc2 + 8 * nc
+    else:
+        b["yconv"] = 8 * nc * 2 + 4 * (4 * (ny + 1) * (nx + 1))
+    # RK4 stages read/write 48N, 72N, 72N, 60N bytes: mean per launch
+    b["stage"] = (48 + 72 + 72 + 60) * N / 4.0
+    return b
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1406_7459_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1406_7459_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = kv.get("hbm_bytes_per_launch.%s" % kernel)
+    return float(v) if v else None
+
+
+def cpu_baseline(budget_s=30.0):
+    """The CPU oracle (single-threaded FP64 C), timed on a bounded sample of
+    the cube workload: the same material and cells on a 32^3 cube, set-up
+    excluded, RK4 steps until ~10 s have elapsed."""
+    import oracle
+    from paper_1406_7459_amd import workloads as W
+    wl = W.cube(32)
+    nx, ny, nz = wl.shape
+    dm = oracle.Demag(nx, ny, nz, *wl.cell)
+    m = wl.mat
+    p = oracle.Params(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha, gamma0=m.gamma0,
+                      Hext=m.Hext, dt=m.dt)
+    M = m.Ms * wl.initial_unit()
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        M, _ = dm.run(p, M, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > 10.0 or el > budget_s:
+            break
+    return dict(value=wl.cells * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
+                sample="cube32 (32^3 cells, same material and 2 nm cells), %d RK4 steps in %.1f s, "
+                       "oracle set-up excluded" % (steps, el))
+
+
+def oracle_error_sample(plan, wl, torch):
+    """Relative L2 of the GPU demag field against the oracle's direct sum at
+    sampled cells, for a field of 32 random sources at the full grid size."""
+    import numpy as np
+    import oracle
+    from paper_1406_7459_amd import workloads as W
+    nx, ny, nz = wl.shape
+    M = wl.mat.Ms * W.sparse_sources(nx, ny, nz, 32, seed=77)
+    src = np.flatnonzero(np.abs(M).sum(axis=0).ravel())
+    obs = np.unique(np.concatenate([src, W.sample_cells(nx * ny * nz, 96, seed=78)]))
+    Hg = plan.demag(torch.from_numpy(M.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    Hg = Hg.cpu().numpy().reshape(3, -1)[:, obs].astype(np.float64)
+    Ho = oracle.demag_direct_at(M, wl.cell, obs)
+    return float(np.linalg.norm(Hg - Ho) / np.linalg.norm(Ho)), int(obs.size)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cube128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (got --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1406_7459_amd import mm
+    from paper_1406_7459_amd import workloads as W
+
+    name = args.workload
+    if name.startswith("cube"):
+        wl = W.cube(int(name[4:]))
+    elif name == "film256":
+        wl = W.film256()
+    elif name == "film128":
+        wl = W.film128()
+    else:
+        wl = W.film32()
+    nx, ny, nz = wl.shape
+    m = wl.mat
+    torch.cuda.init()
+    t0 = time.perf_counter()
+    plan = mm.Plan(nx, ny, nz, *wl.cell)
+    setup_s = time.perf_counter() - t0
+    tiles = plan.autotune(reps=5) if not args.no_autotune else plan.info()["tiles"]
+    params = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha,
+                               gamma0=m.gamma0, Hext=m.Hext, dt=m.dt)
+    M = torch.from_numpy((m.Ms * wl.initial_unit()).astype("float32")).cuda()
+    stream = torch.cuda.current_stream()
+
+    # warm-up, then the timed region: K RK4 steps, every launch bracketed by
+    # HIP events on the stream it runs on (per-kernel durations)
+    plan.step(params, M, args.warmup)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.timing()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(params, M, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    per_kernel = plan.timing()
+    plan.set_timing(False)
+    st = plan.reduce(params, M)
+
+    # isolated demag evaluations, graph-free, events around the loop
+    H = torch.empty_like(M)
+    for _ in range(5):
+        plan.demag(M, H)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    nd = 100
+    for _ in range(nd):
+        plan.demag(M, H)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    demag_ms = e0.elapsed_time(e1) / nd
+
+    # Euler steps on the same cube (the integrator of the paper's Table 1)
+    pe = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha,
+                           gamma0=m.gamma0, Hext=m.Hext, dt=m.dt, integrator="euler")
+    Me = M.clone()
+    plan.step(pe, Me, 3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.step(pe, Me, args.steps)
+    torch.cuda.synchronize()
+    euler_ms = (time.perf_counter() - t1) / args.steps * 1e3
+
+    bytes_per = pass_bytes(nx, ny, nz)
+    kern = {}
+    for k, (ms, n) in per_kernel.items():
+        if n > 0:
+            kern[k] = dict(launches=n, avg_us=ms / n * 1e3,
+                           gbs=(bytes_per.get(k, 0) / (ms / n * 1e-3) / 1e9) if k in bytes_per else None)
+    dom = max((k for k in kern if k in bytes_per), key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+    ach = kern[dom]["gbs"]
+    traffic = read_traffic(name, dom)
+    err, nobs = oracle_error_sample(plan, wl, torch)
+    cells = nx * ny * nz
+    out = {
+        "metric": "cell-updates/s",
+        "value": cells * args.steps / el,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "grid": [nx, ny, nz],
+                   "padded_fft_grid": [2 * nx, 2 * ny, 2 * nz if nz > 1 else 2],
+                   "cell_m": list(wl.cell), "integrator": "rk4", "dt_s": m.dt,
+                   "demag_evals_per_step": 4},
+        "demag_evals_per_s": 1e3 / demag_ms,
+        "demag_ms": demag_ms,
+        "euler_ms_per_step": euler_ms,
+        "euler_cell_updates_per_s": cells / (euler_ms * 1e-3),
+        "oracle_err": {"H_demag_rel_l2": err, "bar": 1e-5,
+                       "sample": "32 random unit sources x Ms at full grid size, %d observer cells "
+                                 "(sources included), oracle direct O(N^2) sum" % nobs},
+        "state_after": {"E_tot_J": st["E_tot"], "m_avg": st["m_avg"], "nonfinite": st["nonfinite"]},
+        "kernels": kern,
+        "tiles": tiles,
+        "setup_s": setup_s,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per[dom]},
+        "step_roofline": {
+            "algorithmic_bytes_per_step": sum(4 * v for k, v in bytes_per.items()),
+            "achieved_GBs": sum(4 * v for k, v in bytes_per.items()) / (el / args.steps) / 1e9,
+        },
+        "paper_context": {"table1_128cube_euler_ms_HD7970_fp32": 26.34,
+                          "note": "paper Table 1, Euler, AMD HD 7970, other hardware: context only"},
+    }
+    out["step_roofline"]["frac"] = out["step_roofline"]["achieved_GBs"] / HBM_PEAK_GBS
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

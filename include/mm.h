@@ -1,0 +1,185 @@
+/*
+ * mm.h -- C ABI of the MI355X (gfx950) FFT-demagnetisation + LLG library.
+ *
+ * The library computes, for magnetisation M on an nx x ny x nz grid of equal
+ * dx x dy x dz cells (R. Zhu, arXiv:1406.7459, Sec. 2, cell labelling),
+ *   - the demagnetising field H_demag = K * M as a zero-padded discrete
+ *     convolution evaluated by FFT on the 2nx x 2ny x 2nz grid (Sec. 2,
+ *     eq. (7)-(16); zero-padding steps (1)-(5)); K = -N with N the
+ *     cell-averaged Newell demagnetising tensor, whose transform is taken
+ *     once at set-up (Sec. 3, remark after eq. (16));
+ *   - the Landau-Lifshitz-Gilbert evolution, eq. (6), under the effective
+ *     field of eq. (2): exchange (eq. (3)-(4), free boundaries), uniaxial
+ *     anisotropy (eq. (5), easy-axis form), demag and Zeeman.
+ *
+ * Conventions shared by every entry point
+ *   - Fields M and H are float32, structure-of-arrays [3][nz][ny][nx], x
+ *     fastest, cells zero-indexed; SI units (A/m), lengths in metres.
+ *   - Pointers named *_dev are device (HBM) pointers owned by the caller;
+ *     the library never frees them.  Host pointers are named plainly.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued asynchronously on it unless the entry point
+ *     says it synchronises.
+ *   - Every call returns MM_OK (0) or a negative MM_E* code; no C++
+ *     exception crosses the ABI.  mm_last_error() gives a human-readable
+ *     detail of the last failure on the calling thread.
+ *   - A plan may be used from one host thread / stream at a time.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MM_OK = 0,
+    MM_EINVAL = -1,       /* bad argument (n <= 0, d <= 0, NULL, unsupported length, ...) */
+    MM_ENOMEM = -2,       /* device allocation failed */
+    MM_ENODEV = -3,       /* no HIP device visible */
+    MM_EHIP = -4,         /* a HIP runtime call failed (detail in mm_last_error) */
+    MM_ENONFINITE = -5,   /* a reduction found NaN/Inf in the state */
+    MM_ETUNE = -6,        /* the autotuner found no valid candidate */
+    MM_EUNSUPPORTED = -7  /* valid request outside what this build implements */
+};
+
+enum { MM_RK4 = 0, MM_EULER = 1 };
+
+/* Opaque plan: grid, Newell spectrum, FFT launch configuration, workspace. */
+typedef struct mm_plan_s *mm_plan;
+
+/* Material and integration parameters (Sec. 2, eq. (1)-(6)).
+ *  Ms      saturation magnetisation [A/m]
+ *  A       exchange stiffness [J/m]; H_exch = 2A/(mu0 Ms^2) lap(M)
+ *  Ku      uniaxial anisotropy [J/m^3]; H_anis = 2Ku/(mu0 Ms^2) (u.M) u
+ *  axis    easy axis u (unit vector; the paper uses x)
+ *  alpha   Gilbert damping
+ *  gamma0  gamma*mu0 [m/(A s)], multiplies H in A/m in eq. (6)
+ *  Hext    applied field [A/m]
+ *  dt      time step [s]
+ *  integrator MM_RK4 (classical, 4 field evaluations per step) or MM_EULER
+ *  renorm  1: M <- Ms M/|M| after every step, 0: leave |M| free          */
+typedef struct {
+    double Ms, A, Ku;
+    double axis[3];
+    double alpha, gamma0;
+    double Hext[3];
+    double dt;
+    int integrator;
+    int renorm;
+} mm_llg_params;
+
+/* Observables of a state (Sec. 2, eq. (1) with V = dx dy dz per cell):
+ * energies in J, torque_max = max_i |M_i x H_eff,i| / Ms in A/m,
+ * m_avg = (1/N) sum M/Ms, nonfinite = number of cells holding NaN/Inf.    */
+typedef struct {
+    double E_ex, E_an, E_d, E_z, E_tot;
+    double torque_max;
+    double m_avg[3];
+    long long nonfinite;
+} mm_stats;
+
+/* Plan description filled by mm_plan_query. */
+typedef struct {
+    int nx, ny, nz;
+    int Lx, Ly, Lz;            /* padded FFT lengths 2nx, 2ny, 2nz (Lz = 1 when nz = 1: collapsed) */
+    long long spectrum_count;  /* floats in the stored K~ octant: 6 * (nx+1)(ny+1)(nz+1), nz=1: 6(nx+1)(ny+1) */
+    long long workspace_bytes; /* device bytes held by the plan */
+    int cfg[8];                /* launch tile per pass kind (see MM_PASS_*) */
+} mm_plan_info;
+
+/* Pass kinds of one demag evaluation, for tiles and per-kernel timing. */
+enum {
+    MM_PASS_XFWD = 0,   /* x: real rows -> nx+1 complex, upper half of the padded row zero  */
+    MM_PASS_YFWD = 1,   /* y: forward, input rows j < ny                                     */
+    MM_PASS_ZCONV = 2,  /* z: forward, K~ . M~ (eq. (13)/(15)), inverse, keep k < nz         */
+    MM_PASS_YINV = 3,   /* y: inverse, keep j < ny                                           */
+    MM_PASS_XINV = 4,   /* x: complex -> real, keep i < nx (eq. (16), keep first half)       */
+    MM_PASS_YCONV = 5,  /* nz = 1: y forward, K~ . M~, y inverse in one pass                 */
+    MM_PASS_STAGE = 6,  /* fused H_eff + LLG stage update                                    */
+    MM_PASS_REDUCE = 7, /* observables reduction                                             */
+    MM_PASS_COUNT = 8
+};
+
+/* Build a plan for an nx x ny x nz grid of dx x dy x dz cells (Sec. 2,
+ * eq. (7)-(12), set-up of K~ per the remark after eq. (16)).  Computes the
+ * Newell tensor in FP64 on the current device, its transform in FP64 by
+ * separable cosine/sine sums, and stores the real, parity-folded octant of
+ * K~ = FFT(-N)/(2nx 2ny 2nz) in FP32.  Allocates the plan's workspace with
+ * hipMalloc and synchronises the device before returning.
+ * Supported n per axis: 1..512 with 2n of the form 2^a 3^b and 2n <= 1024.
+ * Errors: MM_EINVAL (bad sizes), MM_ENODEV, MM_ENOMEM, MM_EHIP.            */
+int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_plan *out);
+
+/* H_dev = demagnetising field of M_dev (eq. (11)-(16)).  M_dev, H_dev:
+ * [3][nz][ny][nx] float32 device arrays, not aliased.  Asynchronous.
+ * Errors: MM_EINVAL (NULL plan/pointer, M == H), MM_EHIP.                  */
+int mm_demag_apply(mm_plan plan, const float *M_dev, float *H_dev, void *stream);
+
+/* Advance M_dev (in place) by nsteps time steps of eq. (6) under H_eff of
+ * eq. (2), with classical RK4 (four demag evaluations per step) or explicit
+ * Euler (one).  nsteps = 0 is a no-op.  Asynchronous; the steps are
+ * replayed from a captured HIP graph after the first call with the same
+ * (M_dev, params).  Errors: MM_EINVAL (NULL, nsteps < 0, Ms <= 0, dt not
+ * finite), MM_EHIP.                                                         */
+int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M_dev, int nsteps,
+                void *stream);
+
+/* Observables of state M_dev (energies per eq. (1), max torque, <m>, NaN
+ * count) accumulated in FP64 with a deterministic two-pass wave64
+ * reduction.  Synchronises `stream`.  Returns MM_ENONFINITE (with *out
+ * filled) if any cell is not finite.                                        */
+int mm_reduce(mm_plan plan, const mm_llg_params *params, const float *M_dev, mm_stats *out,
+              void *stream);
+
+/* Newell tensor N in FP64 on the device for the octant of offsets
+ * (i dx, j dy, k dz), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz, written to
+ * N_dev[6][nz][ny][nx] (order xx, yy, zz, xy, xz, yz); N_dev is caller
+ * device memory of 6*nx*ny*nz doubles.  Exact f/g form for centre distance
+ * < 8 cell edges (largest edge), tent-weighted Gauss-Legendre average of the
+ * dipole kernel beyond.  Synchronises `stream`.                             */
+int mm_newell_tensor(int nx, int ny, int nz, double dx, double dy, double dz, double *N_dev,
+                     void *stream);
+
+/* Copy the plan's stored K~ octant (FP32, [6][nzK][ny+1][nx+1], nzK = nz+1,
+ * or 1 when nz = 1; scale and sign folded in) to Kt_dev, which holds
+ * `count` floats (>= mm_plan_info.spectrum_count).  Asynchronous.           */
+int mm_plan_spectrum(mm_plan plan, float *Kt_dev, long long count, void *stream);
+
+/* Describe a plan. */
+int mm_plan_query(mm_plan plan, mm_plan_info *info);
+
+/* Set the launch tile of one pass kind (columns or rows per workgroup; a
+ * power of two).  Returns MM_EINVAL for a tile the pass cannot launch.    */
+int mm_plan_set_tile(mm_plan plan, int pass, int tile);
+
+/* Time every candidate tile of every pass on this plan's buffers and keep
+ * the fastest (hipEvent timing, `reps` launches each).  Candidates must
+ * agree numerically; the chosen tiles are readable with mm_plan_query.
+ * Synchronises.  Errors: MM_ETUNE if no candidate ran.                       */
+int mm_plan_autotune(mm_plan plan, int reps, void *stream);
+
+/* Per-kernel timing: when enabled, every launch of the plan is bracketed
+ * by HIP events on its stream and its duration accumulated per pass kind.
+ * mm_plan_timing synchronises and returns total milliseconds and launch
+ * counts per MM_PASS_* kind (arrays of MM_PASS_COUNT), then resets them.   */
+int mm_plan_set_timing(mm_plan plan, int enable);
+int mm_plan_timing(mm_plan plan, double *total_ms, long long *launches);
+
+/* Release a plan and its device memory (NULL is ignored). */
+void mm_destroy(mm_plan plan);
+
+/* Static description of a status code. */
+const char *mm_status_string(int status);
+
+/* Copy the calling thread's last error detail into buf (NUL-terminated,
+ * truncated to n bytes).  Returns the number of bytes of the full detail. */
+int mm_last_error(char *buf, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MM_H */

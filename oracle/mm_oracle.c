@@ -381,7 +381,11 @@ static int smallest_factor(int n)
     return n;
 }
 
-static void fft_rec(int n, const cplx *in, size_t stride, cplx *out, int sign)
+/* tw[e * tws] = exp(sign 2 pi i e / n) for the current length n; tmp holds
+ * n values of scratch, shared by all levels (a level uses it only after its
+ * sub-transforms have returned). */
+static void fft_rec(int n, const cplx *in, size_t stride, cplx *out, const cplx *tw, size_t tws,
+                    cplx *tmp)
 {
     if (n == 1) {
         out[0] = in[0];
@@ -389,22 +393,30 @@ static void fft_rec(int n, const cplx *in, size_t stride, cplx *out, int sign)
     }
     const int p = smallest_factor(n);
     const int m = n / p;
-    for (int r = 0; r < p; r++) fft_rec(m, in + r * stride, stride * p, out + (size_t)r * m, sign);
-    cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    for (int r = 0; r < p; r++)
+        fft_rec(m, in + r * stride, stride * p, out + (size_t)r * m, tw, tws * p, tmp);
     for (int k = 0; k < m; k++)
         for (int q = 0; q < p; q++) {
             const int kk = k + m * q;
             cplx acc = 0;
             for (int r = 0; r < p; r++) {
-                /* exact integer reduction of the twiddle angle */
-                const long e = ((long)r * kk) % n;
-                const double ang = sign * 2.0 * PI_D * (double)e / (double)n;
-                acc += out[(size_t)r * m + k] * (cos(ang) + I * sin(ang));
+                const long e = ((long)r * kk) % n; /* exact integer reduction of the angle */
+                acc += out[(size_t)r * m + k] * tw[(size_t)e * tws];
             }
             tmp[kk] = acc;
         }
     memcpy(out, tmp, sizeof(cplx) * (size_t)n);
-    free(tmp);
+}
+
+/* Twiddle table exp(sign 2 pi i e / n), e < n. */
+static cplx *twiddles(int n, int sign)
+{
+    cplx *tw = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    for (int e = 0; e < n; e++) {
+        const double ang = sign * 2.0 * PI_D * (double)e / (double)n;
+        tw[e] = cos(ang) + I * sin(ang);
+    }
+    return tw;
 }
 
 /* In-place length-n transform of (re, im). */
@@ -412,14 +424,18 @@ void oracle_fft(int n, double *re, double *im, int sign)
 {
     cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)n);
     cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *t = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *tw = twiddles(n, sign);
     for (int i = 0; i < n; i++) a[i] = re[i] + I * im[i];
-    fft_rec(n, a, 1, b, sign);
+    fft_rec(n, a, 1, b, tw, 1, t);
     for (int i = 0; i < n; i++) {
         re[i] = creal(b[i]);
         im[i] = cimag(b[i]);
     }
     free(a);
     free(b);
+    free(t);
+    free(tw);
 }
 
 /* 3-D transform of a [Pz][Py][Px] complex array, one axis at a time. */
@@ -429,26 +445,32 @@ static void fft3(cplx *a, int Px, int Py, int Pz, int sign)
     if (Pz > mx) mx = Pz;
     cplx *line = (cplx *)malloc(sizeof(cplx) * (size_t)mx);
     cplx *res = (cplx *)malloc(sizeof(cplx) * (size_t)mx);
+    cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)mx);
+    cplx *tx = twiddles(Px, sign), *ty = twiddles(Py, sign), *tz = twiddles(Pz, sign);
     for (int z = 0; z < Pz; z++)
         for (int y = 0; y < Py; y++) {
             cplx *row = a + ((size_t)z * Py + y) * Px;
-            fft_rec(Px, row, 1, res, sign);
+            fft_rec(Px, row, 1, res, tx, 1, tmp);
             memcpy(row, res, sizeof(cplx) * (size_t)Px);
         }
     for (int z = 0; z < Pz; z++)
         for (int x = 0; x < Px; x++) {
             for (int y = 0; y < Py; y++) line[y] = a[((size_t)z * Py + y) * Px + x];
-            fft_rec(Py, line, 1, res, sign);
+            fft_rec(Py, line, 1, res, ty, 1, tmp);
             for (int y = 0; y < Py; y++) a[((size_t)z * Py + y) * Px + x] = res[y];
         }
     for (int y = 0; y < Py; y++)
         for (int x = 0; x < Px; x++) {
             for (int z = 0; z < Pz; z++) line[z] = a[((size_t)z * Py + y) * Px + x];
-            fft_rec(Pz, line, 1, res, sign);
+            fft_rec(Pz, line, 1, res, tz, 1, tmp);
             for (int z = 0; z < Pz; z++) a[((size_t)z * Py + y) * Px + x] = res[z];
         }
     free(line);
     free(res);
+    free(tmp);
+    free(tx);
+    free(ty);
+    free(tz);
 }
 
 /* ------------------------------------------------------------------------ */

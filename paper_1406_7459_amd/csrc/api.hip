@@ -1,0 +1,467 @@
+// api.hip -- the C ABI of include/mm.h: argument checking, plan memory,
+// launch configuration, step driver with HIP-graph replay, timing.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mm_internal.hpp"
+
+namespace mmk {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+bool length_supported(int L);
+
+// ------------------------------------------------------------------ timing ---
+static hipEvent_t take_event(Plan &p)
+{
+    if (!p.event_pool.empty()) {
+        hipEvent_t e = p.event_pool.back();
+        p.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void timing_begin(Plan &p, int pass, hipStream_t s, hipEvent_t *ev0)
+{
+    (void)pass;
+    *ev0 = nullptr;
+    if (!p.timing) return;
+    hipEvent_t e = take_event(p);
+    if (e && hipEventRecord(e, s) == hipSuccess) *ev0 = e;
+}
+
+void timing_end(Plan &p, int pass, hipStream_t s, hipEvent_t ev0)
+{
+    if (!p.timing || !ev0) return;
+    hipEvent_t e1 = take_event(p);
+    if (!e1 || hipEventRecord(e1, s) != hipSuccess) return;
+    p.pending.push_back({pass, {ev0, e1}});
+}
+
+static int drain_timing(Plan &p)
+{
+    for (auto &t : p.pending) {
+        MMK_HIP(hipEventSynchronize(t.second.second));
+        float ms = 0.f;
+        MMK_HIP(hipEventElapsedTime(&ms, t.second.first, t.second.second));
+        p.acc[t.first].ms += ms;
+        p.acc[t.first].n += 1;
+        p.event_pool.push_back(t.second.first);
+        p.event_pool.push_back(t.second.second);
+    }
+    p.pending.clear();
+    return MM_OK;
+}
+
+// ------------------------------------------------------------------- plan ---
+static int upload_twiddles(int L, float2 **dst, std::vector<void *> &owned)
+{
+    std::vector<float2> h((size_t)L);
+    for (int m = 0; m < L; ++m) {
+        const double a = -2.0 * M_PI * (double)m / (double)L;
+        h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    float2 *d = nullptr;
+    MMK_HIP(hipMalloc(&d, sizeof(float2) * (size_t)L));
+    owned.push_back(d);
+    MMK_HIP(hipMemcpy(d, h.data(), sizeof(float2) * (size_t)L, hipMemcpyHostToDevice));
+    *dst = d;
+    return MM_OK;
+}
+
+struct PlanOwner {
+    Plan p;
+    std::vector<void *> owned;
+};
+
+static void free_plan(PlanOwner *o)
+{
+    if (!o) return;
+    Plan &p = o->p;
+    if (p.graph.exec) (void)hipGraphExecDestroy(p.graph.exec);
+    if (p.graph.graph) (void)hipGraphDestroy(p.graph.graph);
+    if (p.cap_stream) (void)hipStreamDestroy(p.cap_stream);
+    for (auto &t : p.pending) {
+        (void)hipEventDestroy(t.second.first);
+        (void)hipEventDestroy(t.second.second);
+    }
+    for (auto e : p.event_pool) (void)hipEventDestroy(e);
+    for (void *ptr : o->owned) (void)hipFree(ptr);
+    delete o;
+}
+
+static bool axis_ok(int n) { return n >= 1 && n <= 512 && length_supported(2 * n); }
+
+static int check_grid(int nx, int ny, int nz, double dx, double dy, double dz)
+{
+    if (!axis_ok(nx) || !axis_ok(ny) || !axis_ok(nz))
+        return fail(MM_EINVAL, "grid sizes must be 1..512 with 2n = 2^a 3^b <= 1024");
+    if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dx) || !std::isfinite(dy) ||
+        !std::isfinite(dz))
+        return fail(MM_EINVAL, "cell sizes must be finite and > 0");
+    return MM_OK;
+}
+
+}  // namespace mmk
+
+using namespace mmk;
+
+struct mm_plan_s {
+    PlanOwner *o;
+};
+
+static Plan *P(mm_plan h) { return (h && h->o) ? &h->o->p : nullptr; }
+
+extern "C" {
+
+const char *mm_status_string(int status)
+{
+    switch (status) {
+    case MM_OK: return "ok";
+    case MM_EINVAL: return "invalid argument";
+    case MM_ENOMEM: return "out of device memory";
+    case MM_ENODEV: return "no HIP device";
+    case MM_EHIP: return "HIP runtime error";
+    case MM_ENONFINITE: return "non-finite value in state";
+    case MM_ETUNE: return "autotuner found no candidate";
+    case MM_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+int mm_last_error(char *buf, size_t n)
+{
+    if (buf && n > 0) {
+        const size_t k = g_err.size() < n - 1 ? g_err.size() : n - 1;
+        std::memcpy(buf, g_err.data(), k);
+        buf[k] = '\0';
+    }
+    return (int)g_err.size();
+}
+
+static int have_device()
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(MM_ENODEV, "no HIP device visible");
+    }
+    return MM_OK;
+}
+
+int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_plan *out)
+{
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_grid(nx, ny, nz, dx, dy, dz);
+    if (rc != MM_OK) return rc;
+    if ((rc = have_device()) != MM_OK) return rc;
+    PlanOwner *o = new PlanOwner();
+    Plan &p = o->p;
+    p.nx = nx; p.ny = ny; p.nz = nz;
+    p.dx = dx; p.dy = dy; p.dz = dz;
+    p.Lx = 2 * nx; p.Ly = 2 * ny; p.Lz = nz > 1 ? 2 * nz : 1;
+    p.nxc = nx + 1;
+    p.nzK = nz > 1 ? nz + 1 : 1;
+    if (hipGetDevice(&p.device) != hipSuccess) {
+        free_plan(o);
+        return fail(MM_EHIP, "hipGetDevice");
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, p.device) == hipSuccess) {
+        p.lds_limit = prop.sharedMemPerBlock;
+        if (p.lds_limit > 160 * 1024) p.lds_limit = 160 * 1024;
+        if (p.lds_limit < 32768) p.lds_limit = 32768;
+    }
+    const size_t N = (size_t)nx * ny * nz;
+    p.nK = 6LL * p.nzK * (ny + 1) * (nx + 1);
+    p.red_blocks = 1024;
+    const size_t szK = sizeof(float) * (size_t)p.nK;
+    const size_t szX1 = sizeof(float2) * 3 * (size_t)nz * ny * p.nxc;
+    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * 2 * ny * p.nxc : 0;
+    const size_t szF = sizeof(float) * 3 * N;
+    const size_t szPart = sizeof(double) * 9 * (size_t)p.red_blocks;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t total = al(szK) + al(szX1) + al(szX2) + 4 * al(szF) + al(szPart) + al(16 * sizeof(double));
+    char *base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) {
+        (void)hipGetLastError();
+        free_plan(o);
+        return fail(MM_ENOMEM, "plan workspace (" + std::to_string(total) + " bytes)");
+    }
+    o->owned.push_back(base);
+    p.bytes = total;
+    char *cur = base;
+    p.Kt = (float *)cur; cur += al(szK);
+    p.X1 = (float2 *)cur; cur += al(szX1);
+    p.X2 = szX2 ? (float2 *)cur : nullptr; cur += al(szX2);
+    p.H = (float *)cur; cur += al(szF);
+    p.Sa = (float *)cur; cur += al(szF);
+    p.Sb = (float *)cur; cur += al(szF);
+    p.kacc = (float *)cur; cur += al(szF);
+    p.part = (double *)cur; cur += al(szPart);
+    p.red = (double *)cur;
+    const int Ls[3] = {p.Lx, p.Ly, nz > 1 ? p.Lz : 0};
+    for (int a = 0; a < 3; ++a) {
+        if (!Ls[a]) continue;
+        if ((rc = upload_twiddles(Ls[a], &p.tw[a], o->owned)) != MM_OK) {
+            free_plan(o);
+            return rc;
+        }
+    }
+    if ((rc = prepare_kernels(p)) != MM_OK) {
+        free_plan(o);
+        return rc;
+    }
+    for (int k = 0; k < MM_PASS_COUNT; ++k) p.tile[k] = pass_default_tile(p, k);
+    if (hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        free_plan(o);
+        return fail(MM_EHIP, "stream create");
+    }
+    if ((rc = build_spectrum(p, nullptr)) != MM_OK) {
+        free_plan(o);
+        return rc;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        free_plan(o);
+        return fail(MM_EHIP, "set-up sync");
+    }
+    mm_plan h = new mm_plan_s{o};
+    *out = h;
+    return MM_OK;
+}
+
+void mm_destroy(mm_plan plan)
+{
+    if (!plan) return;
+    free_plan(plan->o);
+    delete plan;
+}
+
+int mm_demag_apply(mm_plan plan, const float *M, float *H, void *stream)
+{
+    Plan *p = P(plan);
+    if (!p || !M || !H) return fail(MM_EINVAL, "NULL plan or pointer");
+    if ((const void *)M == (const void *)H) return fail(MM_EINVAL, "M and H alias");
+    return demag_enqueue(*p, M, H, (hipStream_t)stream);
+}
+
+static int check_params(const mm_llg_params *q)
+{
+    if (!q) return fail(MM_EINVAL, "params is NULL");
+    if (!(q->Ms > 0.0) || !std::isfinite(q->Ms)) return fail(MM_EINVAL, "Ms must be > 0");
+    if (!std::isfinite(q->dt) || !std::isfinite(q->alpha) || !std::isfinite(q->gamma0) || !std::isfinite(q->A) ||
+        !std::isfinite(q->Ku))
+        return fail(MM_EINVAL, "non-finite parameter");
+    if (q->integrator != MM_RK4 && q->integrator != MM_EULER) return fail(MM_EINVAL, "unknown integrator");
+    const double u2 = q->axis[0] * q->axis[0] + q->axis[1] * q->axis[1] + q->axis[2] * q->axis[2];
+    if (q->Ku != 0.0 && !(std::fabs(u2 - 1.0) < 1e-6)) return fail(MM_EINVAL, "anisotropy axis must be a unit vector");
+    return MM_OK;
+}
+
+int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M, int nsteps, void *stream)
+{
+    Plan *p = P(plan);
+    if (!p || !M) return fail(MM_EINVAL, "NULL plan or M");
+    int rc = check_params(params);
+    if (rc != MM_OK) return rc;
+    if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return MM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const StageCoef c = stage_coef(*p, *params);
+    static const bool no_graph = std::getenv("MM_NO_GRAPH") != nullptr;
+    if (p->timing || no_graph || nsteps < 2) {
+        for (int i = 0; i < nsteps; ++i)
+            if ((rc = llg_enqueue_step(*p, c, params->integrator, M, s)) != MM_OK) return rc;
+        return MM_OK;
+    }
+    std::string key((const char *)&c, sizeof(c));
+    key += std::string((const char *)&params->integrator, sizeof(int));
+    key += std::string((const char *)p->tile, sizeof(p->tile));
+    if (!p->graph.exec || p->graph.M != M || p->graph.key != key) {
+        if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
+        if (p->graph.graph) (void)hipGraphDestroy(p->graph.graph);
+        p->graph = GraphCache{};
+        MMK_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+        rc = llg_enqueue_step(*p, c, params->integrator, M, p->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        if (rc != MM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(MM_EHIP, std::string("capture: ") + hipGetErrorString(e));
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(MM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+        }
+        p->graph.graph = g;
+        p->graph.exec = x;
+        p->graph.M = M;
+        p->graph.key = key;
+    }
+    for (int i = 0; i < nsteps; ++i) MMK_HIP(hipGraphLaunch(p->graph.exec, s));
+    return MM_OK;
+}
+
+int mm_reduce(mm_plan plan, const mm_llg_params *params, const float *M, mm_stats *out, void *stream)
+{
+    Plan *p = P(plan);
+    if (!p || !M || !out) return fail(MM_EINVAL, "NULL plan, M or out");
+    int rc = check_params(params);
+    if (rc != MM_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = demag_enqueue(*p, M, p->H, s)) != MM_OK) return rc;
+    if ((rc = reduce_enqueue(*p, *params, M, p->H, s)) != MM_OK) return rc;
+    double r[9];
+    MMK_HIP(hipMemcpyAsync(r, p->red, sizeof(r), hipMemcpyDeviceToHost, s));
+    MMK_HIP(hipStreamSynchronize(s));
+    const double mu0 = 4e-7 * M_PI;
+    const double V = p->dx * p->dy * p->dz;
+    const double N = (double)p->cells();
+    out->E_ex = params->A * V * r[0];
+    out->E_an = V * r[1];
+    out->E_d = -0.5 * mu0 * V * r[2];
+    out->E_z = -mu0 * V * r[3];
+    out->E_tot = out->E_ex + out->E_an + out->E_d + out->E_z;
+    out->m_avg[0] = r[4] / N;
+    out->m_avg[1] = r[5] / N;
+    out->m_avg[2] = r[6] / N;
+    out->nonfinite = (long long)r[7];
+    out->torque_max = r[8];
+    if (out->nonfinite > 0) return fail(MM_ENONFINITE, std::to_string(out->nonfinite) + " non-finite cells");
+    return MM_OK;
+}
+
+int mm_newell_tensor(int nx, int ny, int nz, double dx, double dy, double dz, double *N, void *stream)
+{
+    if (!N) return fail(MM_EINVAL, "N is NULL");
+    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > (1LL << 31))
+        return fail(MM_EINVAL, "bad grid");
+    if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0)) return fail(MM_EINVAL, "cell sizes must be > 0");
+    int rc = have_device();
+    if (rc != MM_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = newell_octant_device(nx, ny, nz, dx, dy, dz, N, s)) != MM_OK) return rc;
+    MMK_HIP(hipStreamSynchronize(s));
+    return MM_OK;
+}
+
+int mm_plan_spectrum(mm_plan plan, float *Kt, long long count, void *stream)
+{
+    Plan *p = P(plan);
+    if (!p || !Kt) return fail(MM_EINVAL, "NULL plan or Kt");
+    if (count < p->nK) return fail(MM_EINVAL, "Kt too small");
+    MMK_HIP(hipMemcpyAsync(Kt, p->Kt, sizeof(float) * (size_t)p->nK, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return MM_OK;
+}
+
+int mm_plan_query(mm_plan plan, mm_plan_info *info)
+{
+    Plan *p = P(plan);
+    if (!p || !info) return fail(MM_EINVAL, "NULL plan or info");
+    info->nx = p->nx; info->ny = p->ny; info->nz = p->nz;
+    info->Lx = p->Lx; info->Ly = p->Ly; info->Lz = p->Lz;
+    info->spectrum_count = p->nK;
+    info->workspace_bytes = (long long)p->bytes;
+    for (int k = 0; k < 8; ++k) info->cfg[k] = p->tile[k];
+    return MM_OK;
+}
+
+int mm_plan_set_tile(mm_plan plan, int pass, int tile)
+{
+    Plan *p = P(plan);
+    if (!p) return fail(MM_EINVAL, "NULL plan");
+    if (!pass_tile_valid(*p, pass, tile)) return fail(MM_EINVAL, "tile not launchable for this pass");
+    p->tile[pass] = tile;
+    return MM_OK;
+}
+
+int mm_plan_set_timing(mm_plan plan, int enable)
+{
+    Plan *p = P(plan);
+    if (!p) return fail(MM_EINVAL, "NULL plan");
+    p->timing = enable != 0;
+    return MM_OK;
+}
+
+int mm_plan_timing(mm_plan plan, double *total_ms, long long *launches)
+{
+    Plan *p = P(plan);
+    if (!p || !total_ms || !launches) return fail(MM_EINVAL, "NULL argument");
+    int rc = drain_timing(*p);
+    if (rc != MM_OK) return rc;
+    for (int k = 0; k < MM_PASS_COUNT; ++k) {
+        total_ms[k] = p->acc[k].ms;
+        launches[k] = p->acc[k].n;
+        p->acc[k] = TimingAcc{};
+    }
+    return MM_OK;
+}
+
+int mm_plan_autotune(mm_plan plan, int reps, void *stream)
+{
+    Plan *p = P(plan);
+    if (!p) return fail(MM_EINVAL, "NULL plan");
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    // inputs: a finite state in Sa (content does not change the timing)
+    MMK_HIP(hipMemsetAsync(p->Sa, 0, sizeof(float) * 3 * (size_t)p->cells(), s));
+    const bool was = p->timing;
+    p->timing = false;
+    hipEvent_t e0, e1;
+    MMK_HIP(hipEventCreate(&e0));
+    MMK_HIP(hipEventCreate(&e1));
+    int rc = MM_OK;
+    int tuned = 0;
+    for (int pass = 0; pass <= MM_PASS_YCONV && rc == MM_OK; ++pass) {
+        std::vector<int> cand = pass_tile_candidates(*p, pass);
+        if (cand.empty()) continue;
+        const int keep = p->tile[pass];
+        float best = 1e30f;
+        int best_tile = keep;
+        for (int t : cand) {
+            p->tile[pass] = t;
+            // warm-up
+            if ((rc = launch_pass(*p, pass, p->Sa, p->H, s)) != MM_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MM_EHIP, "event"); break; }
+            for (int r = 0; r < reps && rc == MM_OK; ++r) rc = launch_pass(*p, pass, p->Sa, p->H, s);
+            if (rc != MM_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(MM_EHIP, "event");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_tile = t;
+            }
+            ++tuned;
+        }
+        p->tile[pass] = best_tile;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->timing = was;
+    if (rc != MM_OK) return rc;
+    if (tuned == 0) return fail(MM_ETUNE, "no candidate ran");
+    return MM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+// fft_engine.hpp -- register-resident Stockham FFT for gfx950 (wave64).
+//
+// A length-L transform is shared by Q = L/E threads of one workgroup; each
+// thread keeps E complex values in VGPRs.  A stage of radix R lets every
+// thread run E/R butterflies: butterfly j (j = q + Q*b) reads rows
+// j + r*L/R and writes rows (j/Ns)*Ns*R + j%Ns + r*Ns (Stockham autosort,
+// Ns = product of the radices already applied), so the result comes out in
+// natural order with no bit reversal.  Between stages the values cross the
+// threads through LDS; the first stage reads straight from the caller's
+// registers and the last stage leaves its outputs in registers, at rows
+//   q + Q*b + r*L/R_last       (value v[b*R_last + r]).
+// The same row set is what the first stage of a transform in the reversed
+// radix order expects, so a forward transform, a pointwise product and an
+// inverse in reversed order chain with no exchange at all (the spectral
+// product of the demag convolution, paper eq. (13)/(15)).
+//
+// Twiddles come from a per-length table exp(-2 pi i m / L), m < L, built on
+// the host in FP64 and rounded once to FP32.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mmk {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// a * (-i) for the forward sign (DIR = -1), a * (+i) for the inverse.
+template <int DIR>
+__device__ __forceinline__ float2 mul_mi(float2 a)
+{
+    return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// ------------------------------------------------------------ butterflies ---
+template <int DIR>
+__device__ __forceinline__ void bfly2(float2 *x)
+{
+    const float2 a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void bfly3(float2 *x)
+{
+    const float h = 0.86602540378443864676f;  // sqrt(3)/2
+    const float2 t1 = cadd(x[1], x[2]);
+    const float2 t2 = csub(x[0], cscale(t1, 0.5f));
+    const float2 t3 = cscale(mul_mi<DIR>(csub(x[1], x[2])), h);
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(t2, t3);
+    x[2] = csub(t2, t3);
+}
+
+template <int DIR>
+__device__ __forceinline__ void bfly4(float2 *x)
+{
+    const float2 a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
+    const float2 a2 = cadd(x[1], x[3]), a3 = mul_mi<DIR>(csub(x[1], x[3]));
+    x[0] = cadd(a0, a2);
+    x[2] = csub(a0, a2);
+    x[1] = cadd(a1, a3);
+    x[3] = csub(a1, a3);
+}
+
+template <int DIR>
+__device__ __forceinline__ void bfly8(float2 *x)
+{
+    const float s = 0.70710678118654752440f;
+    float2 e[4] = {x[0], x[2], x[4], x[6]};
+    float2 o[4] = {x[1], x[3], x[5], x[7]};
+    bfly4<DIR>(e);
+    bfly4<DIR>(o);
+    // o[k] *= exp(DIR * 2 pi i k / 8)
+    o[1] = cmul(o[1], make_float2(s, DIR * s));
+    o[2] = mul_mi<DIR>(o[2]);
+    o[3] = cmul(o[3], make_float2(-s, DIR * s));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        x[k] = cadd(e[k], o[k]);
+        x[k + 4] = csub(e[k], o[k]);
+    }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void bfly(float2 *x)
+{
+    if constexpr (R == 2) bfly2<DIR>(x);
+    else if constexpr (R == 3) bfly3<DIR>(x);
+    else if constexpr (R == 4) bfly4<DIR>(x);
+    else if constexpr (R == 8) bfly8<DIR>(x);
+    else static_assert(R == 2 || R == 3 || R == 4 || R == 8, "radix");
+}
+
+// ------------------------------------------------- factorisation tables ---
+// Radix order of the forward transform and values per thread E (E must be
+// a multiple of every radix; Q = L/E threads share one transform).
+template <int L> struct Factors;
+#define MMK_FACTORS(LEN, EPT, ...)                                   \
+    template <> struct Factors<LEN> {                                \
+        static constexpr int E = EPT;                                \
+        static constexpr int R[] = {__VA_ARGS__};                    \
+        static constexpr int N = sizeof(R) / sizeof(int);            \
+    };
+MMK_FACTORS(2, 2, 2)
+MMK_FACTORS(4, 4, 4)
+MMK_FACTORS(6, 6, 3, 2)
+MMK_FACTORS(8, 8, 8)
+MMK_FACTORS(12, 12, 3, 4)
+MMK_FACTORS(16, 8, 8, 2)
+MMK_FACTORS(24, 24, 3, 8)
+MMK_FACTORS(32, 8, 8, 4)
+MMK_FACTORS(48, 24, 3, 8, 2)
+MMK_FACTORS(64, 8, 8, 8)
+MMK_FACTORS(96, 24, 3, 8, 4)
+MMK_FACTORS(128, 8, 8, 4, 4)
+MMK_FACTORS(192, 24, 3, 8, 8)
+MMK_FACTORS(256, 8, 8, 8, 4)
+MMK_FACTORS(384, 24, 3, 8, 4, 4)
+MMK_FACTORS(512, 8, 8, 8, 8)
+MMK_FACTORS(768, 24, 3, 8, 8, 4)
+MMK_FACTORS(1024, 8, 8, 8, 4, 4)
+#undef MMK_FACTORS
+
+template <int L, bool REV>
+__device__ __host__ constexpr int radix_at(int s)
+{
+    return REV ? Factors<L>::R[Factors<L>::N - 1 - s] : Factors<L>::R[s];
+}
+template <int L, bool REV>
+__device__ __host__ constexpr int ns_before(int s)
+{
+    int p = 1;
+    for (int i = 0; i < s; ++i) p *= radix_at<L, REV>(i);
+    return p;
+}
+template <int L, bool REV>
+__device__ __host__ constexpr int first_radix() { return radix_at<L, REV>(0); }
+template <int L, bool REV>
+__device__ __host__ constexpr int last_radix() { return radix_at<L, REV>(Factors<L>::N - 1); }
+
+// LDS view of a tile of transforms: element (row, col) at
+// base[row * rs + col * cs].
+struct LdsView {
+    float2 *base;
+    int rs;  // stride between rows of one transform
+    int co;  // this thread's column offset (col * cs), precomputed
+};
+
+// -------------------------------------------------------------- stages ---
+template <int L, int E, int R, int NS, int DIR>
+__device__ __forceinline__ void stage_compute(float2 (&v)[E], int q, const float2 *__restrict__ tw)
+{
+    constexpr int Q = L / E;
+    constexpr int NB = E / R;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        float2 *x = &v[b * R];
+        if constexpr (NS > 1) {
+            const int k = (q + Q * b) % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tw[r * k * (L / (NS * R))];
+                if constexpr (DIR > 0) w.y = -w.y;
+                x[r] = cmul(x[r], w);
+            }
+        }
+        bfly<R, DIR>(x);
+    }
+}
+
+// Write the outputs of a stage (radix R, NS) to LDS, then read the inputs
+// of the next stage (radix R2).  Two barriers: the second keeps the next
+// exchange's writes from overtaking this exchange's reads.
+template <int L, int E, int R, int NS, int R2>
+__device__ __forceinline__ void exchange(float2 (&v)[E], const LdsView &s, int q)
+{
+    constexpr int Q = L / E;
+#pragma unroll
+    for (int b = 0; b < E / R; ++b) {
+        const int j = q + Q * b;
+        const int row = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) s.base[(row + r * NS) * s.rs + s.co] = v[b * R + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < E / R2; ++b) {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[b * R2 + r] = s.base[(q + Q * b + r * (L / R2)) * s.rs + s.co];
+    }
+    __syncthreads();
+}
+
+template <int L, int E, int DIR, bool REV, int S>
+__device__ __forceinline__ void run_stages(float2 (&v)[E], const LdsView &s, int q,
+                                           const float2 *__restrict__ tw)
+{
+    constexpr int R = radix_at<L, REV>(S);
+    constexpr int NS = ns_before<L, REV>(S);
+    stage_compute<L, E, R, NS, DIR>(v, q, tw);
+    if constexpr (S + 1 < Factors<L>::N) {
+        constexpr int R2 = radix_at<L, REV>(S + 1);
+        exchange<L, E, R, NS, R2>(v, s, q);
+        run_stages<L, E, DIR, REV, S + 1>(v, s, q, tw);
+    }
+}
+
+// Full transform.  On entry v[b*R0 + r] holds row q + Q*b + r*L/R0 with
+// R0 = first_radix<L,REV>; on exit v[b*RL + r] holds row q + Q*b + r*L/RL
+// with RL = last_radix<L,REV>.  Every thread of the workgroup must call it
+// (it contains barriers when the transform has more than one stage).
+template <int L, int DIR, bool REV>
+__device__ __forceinline__ void fft(float2 (&v)[Factors<L>::E], const LdsView &s, int q,
+                                    const float2 *__restrict__ tw)
+{
+    run_stages<L, Factors<L>::E, DIR, REV, 0>(v, s, q, tw);
+}
+
+}  // namespace mmk

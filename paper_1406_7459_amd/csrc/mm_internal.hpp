@@ -1,0 +1,113 @@
+// mm_internal.hpp -- host-side plan state and helpers shared by the library's
+// translation units (not part of the public ABI; see include/mm.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mm.h"
+
+namespace mmk {
+
+// thread-local last-error detail
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+#define MMK_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::mmk::fail(MM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// FP32 coefficients of one LLG stage, precomputed on the host in FP64.
+struct StageCoef {
+    float cx, cy, cz;       // 2A/(mu0 Ms^2 d^2) per axis (0 for an axis of length 1)
+    float ka;               // 2Ku/(mu0 Ms^2)
+    float ux, uy, uz;       // easy axis
+    float hx, hy, hz;       // applied field
+    float g;                // gamma0/(1+alpha^2)
+    float gd;               // alpha g / Ms
+    float dt;
+    float Ms;
+    int renorm;
+};
+
+// FP64 coefficients of the observables reduction.
+struct ReduceCoef {
+    double cx, cy, cz, ka, ux, uy, uz, hx, hy, hz;
+    double Ms, A, Ku, dx, dy, dz;
+};
+
+struct TimingAcc {
+    double ms = 0.0;
+    long long n = 0;
+};
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    const float *M = nullptr;
+    std::string key;
+};
+
+struct Plan {
+    int nx = 0, ny = 0, nz = 0;
+    double dx = 0, dy = 0, dz = 0;
+    int Lx = 0, Ly = 0, Lz = 0;  // Lz = 1 when nz == 1 (z collapsed)
+    int nxc = 0;                 // nx + 1
+    int nzK = 0;                 // octant depth of K~: nz + 1, or 1 when nz == 1
+    int device = 0;
+    size_t lds_limit = 65536;
+
+    float *Kt = nullptr;         // [6][nzK][ny+1][nx+1]
+    long long nK = 0;
+    float2 *X1 = nullptr;        // [3][nz][ny][nx+1]
+    float2 *X2 = nullptr;        // [3][nz][2ny][nx+1] (nz > 1 only)
+    float *H = nullptr;          // [3][N] demag field scratch for the step driver
+    float *Sa = nullptr, *Sb = nullptr, *kacc = nullptr;  // stage states and RK4 accumulator
+    double *part = nullptr;      // reduction partials
+    double *red = nullptr;       // final reduction [16]
+    int red_blocks = 0;
+    float2 *tw[3] = {nullptr, nullptr, nullptr};  // twiddles per axis length
+    size_t bytes = 0;
+
+    int tile[MM_PASS_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+    bool timing = false;
+    TimingAcc acc[MM_PASS_COUNT];
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> event_pool;
+
+    GraphCache graph;
+    hipStream_t cap_stream = nullptr;
+
+    long long cells() const { return (long long)nx * ny * nz; }
+};
+
+// Launch helpers (demag.hip).
+bool pass_tile_valid(const Plan &p, int pass, int tile);
+std::vector<int> pass_tile_candidates(const Plan &p, int pass);
+int pass_default_tile(const Plan &p, int pass);
+int prepare_kernels(Plan &p);  // raise LDS limits where needed
+int demag_enqueue(Plan &p, const float *M, float *H, hipStream_t s);
+int launch_pass(Plan &p, int pass, const float *M, float *H, hipStream_t s);
+
+// Timing hooks used around every launch of the plan.
+void timing_begin(Plan &p, int pass, hipStream_t s, hipEvent_t *ev0);
+void timing_end(Plan &p, int pass, hipStream_t s, hipEvent_t ev0);
+
+// Tensor set-up (tensor.hip).
+int newell_octant_device(int nx, int ny, int nz, double dx, double dy, double dz, double *N,
+                         hipStream_t s);
+int build_spectrum(Plan &p, hipStream_t s);
+
+// LLG (llg.hip).
+StageCoef stage_coef(const Plan &p, const mm_llg_params &q);
+int llg_enqueue_step(Plan &p, const StageCoef &c, int integrator, float *M, hipStream_t s);
+int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float *Hd, hipStream_t s);
+
+}  // namespace mmk

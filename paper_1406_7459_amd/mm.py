@@ -1,0 +1,219 @@
+"""ctypes binding of libmm.so (include/mm.h): argument marshalling only.
+
+Tensors are torch tensors on the GPU (float32, [3][nz][ny][nx], contiguous);
+their data pointers and the current torch stream go straight to the C ABI.
+Every computation runs in the library's HIP kernels.  If libmm.so is not
+built, loading raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmm.so")
+
+MM_OK, MM_EINVAL, MM_ENOMEM, MM_ENODEV, MM_EHIP, MM_ENONFINITE, MM_ETUNE, MM_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+MM_RK4, MM_EULER = 0, 1
+PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv", "stage", "reduce")
+PASS_INDEX = {n: i for i, n in enumerate(PASSES)}
+
+SYMBOLS = ("mm_demag_setup", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_newell_tensor",
+           "mm_plan_spectrum", "mm_plan_query", "mm_plan_set_tile", "mm_plan_autotune",
+           "mm_plan_set_timing", "mm_plan_timing", "mm_destroy", "mm_status_string",
+           "mm_last_error")
+
+
+class MMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        lib_ = _lib
+        detail = ""
+        if lib_ is not None:
+            buf = C.create_string_buffer(1024)
+            lib_.mm_last_error(buf, 1024)
+            detail = buf.value.decode(errors="replace")
+            msg = lib_.mm_status_string(code).decode()
+        else:
+            msg = str(code)
+        super().__init__("%s: %s (%d) %s" % (where, msg, code, detail))
+
+
+class LLGParams(C.Structure):
+    """mm_llg_params (Sec. 2, eq. (1)-(6))."""
+    _fields_ = [("Ms", C.c_double), ("A", C.c_double), ("Ku", C.c_double),
+                ("axis", C.c_double * 3), ("alpha", C.c_double), ("gamma0", C.c_double),
+                ("Hext", C.c_double * 3), ("dt", C.c_double), ("integrator", C.c_int),
+                ("renorm", C.c_int)]
+
+    @classmethod
+    def make(cls, Ms, A, Ku=0.0, axis=(1.0, 0.0, 0.0), alpha=0.5, gamma0=2.211e5,
+             Hext=(0.0, 0.0, 0.0), dt=1e-14, integrator="rk4", renorm=True):
+        return cls(float(Ms), float(A), float(Ku), (C.c_double * 3)(*map(float, axis)),
+                   float(alpha), float(gamma0), (C.c_double * 3)(*map(float, Hext)), float(dt),
+                   MM_EULER if integrator == "euler" else MM_RK4, 1 if renorm else 0)
+
+
+class Stats(C.Structure):
+    _fields_ = [("E_ex", C.c_double), ("E_an", C.c_double), ("E_d", C.c_double),
+                ("E_z", C.c_double), ("E_tot", C.c_double), ("torque_max", C.c_double),
+                ("m_avg", C.c_double * 3), ("nonfinite", C.c_longlong)]
+
+    def as_dict(self):
+        return dict(E_ex=self.E_ex, E_an=self.E_an, E_d=self.E_d, E_z=self.E_z, E_tot=self.E_tot,
+                    torque_max=self.torque_max, m_avg=tuple(self.m_avg), nonfinite=self.nonfinite)
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("Lx", C.c_int),
+                ("Ly", C.c_int), ("Lz", C.c_int), ("spectrum_count", C.c_longlong),
+                ("workspace_bytes", C.c_longlong), ("cfg", C.c_int * 8)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmm.so not built: run `python -m paper_1406_7459_amd.build` "
+                          "(expected at %s)" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    vp, i, d, ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
+    L.mm_demag_setup.argtypes = [i, i, i, d, d, d, C.POINTER(vp)]
+    L.mm_demag_apply.argtypes = [vp, vp, vp, vp]
+    L.mm_llg_step.argtypes = [vp, C.POINTER(LLGParams), vp, i, vp]
+    L.mm_reduce.argtypes = [vp, C.POINTER(LLGParams), vp, C.POINTER(Stats), vp]
+    L.mm_newell_tensor.argtypes = [i, i, i, d, d, d, vp, vp]
+    L.mm_plan_spectrum.argtypes = [vp, vp, ll, vp]
+    L.mm_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
+    L.mm_plan_set_tile.argtypes = [vp, i, i]
+    L.mm_plan_autotune.argtypes = [vp, i, vp]
+    L.mm_plan_set_timing.argtypes = [vp, i]
+    L.mm_plan_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
+    L.mm_destroy.argtypes = [vp]
+    L.mm_destroy.restype = None
+    L.mm_status_string.argtypes = [i]
+    L.mm_status_string.restype = C.c_char_p
+    L.mm_last_error.argtypes = [C.c_char_p, C.c_size_t]
+    for name in SYMBOLS:
+        if name not in ("mm_destroy", "mm_status_string"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str):
+    if rc != MM_OK:
+        raise MMError(rc, where)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _field(t: torch.Tensor, shape, name):
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s shape %s != %s" % (name, tuple(t.shape), tuple(shape)))
+    return t.data_ptr()
+
+
+class Plan:
+    """mm_demag_setup / mm_demag_apply / mm_llg_step / mm_reduce."""
+
+    def __init__(self, nx, ny, nz, dx, dy, dz):
+        L = lib()
+        h = C.c_void_p()
+        _check(L.mm_demag_setup(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
+                                C.byref(h)), "mm_demag_setup")
+        self._h = h
+        self.shape = (int(nx), int(ny), int(nz))
+        self.cell = (float(dx), float(dy), float(dz))
+
+    @property
+    def field_shape(self):
+        nx, ny, nz = self.shape
+        return (3, nz, ny, nx)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mm_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def demag(self, M: torch.Tensor, H: torch.Tensor = None, stream=None) -> torch.Tensor:
+        if H is None:
+            H = torch.empty_like(M)
+        pm = _field(M, self.field_shape, "M")
+        ph = _field(H, self.field_shape, "H")
+        _check(lib().mm_demag_apply(self._h, pm, ph, _stream(stream)), "mm_demag_apply")
+        return H
+
+    def step(self, params: LLGParams, M: torch.Tensor, nsteps: int, stream=None) -> torch.Tensor:
+        pm = _field(M, self.field_shape, "M")
+        _check(lib().mm_llg_step(self._h, C.byref(params), pm, int(nsteps), _stream(stream)),
+               "mm_llg_step")
+        return M
+
+    def reduce(self, params: LLGParams, M: torch.Tensor, stream=None, allow_nonfinite=False) -> dict:
+        pm = _field(M, self.field_shape, "M")
+        st = Stats()
+        rc = lib().mm_reduce(self._h, C.byref(params), pm, C.byref(st), _stream(stream))
+        if rc == MM_ENONFINITE and allow_nonfinite:
+            return st.as_dict()
+        _check(rc, "mm_reduce")
+        return st.as_dict()
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(lib().mm_plan_query(self._h, C.byref(inf)), "mm_plan_query")
+        return dict(nx=inf.nx, ny=inf.ny, nz=inf.nz, Lx=inf.Lx, Ly=inf.Ly, Lz=inf.Lz,
+                    spectrum_count=inf.spectrum_count, workspace_bytes=inf.workspace_bytes,
+                    tiles={PASSES[k]: inf.cfg[k] for k in range(8)})
+
+    def spectrum(self, stream=None) -> torch.Tensor:
+        """The stored K~ octant, float32 [6][nzK][ny+1][nx+1]."""
+        inf = self.info()
+        nx, ny, nz = self.shape
+        nzk = nz + 1 if nz > 1 else 1
+        out = torch.empty((6, nzk, ny + 1, nx + 1), dtype=torch.float32, device="cuda")
+        _check(lib().mm_plan_spectrum(self._h, out.data_ptr(), out.numel(), _stream(stream)),
+               "mm_plan_spectrum")
+        assert out.numel() == inf["spectrum_count"]
+        return out
+
+    def set_tile(self, pass_name: str, tile: int):
+        _check(lib().mm_plan_set_tile(self._h, PASS_INDEX[pass_name], int(tile)),
+               "mm_plan_set_tile")
+
+    def autotune(self, reps: int = 10, stream=None):
+        _check(lib().mm_plan_autotune(self._h, int(reps), _stream(stream)), "mm_plan_autotune")
+        return self.info()["tiles"]
+
+    def set_timing(self, enable: bool):
+        _check(lib().mm_plan_set_timing(self._h, 1 if enable else 0), "mm_plan_set_timing")
+
+    def timing(self) -> dict:
+        ms = (C.c_double * 8)()
+        n = (C.c_longlong * 8)()
+        _check(lib().mm_plan_timing(self._h, ms, n), "mm_plan_timing")
+        return {PASSES[k]: (ms[k], n[k]) for k in range(8)}
+
+
+def newell_tensor(nx, ny, nz, dx, dy, dz, stream=None) -> torch.Tensor:
+    """FP64 Newell tensor octant N[6][nz][ny][nx] computed on the GPU."""
+    out = torch.empty((6, nz, ny, nx), dtype=torch.float64, device="cuda")
+    _check(lib().mm_newell_tensor(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
+                                  out.data_ptr(), _stream(stream)), "mm_newell_tensor")
+    return out

@@ -1,0 +1,67 @@
+"""GPU set-up parity: the FP64 Newell tensor and the FP32 stored spectrum of
+K = -N against the CPU oracle (paper Sec. 2 eq. (7)/(12); transform taken once,
+remark after eq. (16))."""
+import numpy as np
+import pytest
+
+import oracle
+from gpucommon import say, to_host
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [((5, 4, 3), (1e-9, 1.3e-9, 0.7e-9)), ((16, 16, 1), (4e-9, 4e-9, 4e-9)),
+         ((12, 6, 4), (4e-9, 4e-9, 2e-9)), ((20, 9, 11), (2e-9, 2e-9, 2e-9)),
+         ((33, 17, 2), (3.90625e-9, 3.90625e-9, 3e-9))]
+
+
+@pytest.mark.parametrize("grid,d", GRIDS)
+def test_newell_octant_matches_oracle(grid, d):
+    from paper_1406_7459_amd import mm
+    say("newell", grid, d)
+    nx, ny, nz = grid
+    Ng = to_host(mm.newell_tensor(nx, ny, nz, *d))
+    No = oracle.tensor_octant(nx, ny, nz, *d)
+    scale = np.abs(No).max()
+    # exact-form region loses ~1e-10 of max to cancellation in either libm
+    assert np.abs(Ng - No).max() <= 2e-9 * scale
+    assert np.abs(Ng[0, 0, 0, 0] + Ng[1, 0, 0, 0] + Ng[2, 0, 0, 0] - 1.0) < 1e-12
+
+
+def _expected_spectrum(nx, ny, nz, d):
+    """K~ from the oracle: K = -N at every signed offset of the wrapped
+    2nx x 2ny x 2nz grid (spare slot +-n left zero), library FFT, real part,
+    octant, scaled by the inverse normalisation (for nz = 1 the two equal z
+    bins are summed by the inverse, hence the factor 2)."""
+    Px, Py, Pz = 2 * nx, 2 * ny, 2 * nz
+    W = np.zeros((6, Pz, Py, Px))
+
+    def off(i, n):
+        return i if i < n else (None if i == n else i - 2 * n)
+
+    for z in range(Pz):
+        Z = off(z, nz)
+        for y in range(Py):
+            Y = off(y, ny)
+            for x in range(Px):
+                X = off(x, nx)
+                if X is None or Y is None or Z is None:
+                    continue
+                W[:, z, y, x] = -oracle.newell(X * d[0], Y * d[1], Z * d[2], *d)
+    F = np.fft.fftn(W, axes=(1, 2, 3))
+    assert np.abs(F.imag).max() <= 1e-9 * np.abs(F).max()
+    if nz > 1:
+        return F.real[:, : nz + 1, : ny + 1, : nx + 1] / (8 * nx * ny * nz)
+    return F.real[:, :1, : ny + 1, : nx + 1] * 2 / (8 * nx * ny * nz)
+
+
+@pytest.mark.parametrize("grid,d", GRIDS[:4])
+def test_stored_spectrum_matches_fft_of_oracle_tensor(grid, d):
+    from paper_1406_7459_amd import mm
+    say("spectrum", grid, d)
+    nx, ny, nz = grid
+    plan = mm.Plan(nx, ny, nz, *d)
+    Kg = to_host(plan.spectrum())
+    Ke = _expected_spectrum(nx, ny, nz, d)
+    assert Kg.shape == Ke.shape
+    assert np.abs(Kg - Ke).max() <= 1e-6 * np.abs(Ke).max()
+    plan.close()
