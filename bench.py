@@ -122,6 +122,9 @@ def main():
     ap.add_argument("--workload", default="cube128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain elementwise copy of 512 MiB (known traffic) for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (got --gpus %d)"
@@ -131,6 +134,17 @@ def main():
     import torch
     from paper_1406_7459_amd import mm
     from paper_1406_7459_amd import workloads as W
+
+    if args.calibrate_copy:
+        n = 128 * 1024 * 1024  # floats: 512 MiB read + 512 MiB written per launch
+        a = torch.ones(n, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "elementwise copy", "bytes_read_per_launch": 4 * n,
+                          "bytes_written_per_launch": 4 * n, "launches": 5}))
+        return
 
     name = args.workload
     if name.startswith("cube"):

@@ -82,7 +82,7 @@ def test_macrospin_precession_on_gpu():
 
 def test_reduce_matches_oracle_observables():
     from paper_1406_7459_amd import mm
-    nx, ny, nz = 20, 12, 6
+    nx, ny, nz = 24, 12, 6
     d = (2e-9, 3e-9, 1.5e-9)
     mat = W.Material(Ms=1e6, A=1.5e-11, Ku=5e4, axis=(1, 0, 0), alpha=0.1, Hext=(2e4, 1e4, -3e4))
     pg, po = _params(mm, mat)
