@@ -110,7 +110,8 @@ enum {
  * separable cosine/sine sums, and stores the real, parity-folded octant of
  * K~ = FFT(-N)/(2nx 2ny 2nz) in FP32.  Allocates the plan's workspace with
  * hipMalloc and synchronises the device before returning.
- * Supported n per axis: 1..512 with 2n of the form 2^a 3^b and 2n <= 1024.
+ * Supported n per axis: 2^a or 3*2^a, 1 <= n <= 512 (padded lengths 2n of
+ * 2, 4, 6, 8, 12, 16, 24, ..., 512, 768, 1024: radices 2, 3, 4, 8).
  * Errors: MM_EINVAL (bad sizes), MM_ENODEV, MM_ENOMEM, MM_EHIP.            */
 int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_plan *out);
 

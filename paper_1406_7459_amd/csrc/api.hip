@@ -108,7 +108,7 @@ static bool axis_ok(int n) { return n >= 1 && n <= 512 && length_supported(2 * n
 static int check_grid(int nx, int ny, int nz, double dx, double dy, double dz)
 {
     if (!axis_ok(nx) || !axis_ok(ny) || !axis_ok(nz))
-        return fail(MM_EINVAL, "grid sizes must be 1..512 with 2n = 2^a 3^b <= 1024");
+        return fail(MM_EINVAL, "grid sizes must be 2^a or 3*2^a, 1..512");
     if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dx) || !std::isfinite(dy) ||
         !std::isfinite(dz))
         return fail(MM_EINVAL, "cell sizes must be finite and > 0");

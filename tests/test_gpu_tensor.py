@@ -54,7 +54,12 @@ def _expected_spectrum(nx, ny, nz, d):
     return F.real[:, :1, : ny + 1, : nx + 1] * 2 / (8 * nx * ny * nz)
 
 
-@pytest.mark.parametrize("grid,d", GRIDS[:4])
+SPEC_GRIDS = [((6, 4, 3), (1e-9, 1.3e-9, 0.7e-9)), ((16, 16, 1), (4e-9, 4e-9, 4e-9)),
+              ((12, 6, 4), (4e-9, 4e-9, 2e-9)), ((24, 8, 12), (2e-9, 2e-9, 2e-9)),
+              ((3, 32, 2), (3.90625e-9, 3.90625e-9, 3e-9))]
+
+
+@pytest.mark.parametrize("grid,d", SPEC_GRIDS)
 def test_stored_spectrum_matches_fft_of_oracle_tensor(grid, d):
     from paper_1406_7459_amd import mm
     say("spectrum", grid, d)
