@@ -153,8 +153,14 @@ int mm_plan_spectrum(mm_plan plan, float *Kt_dev, long long count, void *stream)
 /* Describe a plan. */
 int mm_plan_query(mm_plan plan, mm_plan_info *info);
 
-/* Set the launch tile of one pass kind (columns or rows per workgroup; a
- * power of two).  Returns MM_EINVAL for a tile the pass cannot launch.    */
+/* Set the launch configuration of one pass kind: tile = P + 256 * variant,
+ * P = transforms per workgroup (x rows, or kx columns for y/z; a power of
+ * two <= 128), variant = schedule: for the single-component passes 0 = the
+ * default values per thread E, 1 = 2E; for the product passes (ZCONV, YCONV)
+ * 0 = all three components in one thread's registers, 1 = one component per
+ * thread group with the 3x3 product exchanged through LDS, 2 = as 1 with 2E.
+ * Every configuration computes bitwise the same result.  Returns MM_EINVAL
+ * for a configuration the pass cannot launch.                              */
 int mm_plan_set_tile(mm_plan plan, int pass, int tile);
 
 /* Time every candidate tile of every pass on this plan's buffers and keep

@@ -19,13 +19,19 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+// No implicit multiply-add contraction in the transform code: every fused
+// multiply-add is written out (cmul), so every schedule of a pass -- tile,
+// values per thread, component split -- performs the same operations on every
+// element and gives bitwise the same result.
+#pragma clang fp contract(off)
+
 namespace mmk {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
@@ -50,7 +56,7 @@ __device__ __forceinline__ void bfly3(float2 *x)
 {
     const float h = 0.86602540378443864676f;  // sqrt(3)/2
     const float2 t1 = cadd(x[1], x[2]);
-    const float2 t2 = csub(x[0], cscale(t1, 0.5f));
+    const float2 t2 = make_float2(fmaf(-0.5f, t1.x, x[0].x), fmaf(-0.5f, t1.y, x[0].y));
     const float2 t3 = cscale(mul_mi<DIR>(csub(x[1], x[2])), h);
     x[0] = cadd(x[0], t1);
     x[1] = cadd(t2, t3);
@@ -211,15 +217,30 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], const LdsView &s, int
     }
 }
 
-// Full transform.  On entry v[b*R0 + r] holds row q + Q*b + r*L/R0 with
-// R0 = first_radix<L,REV>; on exit v[b*RL + r] holds row q + Q*b + r*L/RL
-// with RL = last_radix<L,REV>.  Every thread of the workgroup must call it
-// (it contains barriers when the transform has more than one stage).
+// Full transform with E values per thread (E a multiple of every radix of
+// L; Q = L/E threads per transform).  On entry v[b*R0 + r] holds row
+// q + Q*b + r*L/R0 with R0 = first_radix<L,REV>; on exit v[b*RL + r] holds
+// row q + Q*b + r*L/RL with RL = last_radix<L,REV>.  Every thread of the
+// workgroup must call it (it contains barriers when the transform has more
+// than one stage).
+template <int L, int E, int DIR, bool REV>
+__device__ __forceinline__ void fft_e(float2 (&v)[E], const LdsView &s, int q, const float2 *__restrict__ tw)
+{
+    run_stages<L, E, DIR, REV, 0>(v, s, q, tw);
+}
+
 template <int L, int DIR, bool REV>
 __device__ __forceinline__ void fft(float2 (&v)[Factors<L>::E], const LdsView &s, int q,
                                     const float2 *__restrict__ tw)
 {
     run_stages<L, Factors<L>::E, DIR, REV, 0>(v, s, q, tw);
+}
+
+// Values per thread of variant V of length L: V = 0 the default E, V = 1
+// twice as many (half the threads per transform, wider tiles per workgroup).
+template <int L, int V> constexpr int ept()
+{
+    return (V == 1 && 2 * Factors<L>::E <= L) ? 2 * Factors<L>::E : Factors<L>::E;
 }
 
 }  // namespace mmk

@@ -72,7 +72,7 @@ def test_every_tile_gives_identical_field():
             default = plan.info()["tiles"][pname]
             if default == 0:
                 continue
-            for t in (1, 2, 4, 8, 16, 32, 64, 128):
+            for t in [P + 256 * var for var in (0, 1, 2) for P in (1, 2, 4, 8, 16, 32, 64, 128)]:
                 try:
                     plan.set_tile(pname, t)
                 except mm.MMError:
