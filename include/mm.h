@@ -176,6 +176,46 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream);
 int mm_plan_set_timing(mm_plan plan, int enable);
 int mm_plan_timing(mm_plan plan, double *total_ms, long long *launches);
 
+/* ------------------------------------------------------------------------ *
+ * Batches: many independent grids of uneven sizes (e.g. the points of a
+ * field sweep) stepped together.  Each instance is a full plan; a batched
+ * launch runs one pass kind for all instances sharing that pass's transform
+ * length, its workgroups taking (instance, block) coordinates from a task
+ * table; the whole step is replayed from one captured HIP graph.  Results
+ * are bitwise those of the per-instance entry points.
+ * ------------------------------------------------------------------------ */
+typedef struct mm_batch_s *mm_batch;
+
+/* Build `count` plans (arrays of per-instance sizes and cells, host memory;
+ * each instance as in mm_demag_setup) and their task tables.  Synchronises.
+ * Errors: those of mm_demag_setup, MM_EINVAL (count < 1, NULL array).      */
+int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const double *dx, const double *dy,
+                   const double *dz, mm_batch *out);
+
+/* Demag field of every instance: M_dev[i] -> H_dev[i] (host arrays of
+ * `count` device pointers, layout as mm_demag_apply, not aliased).  Waits
+ * for `stream` before updating the pointer table, then enqueues.            */
+int mm_batch_demag(mm_batch batch, const float *const *M_dev, float *const *H_dev, void *stream);
+
+/* nsteps steps of every instance (params: host array of `count`, one
+ * integrator for all; M_dev: host array of `count` device pointers,
+ * advanced in place).  A change of pointers or parameters re-uploads the
+ * instance table (synchronising) and re-captures the step graph.           */
+int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M_dev, int nsteps, void *stream);
+
+/* Tune the tile of every (pass, length) group on the batch's buffers
+ * (hipEvent timing, `reps` launches per candidate).  Synchronises.          */
+int mm_batch_autotune(mm_batch batch, int reps, void *stream);
+
+/* Number of (pass, length) groups, kernel launches per RK4 step, total cells. */
+int mm_batch_query(mm_batch batch, int *groups, int *launches_per_step, long long *cells);
+
+/* Pass kind (MM_PASS_*), transform length and tile of group `index`.       */
+int mm_batch_group_tile(mm_batch batch, int index, int *pass, int *length, int *tile);
+
+/* Release a batch, its plans and tables (NULL is ignored). */
+void mm_batch_destroy(mm_batch batch);
+
 /* Release a plan and its device memory (NULL is ignored). */
 void mm_destroy(mm_plan plan);
 

@@ -124,6 +124,7 @@ struct mm_plan_s {
 };
 
 static Plan *P(mm_plan h) { return (h && h->o) ? &h->o->p : nullptr; }
+Plan *mmk::plan_of(mm_plan h) { return P(h); }
 
 extern "C" {
 

@@ -1,0 +1,560 @@
+// batch.hip -- many independent grids of uneven sizes (for example the
+// points of a field sweep) stepped together.  Every pass of every instance
+// runs through the same kernel bodies as a single plan (demag_kernels.hpp,
+// stage_body.hpp); a batched launch covers one pass kind for all instances
+// that share the transform length of that pass, reading its workgroups'
+// (instance, block) coordinates from a task table.  A whole RK4 step is a
+// fixed sequence of such launches and is captured once into a HIP graph.
+//
+// Grouping by length keeps each launch's register and LDS budget that of its
+// own length (a single launch over every length would size both for the
+// largest).  The launch tile of every (pass, length) group is tuned on the
+// batch's own buffers.
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "demag_kernels.hpp"
+#include "mm_internal.hpp"
+#include "stage_body.hpp"
+
+namespace mmk {
+
+struct BInst {
+    float *M;      // caller state (bound per call)
+    float *Sa, *Sb, *H, *kacc;
+    float *Hout;   // output of the inverse x pass: H for a step, caller H for mm_batch_demag
+    float2 *X1, *X2;
+    const float *Kt;
+    const float2 *tw0, *tw1, *tw2;
+    int nx, ny, nz, pad;
+    StageCoef c;
+};
+
+__device__ __forceinline__ float *bsel(const BInst &I, int s) { return s == 0 ? I.M : (s == 1 ? I.Sa : I.Sb); }
+
+template <int L, int V>
+__global__ __launch_bounds__(1024) void kb_xfwd(const BInst *__restrict__ B, const int4 *__restrict__ T, int sel,
+                                                int lp2)
+{
+    const int4 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    xfwd_body<L, V>(bsel(I, sel), I.X1, 3 * I.nz * I.ny, lp2, I.tw0, t.y);
+}
+template <int L, int V>
+__global__ __launch_bounds__(1024) void kb_yfwd(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
+{
+    const int4 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    yfwd_body<L, V>(I.X1, I.X2, I.nx + 1, lp2, I.tw1, t.y, t.z);
+}
+template <int L, bool Z>
+__global__ __launch_bounds__(conv_max_threads<L>()) void kb_reg3(const BInst *__restrict__ B,
+                                                                  const int4 *__restrict__ T, int lp2)
+{
+    const int4 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    conv_reg3_body<L, Z>(Z ? I.X2 : I.X1, I.Kt, I.nx + 1, I.ny, lp2, Z ? I.tw2 : I.tw1, t.y, t.z);
+}
+template <int L, int V, bool Z>
+__global__ __launch_bounds__(1024) void kb_split(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
+{
+    const int4 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    conv_split_body<L, V, Z>(Z ? I.X2 : I.X1, I.Kt, I.nx + 1, I.ny, lp2, Z ? I.tw2 : I.tw1, t.y, t.z);
+}
+template <int L, int V>
+__global__ __launch_bounds__(1024) void kb_yinv(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
+{
+    const int4 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    yinv_body<L, V>(I.X2, I.X1, I.nx + 1, lp2, I.tw1, t.y, t.z);
+}
+template <int L, int V>
+__global__ __launch_bounds__(1024) void kb_xinv(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
+{
+    const int4 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    xinv_body<L, V>(I.X1, I.Hout, 3 * I.nz * I.ny, lp2, I.tw0, t.y);
+}
+template <int STAGE>
+__global__ __launch_bounds__(256) void kb_stage(const BInst *__restrict__ B, const int2 *__restrict__ T, int ssel,
+                                                int osel)
+{
+    const int2 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    stage_body<STAGE>(bsel(I, ssel), I.H, I.M, I.kacc, bsel(I, osel), I.nx, I.ny, I.nz, I.c,
+                      (size_t)t.y * 256 + threadIdx.x);
+}
+// Euler: the new state, written to Sa, becomes M
+__global__ __launch_bounds__(256) void kb_copy(const BInst *__restrict__ B, const int2 *__restrict__ T)
+{
+    const int2 t = T[blockIdx.x];
+    const BInst &I = B[t.x];
+    const size_t n3 = 3 * (size_t)I.nx * I.ny * I.nz;
+    for (size_t i = (size_t)t.y * 768 + threadIdx.x; i < n3 && i < (size_t)(t.y + 1) * 768; i += 256) I.M[i] = I.Sa[i];
+}
+
+// ---------------------------------------------------------------- host ---
+struct BGroup {
+    int pass = 0, L = 0, tile = 0;
+    int threads = 0;
+    size_t lds = 0;
+    std::vector<int4> tasks;
+    int4 *d = nullptr;
+    size_t cap = 0;
+};
+
+struct BatchImpl {
+    int count = 0;
+    std::vector<mm_plan> plans;
+    std::vector<BInst> inst;
+    BInst *d_inst = nullptr, *d_io = nullptr;
+    std::vector<BGroup> groups;
+    std::vector<int2> stage_tasks, copy_tasks;
+    int2 *d_stage = nullptr, *d_copy = nullptr;
+    size_t lds_limit = 65536;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::string key;
+    std::vector<float *> bound_M;
+    std::string bound_params;
+};
+
+static int pass_len_of(const BInst &I, int pass)
+{
+    switch (pass) {
+    case MM_PASS_XFWD:
+    case MM_PASS_XINV: return 2 * I.nx;
+    case MM_PASS_YFWD:
+    case MM_PASS_YINV: return I.nz > 1 ? 2 * I.ny : 0;
+    case MM_PASS_ZCONV: return I.nz > 1 ? 2 * I.nz : 0;
+    case MM_PASS_YCONV: return I.nz == 1 ? 2 * I.ny : 0;
+    default: return 0;
+    }
+}
+
+static int launch_group(const BGroup &g, const BInst *table, int sel, hipStream_t s, bool raise_only);
+
+static int build_tasks(BatchImpl &b, BGroup &g)
+{
+    const int P = g.tile & 255;
+    g.tasks.clear();
+    for (int i = 0; i < b.count; ++i) {
+        const BInst &I = b.inst[i];
+        if (pass_len_of(I, g.pass) != g.L) continue;
+        const int nxc = I.nx + 1, nrows = 3 * I.nz * I.ny;
+        switch (g.pass) {
+        case MM_PASS_XFWD:
+            for (int bx = 0; bx < (nrows + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));
+            break;
+        case MM_PASS_XINV: {
+            const int pairs = (nrows + 1) / 2;
+            for (int bx = 0; bx < (pairs + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));
+            break;
+        }
+        case MM_PASS_YFWD:
+        case MM_PASS_YINV:
+            for (int pl = 0; pl < 3 * I.nz; ++pl)
+                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, pl, 0));
+            break;
+        case MM_PASS_ZCONV:
+            for (int ky = 0; ky < 2 * I.ny; ++ky)
+                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, ky, 0));
+            break;
+        case MM_PASS_YCONV:
+            for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));
+            break;
+        default: break;
+        }
+    }
+    if (g.tasks.size() > g.cap) {
+        if (g.d) (void)hipFree(g.d);
+        g.d = nullptr;
+        MMK_HIP(hipMalloc(&g.d, sizeof(int4) * g.tasks.size()));
+        g.cap = g.tasks.size();
+    }
+    MMK_HIP(hipMemcpy(g.d, g.tasks.data(), sizeof(int4) * g.tasks.size(), hipMemcpyHostToDevice));
+    int maxt;
+    shape_for(g.pass, g.L, g.tile, g.threads, g.lds, maxt);
+    return launch_group(g, nullptr, 0, nullptr, true);  // raise the LDS limit if this tile needs it
+}
+
+static int ilog2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+template <typename K>
+static void raise_if_needed(K kern, size_t lds)
+{
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int L>
+static void launch_group_len(const BGroup &g, const BInst *table, int sel, hipStream_t s, bool raise_only)
+{
+    const int P = g.tile & 255, var = g.tile >> 8, lp2 = ilog2i(P);
+    const dim3 grid((unsigned)g.tasks.size()), block(g.threads);
+    const size_t lds = g.lds;
+    switch (g.pass) {
+    case MM_PASS_XFWD:
+        if (var == 0) { if (raise_only) raise_if_needed(kb_xfwd<L, 0>, lds); else hipLaunchKernelGGL((kb_xfwd<L, 0>), grid, block, lds, s, table, g.d, sel, lp2); }
+        else { if (raise_only) raise_if_needed(kb_xfwd<L, 1>, lds); else hipLaunchKernelGGL((kb_xfwd<L, 1>), grid, block, lds, s, table, g.d, sel, lp2); }
+        break;
+    case MM_PASS_YFWD:
+        if (var == 0) { if (raise_only) raise_if_needed(kb_yfwd<L, 0>, lds); else hipLaunchKernelGGL((kb_yfwd<L, 0>), grid, block, lds, s, table, g.d, lp2); }
+        else { if (raise_only) raise_if_needed(kb_yfwd<L, 1>, lds); else hipLaunchKernelGGL((kb_yfwd<L, 1>), grid, block, lds, s, table, g.d, lp2); }
+        break;
+    case MM_PASS_YINV:
+        if (var == 0) { if (raise_only) raise_if_needed(kb_yinv<L, 0>, lds); else hipLaunchKernelGGL((kb_yinv<L, 0>), grid, block, lds, s, table, g.d, lp2); }
+        else { if (raise_only) raise_if_needed(kb_yinv<L, 1>, lds); else hipLaunchKernelGGL((kb_yinv<L, 1>), grid, block, lds, s, table, g.d, lp2); }
+        break;
+    case MM_PASS_XINV:
+        if (var == 0) { if (raise_only) raise_if_needed(kb_xinv<L, 0>, lds); else hipLaunchKernelGGL((kb_xinv<L, 0>), grid, block, lds, s, table, g.d, lp2); }
+        else { if (raise_only) raise_if_needed(kb_xinv<L, 1>, lds); else hipLaunchKernelGGL((kb_xinv<L, 1>), grid, block, lds, s, table, g.d, lp2); }
+        break;
+    case MM_PASS_ZCONV:
+    case MM_PASS_YCONV: {
+        const bool z = g.pass == MM_PASS_ZCONV;
+        if (var == 0) {
+            if (z) { if (raise_only) raise_if_needed(kb_reg3<L, true>, lds); else hipLaunchKernelGGL((kb_reg3<L, true>), grid, block, lds, s, table, g.d, lp2); }
+            else { if (raise_only) raise_if_needed(kb_reg3<L, false>, lds); else hipLaunchKernelGGL((kb_reg3<L, false>), grid, block, lds, s, table, g.d, lp2); }
+        } else if (var == 1) {
+            if (z) { if (raise_only) raise_if_needed(kb_split<L, 0, true>, lds); else hipLaunchKernelGGL((kb_split<L, 0, true>), grid, block, lds, s, table, g.d, lp2); }
+            else { if (raise_only) raise_if_needed(kb_split<L, 0, false>, lds); else hipLaunchKernelGGL((kb_split<L, 0, false>), grid, block, lds, s, table, g.d, lp2); }
+        } else {
+            if (z) { if (raise_only) raise_if_needed(kb_split<L, 1, true>, lds); else hipLaunchKernelGGL((kb_split<L, 1, true>), grid, block, lds, s, table, g.d, lp2); }
+            else { if (raise_only) raise_if_needed(kb_split<L, 1, false>, lds); else hipLaunchKernelGGL((kb_split<L, 1, false>), grid, block, lds, s, table, g.d, lp2); }
+        }
+        break;
+    }
+    default: break;
+    }
+}
+
+#define MMK_BATCH_LENGTHS(X)                                                                             \
+    X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) \
+        X(768) X(1024)
+
+static int launch_group(const BGroup &g, const BInst *table, int sel, hipStream_t s, bool raise_only)
+{
+    if (g.tasks.empty()) return MM_OK;
+    switch (g.L) {
+#define MMK_CASE(LEN) case LEN: launch_group_len<LEN>(g, table, sel, s, raise_only); break;
+        MMK_BATCH_LENGTHS(MMK_CASE)
+#undef MMK_CASE
+    default: return fail(MM_EINVAL, "batch: unsupported length");
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+    return MM_OK;
+}
+
+static const int DEMAG_ORDER[6] = {MM_PASS_XFWD, MM_PASS_YFWD, MM_PASS_ZCONV, MM_PASS_YCONV, MM_PASS_YINV,
+                                   MM_PASS_XINV};
+
+static int batch_demag_enqueue(BatchImpl &b, const BInst *table, int sel, hipStream_t s)
+{
+    for (int pass : DEMAG_ORDER)
+        for (const BGroup &g : b.groups)
+            if (g.pass == pass) {
+                int rc = launch_group(g, table, sel, s, false);
+                if (rc != MM_OK) return rc;
+            }
+    return MM_OK;
+}
+
+template <int STAGE>
+static int batch_stage(BatchImpl &b, int ssel, int osel, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_stage<STAGE>, dim3((unsigned)b.stage_tasks.size()), dim3(256), 0, s, b.d_inst, b.d_stage,
+                       ssel, osel);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MM_EHIP, std::string("batch stage: ") + hipGetErrorString(e));
+    return MM_OK;
+}
+
+static int batch_step_enqueue(BatchImpl &b, int integrator, hipStream_t s)
+{
+    int rc;
+    if (integrator == MM_EULER) {
+        if ((rc = batch_demag_enqueue(b, b.d_inst, 0, s)) != MM_OK) return rc;
+        if ((rc = batch_stage<0>(b, 0, 1, s)) != MM_OK) return rc;
+        hipLaunchKernelGGL(kb_copy, dim3((unsigned)b.copy_tasks.size()), dim3(256), 0, s, b.d_inst, b.d_copy);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? MM_OK : fail(MM_EHIP, std::string("batch copy: ") + hipGetErrorString(e));
+    }
+    // stage states: S1 = M, S2 = Sa, S3 = Sb, S4 = Sa; stage 4 writes M
+    if ((rc = batch_demag_enqueue(b, b.d_inst, 0, s)) != MM_OK) return rc;
+    if ((rc = batch_stage<1>(b, 0, 1, s)) != MM_OK) return rc;
+    if ((rc = batch_demag_enqueue(b, b.d_inst, 1, s)) != MM_OK) return rc;
+    if ((rc = batch_stage<2>(b, 1, 2, s)) != MM_OK) return rc;
+    if ((rc = batch_demag_enqueue(b, b.d_inst, 2, s)) != MM_OK) return rc;
+    if ((rc = batch_stage<3>(b, 2, 1, s)) != MM_OK) return rc;
+    if ((rc = batch_demag_enqueue(b, b.d_inst, 1, s)) != MM_OK) return rc;
+    return batch_stage<4>(b, 1, 0, s);
+}
+
+static void drop_graph(BatchImpl &b)
+{
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    b.key.clear();
+}
+
+static void free_batch(BatchImpl *b)
+{
+    if (!b) return;
+    drop_graph(*b);
+    for (BGroup &g : b->groups)
+        if (g.d) (void)hipFree(g.d);
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_io) (void)hipFree(b->d_io);
+    if (b->d_stage) (void)hipFree(b->d_stage);
+    if (b->d_copy) (void)hipFree(b->d_copy);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (mm_plan p : b->plans) mm_destroy(p);
+    delete b;
+}
+
+}  // namespace mmk
+
+using namespace mmk;
+
+struct mm_batch_s {
+    BatchImpl *impl;
+};
+
+extern "C" {
+
+int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const double *dx, const double *dy,
+                   const double *dz, mm_batch *out)
+{
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !nx || !ny || !nz || !dx || !dy || !dz) return fail(MM_EINVAL, "batch: bad arguments");
+    BatchImpl *b = new BatchImpl();
+    b->count = count;
+    int rc = MM_OK;
+    for (int i = 0; i < count && rc == MM_OK; ++i) {
+        mm_plan p = nullptr;
+        rc = mm_demag_setup(nx[i], ny[i], nz[i], dx[i], dy[i], dz[i], &p);
+        if (rc == MM_OK) b->plans.push_back(p);
+    }
+    if (rc != MM_OK) {
+        free_batch(b);
+        return rc;
+    }
+    b->lds_limit = plan_of(b->plans[0])->lds_limit;
+    for (int i = 0; i < count; ++i) {
+        const Plan &p = *plan_of(b->plans[i]);
+        BInst I{};
+        I.M = nullptr;
+        I.Sa = p.Sa; I.Sb = p.Sb; I.H = p.H; I.kacc = p.kacc; I.Hout = p.H;
+        I.X1 = p.X1; I.X2 = p.X2; I.Kt = p.Kt;
+        I.tw0 = p.tw[0]; I.tw1 = p.tw[1]; I.tw2 = p.tw[2];
+        I.nx = p.nx; I.ny = p.ny; I.nz = p.nz;
+        b->inst.push_back(I);
+        const size_t n = (size_t)p.cells();
+        for (size_t blk = 0; blk < (n + 255) / 256; ++blk) b->stage_tasks.push_back(make_int2(i, (int)blk));
+        for (size_t blk = 0; blk < (3 * n + 767) / 768; ++blk) b->copy_tasks.push_back(make_int2(i, (int)blk));
+    }
+    // one group per (pass, length) present in the batch
+    for (int pass : DEMAG_ORDER) {
+        std::vector<int> lens;
+        for (const BInst &I : b->inst) {
+            const int L = pass_len_of(I, pass);
+            if (L && std::find(lens.begin(), lens.end(), L) == lens.end()) lens.push_back(L);
+        }
+        std::sort(lens.begin(), lens.end());
+        for (int L : lens) {
+            BGroup g;
+            g.pass = pass;
+            g.L = L;
+            g.tile = default_tile_for(pass, L, b->lds_limit);
+            b->groups.push_back(g);
+        }
+    }
+    for (BGroup &g : b->groups)
+        if ((rc = build_tasks(*b, g)) != MM_OK) break;
+    auto up = [](void **dst, const void *src, size_t bytes) -> int {
+        if (hipMalloc(dst, bytes) != hipSuccess) return fail(MM_ENOMEM, "batch tables");
+        if (hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return fail(MM_EHIP, "batch upload");
+        return MM_OK;
+    };
+    if (rc == MM_OK) rc = up((void **)&b->d_inst, b->inst.data(), sizeof(BInst) * count);
+    if (rc == MM_OK) rc = up((void **)&b->d_io, b->inst.data(), sizeof(BInst) * count);
+    if (rc == MM_OK) rc = up((void **)&b->d_stage, b->stage_tasks.data(), sizeof(int2) * b->stage_tasks.size());
+    if (rc == MM_OK) rc = up((void **)&b->d_copy, b->copy_tasks.data(), sizeof(int2) * b->copy_tasks.size());
+    if (rc == MM_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        rc = fail(MM_EHIP, "batch stream");
+    if (rc != MM_OK) {
+        free_batch(b);
+        return rc;
+    }
+    *out = new mm_batch_s{b};
+    return MM_OK;
+}
+
+void mm_batch_destroy(mm_batch batch)
+{
+    if (!batch) return;
+    free_batch(batch->impl);
+    delete batch;
+}
+
+int mm_batch_demag(mm_batch batch, const float *const *M, float *const *H, void *stream)
+{
+    if (!batch || !batch->impl || !M || !H) return fail(MM_EINVAL, "NULL batch or pointer table");
+    BatchImpl &b = *batch->impl;
+    std::vector<BInst> io = b.inst;
+    for (int i = 0; i < b.count; ++i) {
+        if (!M[i] || !H[i] || (const void *)M[i] == (const void *)H[i])
+            return fail(MM_EINVAL, "batch demag: NULL or aliased field of instance " + std::to_string(i));
+        io[i].M = const_cast<float *>(M[i]);
+        io[i].Hout = H[i];
+    }
+    hipStream_t s = (hipStream_t)stream;
+    MMK_HIP(hipStreamSynchronize(s));  // the table may still feed an earlier call
+    MMK_HIP(hipMemcpy(b.d_io, io.data(), sizeof(BInst) * b.count, hipMemcpyHostToDevice));
+    return batch_demag_enqueue(b, b.d_io, 0, s);
+}
+
+int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M, int nsteps, void *stream)
+{
+    if (!batch || !batch->impl || !params || !M) return fail(MM_EINVAL, "NULL batch, params or M table");
+    if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
+    BatchImpl &b = *batch->impl;
+    const int integrator = params[0].integrator;
+    for (int i = 0; i < b.count; ++i) {
+        if (!M[i]) return fail(MM_EINVAL, "NULL M of instance " + std::to_string(i));
+        if (params[i].integrator != integrator) return fail(MM_EINVAL, "batch: one integrator for all instances");
+        if (!(params[i].Ms > 0.0) || !std::isfinite(params[i].dt)) return fail(MM_EINVAL, "batch: bad params");
+    }
+    if (nsteps == 0) return MM_OK;
+    hipStream_t s = (hipStream_t)stream;
+    std::string pkey((const char *)params, sizeof(mm_llg_params) * b.count);
+    std::vector<float *> mv(M, M + b.count);
+    if (mv != b.bound_M || pkey != b.bound_params) {
+        for (int i = 0; i < b.count; ++i) {
+            b.inst[i].M = M[i];
+            b.inst[i].Hout = b.inst[i].H;
+            b.inst[i].c = stage_coef(*plan_of(b.plans[i]), params[i]);
+        }
+        MMK_HIP(hipStreamSynchronize(s));
+        MMK_HIP(hipDeviceSynchronize());
+        MMK_HIP(hipMemcpy(b.d_inst, b.inst.data(), sizeof(BInst) * b.count, hipMemcpyHostToDevice));
+        b.bound_M = mv;
+        b.bound_params = pkey;
+        drop_graph(b);
+    }
+    std::string key = std::to_string(integrator);
+    for (const BGroup &g : b.groups) key += "," + std::to_string(g.tile);
+    if (!b.exec || b.key != key) {
+        drop_graph(b);
+        MMK_HIP(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+        int rc = batch_step_enqueue(b, integrator, b.cap);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b.cap, &g);
+        if (rc != MM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(MM_EHIP, std::string("batch capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            b.exec = nullptr;
+            return fail(MM_EHIP, std::string("batch instantiate: ") + hipGetErrorString(e));
+        }
+        b.graph = g;
+        b.key = key;
+    }
+    for (int i = 0; i < nsteps; ++i) MMK_HIP(hipGraphLaunch(b.exec, s));
+    return MM_OK;
+}
+
+int mm_batch_autotune(mm_batch batch, int reps, void *stream)
+{
+    if (!batch || !batch->impl) return fail(MM_EINVAL, "NULL batch");
+    BatchImpl &b = *batch->impl;
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    // time on the internal buffers: the x pass reads Sa (its content does not
+    // change the timing), the others read what the previous pass left
+    for (int i = 0; i < b.count; ++i) {
+        const Plan &p = *plan_of(b.plans[i]);
+        MMK_HIP(hipMemsetAsync(p.Sa, 0, sizeof(float) * 3 * (size_t)p.cells(), s));
+    }
+    MMK_HIP(hipStreamSynchronize(s));
+    hipEvent_t e0, e1;
+    MMK_HIP(hipEventCreate(&e0));
+    MMK_HIP(hipEventCreate(&e1));
+    int rc = MM_OK, tuned = 0;
+    for (BGroup &g : b.groups) {
+        const int keep = g.tile;
+        float best = 1e30f;
+        int best_tile = keep;
+        for (int t : tile_candidates_for(g.pass, g.L, b.lds_limit)) {
+            g.tile = t;
+            if ((rc = build_tasks(b, g)) != MM_OK) break;
+            if ((rc = launch_group(g, b.d_inst, 1, s, false)) != MM_OK) break;
+            (void)hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rc == MM_OK; ++r) rc = launch_group(g, b.d_inst, 1, s, false);
+            (void)hipEventRecord(e1, s);
+            if (rc != MM_OK || hipEventSynchronize(e1) != hipSuccess) {
+                if (rc == MM_OK) rc = fail(MM_EHIP, "batch autotune event");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_tile = t;
+            }
+            ++tuned;
+        }
+        if (rc != MM_OK) break;
+        g.tile = best_tile;
+        if ((rc = build_tasks(b, g)) != MM_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    drop_graph(b);
+    if (rc != MM_OK) return rc;
+    return tuned ? MM_OK : fail(MM_ETUNE, "batch: no candidate ran");
+}
+
+int mm_batch_query(mm_batch batch, int *groups, int *launches_per_step, long long *cells)
+{
+    if (!batch || !batch->impl) return fail(MM_EINVAL, "NULL batch");
+    BatchImpl &b = *batch->impl;
+    if (groups) *groups = (int)b.groups.size();
+    if (launches_per_step) *launches_per_step = 4 * ((int)b.groups.size() + 1);
+    if (cells) {
+        long long c = 0;
+        for (const BInst &I : b.inst) c += (long long)I.nx * I.ny * I.nz;
+        *cells = c;
+    }
+    return MM_OK;
+}
+
+int mm_batch_group_tile(mm_batch batch, int index, int *pass, int *length, int *tile)
+{
+    if (!batch || !batch->impl) return fail(MM_EINVAL, "NULL batch");
+    BatchImpl &b = *batch->impl;
+    if (index < 0 || index >= (int)b.groups.size()) return fail(MM_EINVAL, "group index");
+    if (pass) *pass = b.groups[index].pass;
+    if (length) *length = b.groups[index].L;
+    if (tile) *tile = b.groups[index].tile;
+    return MM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,410 @@
+// demag_kernels.hpp -- device bodies of the demag passes, shared by the
+// per-plan launches (demag.hip) and the batched launches (batch.hip).  Each
+// body takes its workgroup's coordinates explicitly, so a batched launch can
+// feed it coordinates from a task table.
+//
+// Passes of one demagnetising-field evaluation (the zero-padded convolution
+// H = K * M of the paper, Sec. 2 steps (1)-(5), eq. (13)-(16)), evaluated by
+// a real-to-complex FFT that never touches the zero half of the padded grid
+// (forward) nor computes the discarded half (inverse):
+//
+//   XFWD   M [3][nz][ny][nx] f32   -> X1 [3][nz][ny][nx+1] c64   x: R2C, input i < nx
+//   YFWD   X1                      -> X2 [3][nz][2ny][nx+1]      y: input j < ny
+//   ZCONV  X2 -> X2 in place: z forward (input k < nz), H~ = K~ . M~
+//          (eq. (13)/(15), six real K~ components with parity signs),
+//          z inverse, rows k < nz written back
+//   YINV   X2 -> X1                                               y: keep j < ny
+//   XINV   X1 -> H [3][nz][ny][nx] f32                            x: C2R, keep i < nx
+// For nz = 1 the padded z axis has length 2 with the second slot zero, so the
+// z transform is the identity up to a factor folded into K~; YCONV then does
+// y forward, product and y inverse in one pass (XFWD, YCONV, XINV).
+//
+// A workgroup owns a tile of whole 1-D transforms (P consecutive kx columns
+// for y/z, P rows -- P row pairs for XINV -- for x), loads them coalesced
+// straight into registers, and exchanges through LDS only between FFT stages
+// (fft_engine.hpp).
+#pragma once
+#include "fft_engine.hpp"
+
+namespace mmk {
+
+// Twiddles live at the head of the dynamic LDS block (copied once per
+// workgroup; the first read comes after the first exchange barrier, and a
+// single-stage transform reads none).  MMK_TW_GLOBAL keeps them in global
+// memory instead (for A/B timing).
+template <int L> constexpr int tw_slots()
+{
+#ifdef MMK_TW_GLOBAL
+    return 0;
+#else
+    return Factors<L>::N > 1 ? L : 0;
+#endif
+}
+
+template <int L>
+__device__ __forceinline__ const float2 *stage_twiddles(float2 *lds, const float2 *__restrict__ tw)
+{
+    if constexpr (tw_slots<L>() == 0) {
+        return tw;
+    } else {
+        for (int i = threadIdx.x; i < L; i += blockDim.x) lds[i] = tw[i];
+        return lds;
+    }
+}
+
+// ----------------------------------------------------------------- kernels ---
+
+// x forward: one real row of length nx, zero-padded to L = 2nx, -> nx+1 bins.
+template <int L, int V>
+__device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int nrows, int lp2,
+                                          const float2 *__restrict__ tw, int bx)
+{
+    constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2;
+    extern __shared__ float2 lds[];
+    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const int t = threadIdx.x;
+    const int q = t % Q, p = t / Q;
+    const int row = (bx << lp2) + p;
+    const bool ok = row < nrows;
+    const LdsView s{lds + tw_slots<L>(), 1, p * (L + 1)};
+    float2 v[E];
+    constexpr int R0 = first_radix<L, false>();
+    const float *src = M + (size_t)row * NX;
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int i = q + Q * b + r * (L / R0);
+            const bool upper = r * (L / R0) >= NX;  // compile-time after unrolling
+            v[b * R0 + r] = (!upper && ok && i < NX) ? make_float2(src[i], 0.f) : make_float2(0.f, 0.f);
+        }
+    fft_e<L, E, -1, false>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false>();
+    float2 *dst = X1 + (size_t)row * (NX + 1);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int k = q + Q * b + r * (L / RL);
+            if (ok && k <= NX) dst[k] = v[b * RL + r];
+        }
+}
+
+// y forward on a tile of P kx columns of one (component, z) plane.
+template <int L, int V>
+__device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc, int lp2,
+                                          const float2 *__restrict__ tw, int bx, int plane)
+{
+    constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
+    extern __shared__ float2 lds[];
+    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const int P = 1 << lp2;
+    const int t = threadIdx.x;
+    const int p = t & (P - 1), q = t >> lp2;
+    const int kx = bx * P + p;
+    const bool ok = kx < nxc;
+    const LdsView s{lds + tw_slots<L>(), P + 1, p};
+    float2 v[E];
+    constexpr int R0 = first_radix<L, false>();
+    const float2 *src = X1 + (size_t)plane * NY * nxc + kx;
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int j = q + Q * b + r * (L / R0);
+            const bool upper = r * (L / R0) >= NY;
+            v[b * R0 + r] = (!upper && ok && j < NY) ? src[(size_t)j * nxc] : make_float2(0.f, 0.f);
+        }
+    fft_e<L, E, -1, false>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false>();
+    float2 *dst = X2 + (size_t)plane * L * nxc + kx;
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int k = q + Q * b + r * (L / RL);
+            if (ok) dst[(size_t)k * nxc] = v[b * RL + r];
+        }
+}
+
+// One row of the product, k0 m0 + k1 m1 + k2 m2, in a fixed operation order
+// shared by every schedule.
+__device__ __forceinline__ float2 krow(float k0, float k1, float k2, float2 m0, float2 m1, float2 m2)
+{
+    return make_float2(fmaf(k2, m2.x, fmaf(k1, m1.x, k0 * m0.x)), fmaf(k2, m2.y, fmaf(k1, m1.y, k0 * m0.y)));
+}
+
+// Spectral product at one frequency: H~ = K~ . M~ with K~ real and symmetric
+// (eq. (13)/(15)); the off-diagonal entries carry the parity signs of the
+// folded octant.
+__device__ __forceinline__ void kdot(float2 &a, float2 &b, float2 &c, float kxx, float kyy, float kzz,
+                                     float kxy, float kxz, float kyz)
+{
+    const float2 mx = a, my = b, mz = c;
+    a = krow(kxx, kxy, kxz, mx, my, mz);
+    b = krow(kxy, kyy, kyz, mx, my, mz);
+    c = krow(kxz, kyz, kzz, mx, my, mz);
+}
+
+// Three components stay in VGPRs across the product: cap the workgroup so
+// the allocator gets 256 (E = 8) or 512 (E = 24) registers per lane.
+template <int L> constexpr int conv_max_threads() { return Factors<L>::E > 8 ? 256 : 512; }
+
+// Schedule "reg3" of the product pass.  ZAXIS: z forward -> product -> z
+// inverse for P kx columns at one ky, in place on X2 (rows k < nz).  Else
+// (nz = 1): the same along y on X1 (rows j < ny), with xz = yz = 0.
+template <int L, bool ZAXIS>
+__device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int ny,
+                                               int lp2, const float2 *__restrict__ tw, int bx, int ky)
+{
+    constexpr int E = Factors<L>::E, Q = L / E, NH = L / 2;
+    extern __shared__ float2 lds[];
+    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const int P = 1 << lp2;
+    const int t = threadIdx.x;
+    const int p = t & (P - 1), q = t >> lp2;
+    const int kx = bx * P + p;
+    const bool ok = kx < nxc;
+    const LdsView s{lds + tw_slots<L>(), P + 1, p};
+    const size_t rs = ZAXIS ? (size_t)2 * ny * nxc : (size_t)nxc;  // stride along the transform
+    const size_t cs = (size_t)NH * rs;                              // component stride
+    float2 *base = X + (size_t)ky * nxc + kx;
+    float2 va[E], vb[E], vc[E];
+    constexpr int R0 = first_radix<L, false>();
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = q + Q * b + r * (L / R0);
+            const bool upper = r * (L / R0) >= NH;
+            const bool ld = !upper && ok && k < NH;
+            const float2 z = make_float2(0.f, 0.f);
+            va[b * R0 + r] = ld ? base[k * rs] : z;
+            vb[b * R0 + r] = ld ? base[cs + k * rs] : z;
+            vc[b * R0 + r] = ld ? base[2 * cs + k * rs] : z;
+        }
+    fft<L, -1, false>(va, s, q, twl);
+    fft<L, -1, false>(vb, s, q, twl);
+    fft<L, -1, false>(vc, s, q, twl);
+
+    constexpr int RL = last_radix<L, false>();
+    const int nyk = ny + 1;
+    const int kyf = ky <= ny ? ky : 2 * ny - ky;
+    const float sy0 = ky <= ny ? 1.f : -1.f;
+    const size_t kc = ZAXIS ? (size_t)(NH + 1) * nyk * nxc : (size_t)(NH + 1) * nxc;
+    const float *Kb = Kt + (ZAXIS ? (size_t)kyf * nxc : 0) + (ok ? kx : 0);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int k = q + Q * b + r * (L / RL);
+            const int kf = k <= NH ? k : L - k;
+            const float sk = k <= NH ? 1.f : -1.f;
+            const int i = b * RL + r;
+            if constexpr (ZAXIS) {
+                const float *K = Kb + (size_t)kf * nyk * nxc;
+                kdot(va[i], vb[i], vc[i], K[0], K[kc], K[2 * kc], sy0 * K[3 * kc], sk * K[4 * kc],
+                     sy0 * sk * K[5 * kc]);
+            } else {
+                const float *K = Kb + (size_t)kf * nxc;
+                kdot(va[i], vb[i], vc[i], K[0], K[kc], K[2 * kc], sk * K[3 * kc], 0.f, 0.f);
+            }
+        }
+
+    fft<L, +1, true>(va, s, q, twl);
+    fft<L, +1, true>(vb, s, q, twl);
+    fft<L, +1, true>(vc, s, q, twl);
+    // the reversed order ends with radix R0: outputs sit where the inputs did
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = q + Q * b + r * (L / R0);
+            const bool upper = r * (L / R0) >= NH;
+            if (!upper && ok && k < NH) {
+                base[k * rs] = va[b * R0 + r];
+                base[cs + k * rs] = vb[b * R0 + r];
+                base[2 * cs + k * rs] = vc[b * R0 + r];
+            }
+        }
+}
+
+// Schedule "split" of the product pass: three thread groups, one component
+// each (the register footprint of a single-component pass).  After the
+// forward transforms every thread publishes its spectrum values to LDS,
+// reads the other two components at the same frequencies, forms its own row
+// of K~ . M~, and inverse-transforms it.
+template <int L, int V, bool ZAXIS>
+__device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int ny,
+                                                int lp2, const float2 *__restrict__ tw, int bx, int ky)
+{
+    constexpr int E = ept<L, V>(), Q = L / E, NH = L / 2;
+    extern __shared__ float2 lds[];
+    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const int P = 1 << lp2;
+    const int PQ = P * Q;
+    const int g = threadIdx.x / PQ;
+    const int t = threadIdx.x - g * PQ;
+    const int p = t & (P - 1), q = t >> lp2;
+    const int kx = bx * P + p;
+    const bool ok = kx < nxc;
+    const int rsl = P + 1;
+    float2 *buf = lds + tw_slots<L>();
+    const LdsView s{buf + (size_t)g * L * rsl, rsl, p};
+    const size_t rs = ZAXIS ? (size_t)2 * ny * nxc : (size_t)nxc;
+    const size_t cs = (size_t)NH * rs;
+    float2 *base = X + (size_t)g * cs + (size_t)ky * nxc + kx;
+    float2 v[E];
+    constexpr int R0 = first_radix<L, false>();
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = q + Q * b + r * (L / R0);
+            const bool upper = r * (L / R0) >= NH;
+            v[b * R0 + r] = (!upper && ok && k < NH) ? base[k * rs] : make_float2(0.f, 0.f);
+        }
+    fft_e<L, E, -1, false>(v, s, q, twl);
+
+    constexpr int RL = last_radix<L, false>();
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int k = q + Q * b + r * (L / RL);
+            buf[((size_t)g * L + k) * rsl + p] = v[b * RL + r];
+        }
+    __syncthreads();
+    // this group's row of the symmetric tensor: (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
+    const int c0 = g == 0 ? 0 : (g == 1 ? 3 : 4);
+    const int c1 = g == 0 ? 3 : (g == 1 ? 1 : 5);
+    const int c2 = g == 0 ? 4 : (g == 1 ? 5 : 2);
+    const int nyk = ny + 1;
+    const int kyf = ky <= ny ? ky : 2 * ny - ky;
+    const float sy0 = ky <= ny ? 1.f : -1.f;
+    const size_t kc = ZAXIS ? (size_t)(NH + 1) * nyk * nxc : (size_t)(NH + 1) * nxc;
+    const float *Kb = Kt + (ZAXIS ? (size_t)kyf * nxc : 0) + (ok ? kx : 0);
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int k = q + Q * b + r * (L / RL);
+            const int kf = k <= NH ? k : L - k;
+            const float sk = k <= NH ? 1.f : -1.f;
+            // parity signs: ZAXIS: sy on xy, sk on xz, sy*sk on yz; y only: sk on xy
+            const float sxy = ZAXIS ? sy0 : sk, sxz = ZAXIS ? sk : 0.f, syz = ZAXIS ? sy0 * sk : 0.f;
+            const float w0 = g == 0 ? 1.f : (g == 1 ? sxy : sxz);
+            const float w1 = g == 0 ? sxy : (g == 1 ? 1.f : syz);
+            const float w2 = g == 0 ? sxz : (g == 1 ? syz : 1.f);
+            const float *K = Kb + (ZAXIS ? (size_t)kf * nyk * nxc : (size_t)kf * nxc);
+            const float k0 = w0 * K[c0 * kc], k1 = w1 * K[c1 * kc], k2 = w2 * K[c2 * kc];
+            const float2 m0 = buf[((size_t)0 * L + k) * rsl + p];
+            const float2 m1 = buf[((size_t)1 * L + k) * rsl + p];
+            const float2 m2 = buf[((size_t)2 * L + k) * rsl + p];
+            v[b * RL + r] = krow(k0, k1, k2, m0, m1, m2);
+        }
+    __syncthreads();  // every product read is done before the inverse reuses LDS
+    fft_e<L, E, +1, true>(v, s, q, twl);
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = q + Q * b + r * (L / R0);
+            const bool upper = r * (L / R0) >= NH;
+            if (!upper && ok && k < NH) base[k * rs] = v[b * R0 + r];
+        }
+}
+
+// y inverse on a tile of P kx columns of one (component, z) plane, keep j < ny.
+template <int L, int V>
+__device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc, int lp2,
+                                          const float2 *__restrict__ tw, int bx, int plane)
+{
+    constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
+    extern __shared__ float2 lds[];
+    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const int P = 1 << lp2;
+    const int t = threadIdx.x;
+    const int p = t & (P - 1), q = t >> lp2;
+    const int kx = bx * P + p;
+    const bool ok = kx < nxc;
+    const LdsView s{lds + tw_slots<L>(), P + 1, p};
+    float2 v[E];
+    constexpr int R0 = first_radix<L, false>();
+    const float2 *src = X2 + (size_t)plane * L * nxc + kx;
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = q + Q * b + r * (L / R0);
+            v[b * R0 + r] = ok ? src[(size_t)k * nxc] : make_float2(0.f, 0.f);
+        }
+    fft_e<L, E, +1, false>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false>();
+    float2 *dst = X1 + (size_t)plane * NY * nxc + kx;
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int j = q + Q * b + r * (L / RL);
+            const bool upper = r * (L / RL) >= NY;
+            if (!upper && ok && j < NY) dst[(size_t)j * nxc] = v[b * RL + r];
+        }
+}
+
+// x inverse, complex-to-real, two rows per transform: Z = A + iB with A, B
+// the Hermitian half-spectra of rows 2m and 2m+1; Re/Im of the inverse are
+// the two real rows.  Keep i < nx.
+template <int L, int V>
+__device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *__restrict__ H, int nrows, int lp2,
+                                          const float2 *__restrict__ tw, int bx)
+{
+    constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, NXC = NX + 1;
+    extern __shared__ float2 lds[];
+    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const int t = threadIdx.x;
+    const int q = t % Q, p = t / Q;
+    const int ra = ((bx << lp2) + p) * 2, rb = ra + 1;
+    const bool oka = ra < nrows, okb = rb < nrows;
+    const LdsView s{lds + tw_slots<L>(), 1, p * (L + 1)};
+    const float2 *sa = X1 + (size_t)ra * NXC;
+    const float2 *sb = X1 + (size_t)rb * NXC;
+    float2 v[E];
+    constexpr int R0 = first_radix<L, false>();
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = q + Q * b + r * (L / R0);
+            float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
+            if (k <= NX) {
+                if (oka) A = sa[k];
+                if (okb) B = sb[k];
+                if (k == 0 || k == NX) {  // bins of a real row are real there
+                    A.y = 0.f;
+                    B.y = 0.f;
+                }
+            } else {
+                if (oka) A = cconj(sa[L - k]);
+                if (okb) B = cconj(sb[L - k]);
+            }
+            v[b * R0 + r] = make_float2(A.x - B.y, A.y + B.x);
+        }
+    fft_e<L, E, +1, false>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false>();
+    float *da = H + (size_t)ra * NX;
+    float *db = H + (size_t)rb * NX;
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            const int i = q + Q * b + r * (L / RL);
+            const bool upper = r * (L / RL) >= NX;
+            if (!upper && i < NX) {
+                if (oka) da[i] = v[b * RL + r].x;
+                if (okb) db[i] = v[b * RL + r].y;
+            }
+        }
+}
+
+}  // namespace mmk

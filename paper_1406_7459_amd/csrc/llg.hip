@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "mm_internal.hpp"
+#include "stage_body.hpp"
 
 namespace mmk {
 
@@ -19,77 +20,13 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
     return (b % 8u) * per + b / 8u;
 }
 
-// STAGE 1..4: RK4 stages; 0: Euler.  Reads the stage state S (with its six
-// neighbours), the demag field Hd of S, the step's start state Mn and the
-// accumulator; writes the accumulator and the next stage state `out`
-// (stage 4 / Euler: the new state, renormalised if requested).
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_stage(const float *S, const float *__restrict__ Hd, const float *Mn,
                                                float *__restrict__ kacc, float *out, int nx, int ny, int nz,
                                                StageCoef c)
 {
-    const size_t n = (size_t)nx * ny * nz;
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const size_t id = (size_t)b * blockDim.x + threadIdx.x;
-    if (id >= n) return;
-    const int i = (int)(id % nx);
-    const int j = (int)((id / nx) % ny);
-    const int k = (int)(id / ((size_t)nx * ny));
-    const size_t sx = 1, sy = nx, sz = (size_t)nx * ny;
-    const size_t xm = i > 0 ? id - sx : id, xp = i < nx - 1 ? id + sx : id;
-    const size_t ym = j > 0 ? id - sy : id, yp = j < ny - 1 ? id + sy : id;
-    const size_t zm = k > 0 ? id - sz : id, zp = k < nz - 1 ? id + sz : id;
-    float m[3], h[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float *s = S + a * n;
-        const float mc = s[id];
-        m[a] = mc;
-        h[a] = c.cx * (s[xm] + s[xp] - 2.f * mc) + c.cy * (s[ym] + s[yp] - 2.f * mc) +
-               c.cz * (s[zm] + s[zp] - 2.f * mc) + Hd[a * n + id];
-    }
-    const float um = c.ka * (c.ux * m[0] + c.uy * m[1] + c.uz * m[2]);
-    h[0] += um * c.ux + c.hx;
-    h[1] += um * c.uy + c.hy;
-    h[2] += um * c.uz + c.hz;
-    // f = -g m x h - gd m x (m x h)
-    const float t0 = m[1] * h[2] - m[2] * h[1];
-    const float t1 = m[2] * h[0] - m[0] * h[2];
-    const float t2 = m[0] * h[1] - m[1] * h[0];
-    const float d0 = m[1] * t2 - m[2] * t1;
-    const float d1 = m[2] * t0 - m[0] * t2;
-    const float d2 = m[0] * t1 - m[1] * t0;
-    const float f[3] = {-c.g * t0 - c.gd * d0, -c.g * t1 - c.gd * d1, -c.g * t2 - c.gd * d2};
-    float mn[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) mn[a] = Mn[a * n + id];
-    if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) {
-        const float step = STAGE == 3 ? c.dt : 0.5f * c.dt;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float acc = STAGE == 1 ? f[a] : kacc[a * n + id] + 2.f * f[a];
-            kacc[a * n + id] = acc;
-            out[a * n + id] = mn[a] + step * f[a];
-        }
-    } else {
-        float r[3];
-        if constexpr (STAGE == 4) {
-            const float w = c.dt * (1.f / 6.f);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) r[a] = mn[a] + w * (kacc[a * n + id] + f[a]);
-        } else {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) r[a] = mn[a] + c.dt * f[a];
-        }
-        if (c.renorm) {
-            const float nn = sqrtf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
-            const float sc = nn > 0.f ? c.Ms / nn : 1.f;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) r[a] *= sc;
-        }
-#pragma unroll
-        for (int a = 0; a < 3; ++a) out[a * n + id] = r[a];
-    }
+    stage_body<STAGE>(S, Hd, Mn, kacc, out, nx, ny, nz, c, (size_t)b * blockDim.x + threadIdx.x);
 }
 
 StageCoef stage_coef(const Plan &p, const mm_llg_params &q)

@@ -88,6 +88,14 @@ struct Plan {
     long long cells() const { return (long long)nx * ny * nz; }
 };
 
+Plan *plan_of(mm_plan h);
+
+// Launch configurations by (pass, transform length) (demag.hip).
+bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt);
+bool tile_valid_for(int pass, int L, int tile, size_t lds_limit);
+std::vector<int> tile_candidates_for(int pass, int L, size_t lds_limit);
+int default_tile_for(int pass, int L, size_t lds_limit);
+
 // Launch helpers (demag.hip).
 bool pass_tile_valid(const Plan &p, int pass, int tile);
 std::vector<int> pass_tile_candidates(const Plan &p, int pass);

@@ -25,7 +25,8 @@ PASS_INDEX = {n: i for i, n in enumerate(PASSES)}
 SYMBOLS = ("mm_demag_setup", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_newell_tensor",
            "mm_plan_spectrum", "mm_plan_query", "mm_plan_set_tile", "mm_plan_autotune",
            "mm_plan_set_timing", "mm_plan_timing", "mm_destroy", "mm_status_string",
-           "mm_last_error")
+           "mm_last_error", "mm_batch_setup", "mm_batch_demag", "mm_batch_step",
+           "mm_batch_autotune", "mm_batch_query", "mm_batch_group_tile", "mm_batch_destroy")
 
 
 class MMError(RuntimeError):
@@ -100,11 +101,20 @@ def lib():
     L.mm_plan_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
     L.mm_destroy.argtypes = [vp]
     L.mm_destroy.restype = None
+    ip, dp = C.POINTER(C.c_int), C.POINTER(C.c_double)
+    L.mm_batch_setup.argtypes = [i, ip, ip, ip, dp, dp, dp, C.POINTER(vp)]
+    L.mm_batch_demag.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+    L.mm_batch_step.argtypes = [vp, C.POINTER(LLGParams), C.POINTER(vp), i, vp]
+    L.mm_batch_autotune.argtypes = [vp, i, vp]
+    L.mm_batch_query.argtypes = [vp, ip, ip, C.POINTER(C.c_longlong)]
+    L.mm_batch_group_tile.argtypes = [vp, i, ip, ip, ip]
+    L.mm_batch_destroy.argtypes = [vp]
+    L.mm_batch_destroy.restype = None
     L.mm_status_string.argtypes = [i]
     L.mm_status_string.restype = C.c_char_p
     L.mm_last_error.argtypes = [C.c_char_p, C.c_size_t]
     for name in SYMBOLS:
-        if name not in ("mm_destroy", "mm_status_string"):
+        if name not in ("mm_destroy", "mm_status_string", "mm_batch_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -217,3 +227,69 @@ def newell_tensor(nx, ny, nz, dx, dy, dz, stream=None) -> torch.Tensor:
     _check(lib().mm_newell_tensor(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
                                   out.data_ptr(), _stream(stream)), "mm_newell_tensor")
     return out
+
+
+class Batch:
+    """mm_batch_*: many grids of uneven sizes stepped by grouped launches."""
+
+    def __init__(self, shapes, cells):
+        L = lib()
+        n = len(shapes)
+        arr = lambda t, v: (t * n)(*v)  # noqa: E731
+        h = C.c_void_p()
+        _check(L.mm_batch_setup(n, arr(C.c_int, [s[0] for s in shapes]),
+                                arr(C.c_int, [s[1] for s in shapes]),
+                                arr(C.c_int, [s[2] for s in shapes]),
+                                arr(C.c_double, [c[0] for c in cells]),
+                                arr(C.c_double, [c[1] for c in cells]),
+                                arr(C.c_double, [c[2] for c in cells]), C.byref(h)),
+               "mm_batch_setup")
+        self._h = h
+        self.shapes = [tuple(map(int, s)) for s in shapes]
+        self.count = n
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mm_batch_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _ptrs(self, fields, name):
+        if len(fields) != self.count:
+            raise ValueError("%s: %d fields for %d instances" % (name, len(fields), self.count))
+        return (C.c_void_p * self.count)(*[
+            _field(f, (3, s[2], s[1], s[0]), name) for f, s in zip(fields, self.shapes)])
+
+    def demag(self, Ms, Hs=None, stream=None):
+        if Hs is None:
+            Hs = [torch.empty_like(m) for m in Ms]
+        _check(lib().mm_batch_demag(self._h, self._ptrs(Ms, "M"), self._ptrs(Hs, "H"), _stream(stream)),
+               "mm_batch_demag")
+        return Hs
+
+    def step(self, params, Ms, nsteps, stream=None):
+        if len(params) != self.count:
+            raise ValueError("one parameter set per instance")
+        pa = (LLGParams * self.count)(*params)
+        _check(lib().mm_batch_step(self._h, pa, self._ptrs(Ms, "M"), int(nsteps), _stream(stream)),
+               "mm_batch_step")
+        return Ms
+
+    def autotune(self, reps=5, stream=None):
+        _check(lib().mm_batch_autotune(self._h, int(reps), _stream(stream)), "mm_batch_autotune")
+        return self.groups()
+
+    def query(self):
+        g, n, c = C.c_int(), C.c_int(), C.c_longlong()
+        _check(lib().mm_batch_query(self._h, C.byref(g), C.byref(n), C.byref(c)), "mm_batch_query")
+        return dict(groups=g.value, launches_per_step=n.value, cells=c.value)
+
+    def groups(self):
+        out = []
+        for k in range(self.query()["groups"]):
+            p, L_, t = C.c_int(), C.c_int(), C.c_int()
+            _check(lib().mm_batch_group_tile(self._h, k, C.byref(p), C.byref(L_), C.byref(t)),
+                   "mm_batch_group_tile")
+            out.append((PASSES[p.value], L_.value, t.value))
+        return out

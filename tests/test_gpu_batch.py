@@ -1,0 +1,90 @@
+"""Batched form: many grids of uneven sizes stepped by grouped launches must
+give bitwise the per-instance results (same kernel bodies, same arithmetic)."""
+import numpy as np
+import pytest
+
+from gpucommon import say, to_dev, to_host
+from paper_1406_7459_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [((16, 24, 1), (4e-9, 4e-9, 2e-9)), ((32, 16, 2), (4e-9, 4e-9, 2e-9)),
+         ((24, 48, 4), (4e-9, 4e-9, 2e-9)), ((16, 16, 8), (4e-9, 4e-9, 2e-9)),
+         ((48, 32, 1), (4e-9, 4e-9, 2e-9)), ((32, 32, 2), (2e-9, 2e-9, 2e-9)),
+         ((12, 6, 3), (1e-9, 1.3e-9, 0.7e-9)), ((64, 8, 1), (4e-9, 4e-9, 2e-9)),
+         ((1, 1, 1), (2e-9, 2e-9, 2e-9))]
+
+
+def _params(mm, i, integrator="rk4"):
+    return mm.LLGParams.make(Ms=8e5, A=1.3e-11, Ku=1e4 * (i % 3), alpha=0.3 + 0.05 * i,
+                             Hext=(1e4 * (i - 4), 2e3 * i, -5e3), dt=1e-14, integrator=integrator)
+
+
+def test_batched_demag_is_bitwise_per_instance():
+    from paper_1406_7459_amd import mm
+    b = mm.Batch([s for s, _ in SMALL], [d for _, d in SMALL])
+    Ms = [to_dev(8e5 * W.random_unit(*s, seed=i)) for i, (s, _) in enumerate(SMALL)]
+    Hb = [to_host(h) for h in b.demag(Ms)]
+    for i, (s, d) in enumerate(SMALL):
+        plan = mm.Plan(*s, *d)
+        Hp = to_host(plan.demag(Ms[i]))
+        assert np.array_equal(Hb[i], Hp), s
+        plan.close()
+    b.autotune(reps=2)
+    Hb2 = [to_host(h) for h in b.demag(Ms)]
+    for i in range(len(SMALL)):
+        assert np.array_equal(Hb2[i], Hb[i])
+    b.close()
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "euler"])
+def test_batched_steps_are_bitwise_per_instance(integrator):
+    from paper_1406_7459_amd import mm
+    b = mm.Batch([s for s, _ in SMALL], [d for _, d in SMALL])
+    M0 = [8e5 * W.random_unit(*s, seed=10 + i) for i, (s, _) in enumerate(SMALL)]
+    Mb = [to_dev(m) for m in M0]
+    params = [_params(mm, i, integrator) for i in range(len(SMALL))]
+    b.step(params, Mb, 7)
+    for i, (s, d) in enumerate(SMALL):
+        plan = mm.Plan(*s, *d)
+        Mp = to_dev(M0[i])
+        plan.step(params[i], Mp, 7)
+        assert np.array_equal(to_host(Mb[i]), to_host(Mp)), (s, integrator)
+        plan.close()
+    b.close()
+
+
+def test_sweep_batch_full_size_matches_per_instance():
+    """The 64-film field sweep at full size: a few instances checked bitwise
+    after two batched steps (autotuned groups)."""
+    from paper_1406_7459_amd import mm
+    wls = W.sweep64()
+    b = mm.Batch([w.shape for w in wls], [w.cell for w in wls])
+    say("sweep64 groups", b.query())
+    b.autotune(reps=2)
+    Ms = [to_dev(w.mat.Ms * w.initial_unit()) for w in wls]
+    M0 = [m.clone() for m in Ms]
+    params = [mm.LLGParams.make(Ms=w.mat.Ms, A=w.mat.A, alpha=w.mat.alpha, Hext=w.mat.Hext, dt=w.mat.dt)
+              for w in wls]
+    b.step(params, Ms, 2)
+    for i in (0, 17, 40, 63):
+        plan = mm.Plan(*wls[i].shape, *wls[i].cell)
+        m = M0[i].clone()
+        plan.step(params[i], m, 2)
+        assert np.array_equal(to_host(Ms[i]), to_host(m)), wls[i].shape
+        plan.close()
+    b.close()
+
+
+def test_batch_rejects_bad_input():
+    import torch
+    from paper_1406_7459_amd import mm
+    b = mm.Batch([(8, 8, 2)], [(1e-9, 1e-9, 1e-9)])
+    M = torch.zeros((3, 2, 8, 8), device="cuda")
+    with pytest.raises(mm.MMError):
+        b.demag([M], [M])
+    with pytest.raises(ValueError):
+        b.step([], [M], 1)
+    with pytest.raises(mm.MMError):
+        mm.Batch([(7, 8, 2)], [(1e-9, 1e-9, 1e-9)])
+    b.close()
