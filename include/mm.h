@@ -216,6 +216,64 @@ int mm_batch_group_tile(mm_batch batch, int index, int *pass, int *length, int *
 /* Release a batch, its plans and tables (NULL is ignored). */
 void mm_batch_destroy(mm_batch batch);
 
+/* ------------------------------------------------------------------------ *
+ * Learned demag increment for RK stages 2-4 (not in the paper; an added
+ * form).  Demag is linear, so a stage field is taken as
+ *   H(M_s) = H_d(M_n) + Ms sigma Net((M_s - M_n) / (Ms sigma)),
+ * with H_d(M_n) the exact stage-1 field and sigma the rms of the increment.
+ * Net: six 3x3x3 convolutions, channels 3-32-32-32-32-32-3, zero "same"
+ * padding, bias, GELU (tanh form) between layers; bfloat16 weights and
+ * activations on the matrix cores with FP32 accumulation; FP32 master
+ * weights trained with Adam (b1 0.9, b2 0.999, eps 1e-8) on the MSE loss.
+ * Parameter layout (host arrays of mm_sur_param_count() floats): for each
+ * layer, weights [co][ci][kz][ky][kx] then biases [co].
+ * ------------------------------------------------------------------------ */
+typedef struct mm_sur_s *mm_sur;
+
+typedef struct {
+    long long steps;      /* steps taken */
+    long long checked;    /* accepted states judged against exact demag */
+    long long fallbacks;  /* steps redone with exact demag */
+    double last_residual, max_residual, sum_residual;  /* |H_s - H_d| / |H_d| */
+} mm_sur_stats;
+
+/* Network and training buffers for an nx x ny x nz grid; weights zero. */
+int mm_sur_create(int nx, int ny, int nz, mm_sur *out);
+long long mm_sur_param_count(void);
+int mm_sur_set_params(mm_sur sur, const float *params, long long n);  /* host; resets Adam state */
+int mm_sur_get_params(mm_sur sur, float *params, long long n);
+int mm_sur_zero(mm_sur sur);  /* Net == 0: stages 2-4 reuse the stage-1 field */
+
+/* dh_dev = sigma Net(dm_dev / sigma), [3][nz][ny][nx] FP32 device arrays;
+ * sigma = rms(dm) if normalize, else 1.  Asynchronous.                      */
+int mm_sur_forward(mm_sur sur, const float *dm_dev, float *dh_dev, int normalize, void *stream);
+
+/* MSE loss of Net(dm/sigma) against dh/sigma and its gradient with respect
+ * to every parameter (host array, parameter layout; NULL to skip).
+ * Synchronises.                                                             */
+int mm_sur_gradients(mm_sur sur, const float *dm_dev, const float *dh_dev, int normalize, double *loss,
+                     float *grads, long long n, void *stream);
+
+/* One Adam step on that loss with learning rate lr.  Synchronises.          */
+int mm_sur_train_step(mm_sur sur, const float *dm_dev, const float *dh_dev, float lr, int normalize,
+                      double *loss, void *stream);
+
+/* nsteps RK4 steps of M_dev with the learned increment in stages 2-4 and
+ * exact demag at stage 1.  Every accepted state is judged against its exact
+ * field: if |H_s - H_d| / |H_d| > tol the step is redone with exact demag and
+ * the surrogate is skipped for the next step (tol < 0: never redo; tol = 0:
+ * always redo, i.e. the plain exact path).  Synchronises every step.       */
+int mm_llg_step_surrogate(mm_plan plan, mm_sur sur, const mm_llg_params *params, float *M_dev, int nsteps,
+                          double tol, mm_sur_stats *stats, void *stream);
+
+/* A training pair from the solver's own trajectory: advance M_dev by nsteps
+ * exact steps; dm_dev = (M_after - M_before)/Ms, dh_dev = H_d(dm_dev).
+ * Asynchronous.                                                             */
+int mm_sur_make_pair(mm_plan plan, const mm_llg_params *params, float *M_dev, int nsteps, float *dm_dev,
+                     float *dh_dev, void *stream);
+
+void mm_sur_destroy(mm_sur sur);
+
 /* Release a plan and its device memory (NULL is ignored). */
 void mm_destroy(mm_plan plan);
 

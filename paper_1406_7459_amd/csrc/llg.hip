@@ -54,13 +54,15 @@ StageCoef stage_coef(const Plan &p, const mm_llg_params &q)
 }
 
 template <int STAGE>
-static int launch_stage(Plan &p, const float *S, const float *Mn, float *out, const StageCoef &c, hipStream_t s)
+static int launch_stage(Plan &p, const float *S, const float *Mn, float *out, const StageCoef &c, hipStream_t s,
+                        const float *Hd = nullptr)
 {
+    if (!Hd) Hd = p.H;
     const size_t n = (size_t)p.cells();
     const int bs = 256;
     hipEvent_t ev0 = nullptr;
     timing_begin(p, MM_PASS_STAGE, s, &ev0);
-    hipLaunchKernelGGL(k_stage<STAGE>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, S, p.H, Mn, p.kacc,
+    hipLaunchKernelGGL(k_stage<STAGE>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, S, Hd, Mn, p.kacc,
                        out, p.nx, p.ny, p.nz, c);
     timing_end(p, MM_PASS_STAGE, s, ev0);
     hipError_t e = hipGetLastError();
@@ -88,6 +90,21 @@ int llg_enqueue_step(Plan &p, const StageCoef &c, int integrator, float *M, hipS
     if ((rc = demag_enqueue(p, p.Sb, p.H, s)) != MM_OK) return rc;
     if ((rc = launch_stage<3>(p, p.Sb, M, p.Sa, c, s)) != MM_OK) return rc;
     if ((rc = demag_enqueue(p, p.Sa, p.H, s)) != MM_OK) return rc;
+    return launch_stage<4>(p, p.Sa, M, M, c, s);
+}
+
+// RK4 step whose stage-1 field is given (H1, the field of M) and whose
+// stage 2-4 fields come from `field(stage, S, H)` (written into p.H).
+int llg_step_with_fields(Plan &p, const StageCoef &c, float *M, const float *H1, hipStream_t s,
+                         const std::function<int(int, const float *, float *)> &field)
+{
+    int rc;
+    if ((rc = launch_stage<1>(p, M, M, p.Sa, c, s, H1)) != MM_OK) return rc;
+    if ((rc = field(2, p.Sa, p.H)) != MM_OK) return rc;
+    if ((rc = launch_stage<2>(p, p.Sa, M, p.Sb, c, s)) != MM_OK) return rc;
+    if ((rc = field(3, p.Sb, p.H)) != MM_OK) return rc;
+    if ((rc = launch_stage<3>(p, p.Sb, M, p.Sa, c, s)) != MM_OK) return rc;
+    if ((rc = field(4, p.Sa, p.H)) != MM_OK) return rc;
     return launch_stage<4>(p, p.Sa, M, M, c, s);
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -116,6 +117,8 @@ int build_spectrum(Plan &p, hipStream_t s);
 // LLG (llg.hip).
 StageCoef stage_coef(const Plan &p, const mm_llg_params &q);
 int llg_enqueue_step(Plan &p, const StageCoef &c, int integrator, float *M, hipStream_t s);
+int llg_step_with_fields(Plan &p, const StageCoef &c, float *M, const float *H1, hipStream_t s,
+                         const std::function<int(int, const float *, float *)> &field);
 int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float *Hd, hipStream_t s);
 
 }  // namespace mmk

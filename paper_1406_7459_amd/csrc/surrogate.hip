@@ -1,0 +1,772 @@
+// surrogate.hip -- learned demag increment for the intermediate RK stages.
+//
+// A stack of six 3x3x3 convolutions (3 -> 32 -> 32 -> 32 -> 32 -> 32 -> 3
+// channels, zero "same" padding, a bias per output channel, GELU (tanh form)
+// after all but the last) maps a magnetisation increment dm to a demag-field
+// increment dh.  Demag is linear, so in RK stages 2-4 the field is taken as
+//   H(M_s) = H_d(M_n) + Ms * sigma * Net((M_s - M_n) / (Ms sigma)),
+// sigma = rms of the increment (the exact stage-1 field anchors it).
+//
+// Matrix-core path: activations are bfloat16, channel-last [cell][32]; a
+// convolution is an implicit GEMM (rows = output channels, columns = 16
+// cells, K = 32 input channels per tap, 27 taps) on v_mfma_f32_16x16x32_bf16
+// with FP32 accumulation.  Layers with 3 channels are zero-padded to 32.
+// The input gradient reuses the same kernel with the weights transposed and
+// the taps mirrored; the weight gradient is an FP32 reduction over cells.
+// Training keeps FP32 master weights and Adam moments; the bfloat16 copies
+// are refreshed after every update.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mm_internal.hpp"
+
+namespace mmk {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int SC = 32;       // padded channel count
+constexpr int NT = 27;       // taps
+constexpr int NLAYER = 6;
+constexpr int WSZ = SC * NT * SC;  // weights per padded layer
+static const int CH[NLAYER + 1] = {3, 32, 32, 32, 32, 32, 3};
+
+__device__ __forceinline__ float gelu_f(float x)
+{
+    const float c = 0.7978845608028654f;  // sqrt(2/pi)
+    return 0.5f * x * (1.f + tanhf(c * (x + 0.044715f * x * x * x)));
+}
+__device__ __forceinline__ float gelu_d(float x)
+{
+    const float c = 0.7978845608028654f;
+    const float u = c * (x + 0.044715f * x * x * x);
+    const float t = tanhf(u);
+    return 0.5f * (1.f + t) + 0.5f * x * (1.f - t * t) * c * (1.f + 3.f * 0.044715f * x * x);
+}
+
+// EPI 0: hidden layer, Z = acc + b (FP32) and Xn = bf16(gelu(Z));
+// EPI 1: last layer, dh[co][cell] = scale * (acc + b) for co < 3 (SoA FP32);
+// EPI 2: raw Z = acc (input gradient, no bias).
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ W,
+                                              const float *__restrict__ bias, float *__restrict__ Z,
+                                              __bf16 *__restrict__ Xn, float *__restrict__ dh, float scale, int nx,
+                                              int ny, int nz)
+{
+    __shared__ bf8 wl[SC * NT * (SC / 8)];
+    const bf8 *Wv = reinterpret_cast<const bf8 *>(W);
+    for (int i = threadIdx.x; i < SC * NT * (SC / 8); i += blockDim.x) wl[i] = Wv[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const long long N = (long long)nx * ny * nz;
+    const long long ntiles = (N + 15) / 16;
+    const bf8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long tile = (long long)blockIdx.x * 4 + wv; tile < ntiles; tile += (long long)gridDim.x * 4) {
+        const long long cell = tile * 16 + col;
+        const bool live = cell < N;
+        const int i = live ? (int)(cell % nx) : 0;
+        const int j = live ? (int)((cell / nx) % ny) : 0;
+        const int k = live ? (int)(cell / ((long long)nx * ny)) : 0;
+        f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 3
+        for (int t = 0; t < NT; ++t) {
+            const int ii = i + t % 3 - 1, jj = j + (t / 3) % 3 - 1, kk = k + t / 9 - 1;
+            const bool in = live && ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz;
+            const bf8 b = in ? *reinterpret_cast<const bf8 *>(X + (((long long)kk * ny + jj) * nx + ii) * SC + 8 * kq)
+                             : zero8;
+            const bf8 a0 = wl[(col * NT + t) * 4 + kq];
+            const bf8 a1 = wl[((16 + col) * NT + t) * 4 + kq];
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc1, 0, 0, 0);
+        }
+        if (!live) continue;
+        // lane holds D[co = 4 kq + r][cell] (acc0) and D[16 + 4 kq + r][cell] (acc1)
+        if constexpr (EPI == 0) {
+            f4 z0, z1;
+            bf4 g0, g1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                z0[r] = acc0[r] + bias[4 * kq + r];
+                z1[r] = acc1[r] + bias[16 + 4 * kq + r];
+                g0[r] = (__bf16)gelu_f(z0[r]);
+                g1[r] = (__bf16)gelu_f(z1[r]);
+            }
+            *reinterpret_cast<f4 *>(Z + cell * SC + 4 * kq) = z0;
+            *reinterpret_cast<f4 *>(Z + cell * SC + 16 + 4 * kq) = z1;
+            *reinterpret_cast<bf4 *>(Xn + cell * SC + 4 * kq) = g0;
+            *reinterpret_cast<bf4 *>(Xn + cell * SC + 16 + 4 * kq) = g1;
+        } else if constexpr (EPI == 1) {
+            if (kq == 0) {
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const float z = acc0[r] + bias[r];
+                    Z[cell * SC + r] = z;
+                    dh[r * N + cell] = scale * z;
+                }
+            }
+        } else {
+            *reinterpret_cast<f4 *>(Z + cell * SC + 4 * kq) = acc0;
+            *reinterpret_cast<f4 *>(Z + cell * SC + 16 + 4 * kq) = acc1;
+        }
+    }
+}
+
+// dm [3][N] FP32 (SoA) / scale -> bf16 channel-last [N][32], channels >= 3 zero
+__global__ __launch_bounds__(256) void k_to_cl(const float *__restrict__ dm, __bf16 *__restrict__ X, float inv, long long N)
+{
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        bf8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+        v[0] = (__bf16)(dm[c] * inv);
+        v[1] = (__bf16)(dm[N + c] * inv);
+        v[2] = (__bf16)(dm[2 * N + c] * inv);
+        bf8 *o = reinterpret_cast<bf8 *>(X + c * SC);
+        o[0] = v;
+        const bf8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+        o[1] = z;
+        o[2] = z;
+        o[3] = z;
+    }
+}
+
+// last-layer gradient: dZ = 2 (z - target/scale) / (3N) on co < 3; squared
+// error partials (FP64) per block
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const float *__restrict__ tgt, float inv,
+                                             float *__restrict__ dZ, __bf16 *__restrict__ dZb, double *__restrict__ part,
+                                             long long N)
+{
+    double s = 0.0;
+    const float w = 2.f / (3.f * (float)N);
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        float g[SC];
+#pragma unroll
+        for (int q = 0; q < SC; ++q) g[q] = 0.f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float d = Z[c * SC + r] - tgt[r * N + c] * inv;
+            s += (double)d * d;
+            g[r] = w * d;
+        }
+#pragma unroll
+        for (int q = 0; q < SC; ++q) {
+            dZ[c * SC + q] = g[q];
+            dZb[c * SC + q] = (__bf16)g[q];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// dZ_prev = dX * gelu'(Z_prev), FP32 and bf16 copies
+__global__ __launch_bounds__(256) void k_gelu_back(const float *__restrict__ dX, const float *__restrict__ Zp,
+                                                   float *__restrict__ dZ, __bf16 *__restrict__ dZb, long long n)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const float g = dX[e] * gelu_d(Zp[e]);
+        dZ[e] = g;
+        dZb[e] = (__bf16)g;
+    }
+}
+
+// Weight and bias gradient partials of one layer over a chunk of cells:
+// part[chunk][t][co][ci] = sum_cells dZ[cell][co] X[cell + off(t)][ci], and
+// bpart[chunk][co] = sum_cells dZ[cell][co].  Thread (co, ci group of 4).
+__global__ __launch_bounds__(256) void k_conv_dw(const float *__restrict__ dZ, const __bf16 *__restrict__ X,
+                                                 float *__restrict__ part, float *__restrict__ bpart, int nx, int ny,
+                                                 int nz, int chunk)
+{
+    const int co = threadIdx.x >> 3, cg = threadIdx.x & 7;
+    const long long N = (long long)nx * ny * nz;
+    const long long c0 = (long long)blockIdx.x * chunk;
+    const long long c1 = c0 + chunk < N ? c0 + chunk : N;
+    float acc[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
+    float bacc = 0.f;
+    for (long long c = c0; c < c1; ++c) {
+        const float d = dZ[c * SC + co];
+        bacc += d;
+        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((long long)nx * ny));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int ii = i + t % 3 - 1, jj = j + (t / 3) % 3 - 1, kk = k + t / 9 - 1;
+            if (ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz) {
+                const bf4 x = *reinterpret_cast<const bf4 *>(X + (((long long)kk * ny + jj) * nx + ii) * SC + 4 * cg);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[t][r] += d * (float)x[r];
+            }
+        }
+    }
+    float *o = part + (long long)blockIdx.x * WSZ;
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[(co * NT + t) * SC + 4 * cg + r] = acc[t][r];
+    if (cg == 0) bpart[(long long)blockIdx.x * SC + co] = bacc;
+}
+
+// fixed-order sum over chunks: g[e] = sum_b part[b][e]
+__global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ part, int nchunk, int n,
+                                                    float *__restrict__ g)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double s = 0.0;
+    for (int b = 0; b < nchunk; ++b) s += part[(long long)b * n + e];
+    g[e] = (float)s;
+}
+
+// Adam on FP32 masters, then refresh the bf16 forward weights [co][t][ci]
+// and the mirrored transpose [ci][26-t][co] used by the input gradient.
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                              const float *__restrict__ g, int n, float lr, float b1, float b2,
+                                              float c1, float c2, float eps)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.f - b1) * gg;
+    const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    w[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ __launch_bounds__(256) void k_refresh(const float *__restrict__ w, __bf16 *__restrict__ wb,
+                                                 __bf16 *__restrict__ wt)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= WSZ) return;
+    const int co = e / (NT * SC), t = (e / SC) % NT, ci = e % SC;
+    const __bf16 b = (__bf16)w[e];
+    wb[e] = b;
+    wt[(ci * NT + (NT - 1 - t)) * SC + co] = b;
+}
+
+// residual gate: sums of |a - b|^2 and |b|^2 over 3N (FP64 partials)
+__global__ __launch_bounds__(256) void k_resid(const float *__restrict__ a, const float *__restrict__ b,
+                                               double *__restrict__ part, long long n)
+{
+    double s0 = 0.0, s1 = 0.0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const double d = (double)a[e] - (double)b[e];
+        s0 += d * d;
+        s1 += (double)b[e] * (double)b[e];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_down(s0, o, 64);
+        s1 += __shfl_down(s1, o, 64);
+    }
+    __shared__ double sh[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = s0;
+        sh[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+        part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    }
+}
+
+// sum of squares of a field (FP64 partials), for the increment scale
+__global__ __launch_bounds__(256) void k_sumsq_diff(const float *__restrict__ a, const float *__restrict__ b,
+                                                    double *__restrict__ part, long long n)
+{
+    double s = 0.0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const double d = (double)a[e] - (b ? (double)b[e] : 0.0);
+        s += d * d;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    __shared__ double sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// d = (a - b) * s   (increment of the state, scaled)
+__global__ __launch_bounds__(256) void k_axpby(const float *__restrict__ a, const float *__restrict__ b, float s,
+                                               float *__restrict__ d, long long n)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        d[e] = (a[e] - b[e]) * s;
+}
+// h = h0 + s * dh
+__global__ __launch_bounds__(256) void k_anchor(const float *__restrict__ h0, const float *__restrict__ dh, float s,
+                                                float *__restrict__ h, long long n)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        h[e] = h0[e] + s * dh[e];
+}
+
+}  // namespace mmk
+
+namespace mmk {
+
+// sigma = sqrt(sum / count) (1 if the sum is 0 or normalisation is off);
+// out[0] = sigma, out[1] = 1 / sigma
+__global__ void k_sigma(const double *__restrict__ part, int nb, double count, int normalize, float *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    double sg = normalize ? sqrt(s / count) : 1.0;
+    if (!(sg > 0.0) || !isfinite(sg)) sg = 1.0;
+    out[0] = (float)sg;
+    out[1] = (float)(1.0 / sg);
+}
+
+// k_to_cl / last-layer scale read from device memory (the step driver never
+// synchronises for sigma)
+__global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm, __bf16 *__restrict__ X,
+                                                   const float *__restrict__ sig, long long N)
+{
+    const float inv = sig[1];
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
+        bf8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+        v[0] = (__bf16)(dm[c] * inv);
+        v[1] = (__bf16)(dm[N + c] * inv);
+        v[2] = (__bf16)(dm[2 * N + c] * inv);
+        bf8 *o = reinterpret_cast<bf8 *>(X + c * SC);
+        o[0] = v;
+        const bf8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+        o[1] = z;
+        o[2] = z;
+        o[3] = z;
+    }
+}
+// dh *= sigma (device scalar), in place on [3][N]
+__global__ __launch_bounds__(256) void k_scale_dev(float *__restrict__ dh, const float *__restrict__ sig, long long n)
+{
+    const float s = sig[0];
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        dh[e] *= s;
+}
+
+struct Sur {
+    int nx, ny, nz;
+    long long N;
+    // FP32 masters and Adam moments, padded layout [co][t][ci] per layer, then 32 biases
+    float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    __bf16 *wb = nullptr, *wt = nullptr;  // bf16 forward / mirrored-transposed copies
+    __bf16 *X[NLAYER] = {};               // layer inputs, [N][32]
+    float *Z[NLAYER] = {};                // pre-activations, [N][32]
+    float *dZ = nullptr, *dX = nullptr;   // [N][32]
+    __bf16 *dZb = nullptr;
+    float *part = nullptr, *bpart = nullptr;  // weight/bias gradient partials
+    int nchunk = 0, chunk = 0;
+    double *dpart = nullptr;              // FP64 reduction partials
+    float *sig = nullptr;                 // device sigma, 1/sigma
+    float *tmp = nullptr, *tmp2 = nullptr;  // [3][N] scratch
+    float *H0 = nullptr, *Mprev = nullptr, *Hs = nullptr;  // step driver: anchor field, saved state, prediction
+    int adam_t = 0;
+    std::vector<void *> owned;
+};
+
+static const int RED_B = 512;
+static long long layer_stride() { return (long long)WSZ + SC; }  // weights then biases
+
+static int sur_alloc(Sur &s, void **p, size_t bytes)
+{
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MM_ENOMEM, "surrogate buffers");
+    }
+    s.owned.push_back(*p);
+    return MM_OK;
+}
+
+static long long oracle_param_count()
+{
+    long long n = 0;
+    for (int l = 0; l < NLAYER; ++l) n += (long long)CH[l + 1] * CH[l] * NT + CH[l + 1];
+    return n;
+}
+
+static void refresh(Sur &s, hipStream_t st)
+{
+    for (int l = 0; l < NLAYER; ++l)
+        hipLaunchKernelGGL(k_refresh, dim3((WSZ + 255) / 256), dim3(256), 0, st, s.w + l * layer_stride(),
+                           s.wb + (long long)l * WSZ, s.wt + (long long)l * WSZ);
+}
+
+static unsigned grid_for(long long n) { return (unsigned)std::min<long long>((n + 255) / 256, 4096); }
+
+// forward of the whole stack on X[0] (already filled); last layer -> dh
+static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale)
+{
+    const unsigned gb = (unsigned)std::min<long long>(((s.N + 15) / 16 + 3) / 4, 4096);
+    for (int l = 0; l < NLAYER; ++l) {
+        const __bf16 *W = s.wb + (long long)l * WSZ;
+        const float *b = s.w + l * layer_stride() + WSZ;
+        if (l < NLAYER - 1)
+            hipLaunchKernelGGL(k_conv<0>, dim3(gb), dim3(256), 0, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, 1.f,
+                               s.nx, s.ny, s.nz);
+        else
+            hipLaunchKernelGGL(k_conv<1>, dim3(gb), dim3(256), 0, st, s.X[l], W, b, s.Z[l], nullptr, dh, 1.f, s.nx,
+                               s.ny, s.nz);
+    }
+    if (dev_scale) hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(3 * s.N)), dim3(256), 0, st, dh, s.sig, 3 * s.N);
+}
+
+// sigma of dm (normalize) into s.sig, and X[0] = bf16(dm / sigma)
+static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, dm, nullptr, s.dpart, 3 * s.N);
+    hipLaunchKernelGGL(k_sigma, dim3(1), dim3(64), 0, st, s.dpart, RED_B, (double)(3 * s.N), normalize, s.sig);
+    hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.sig, s.N);
+}
+
+// loss and gradients into s.g (masters' layout); returns the loss on the host
+static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_t st)
+{
+    // target is divided by sigma inside k_mse: pass 1/sigma via a host read
+    float sg[2];
+    MMK_HIP(hipMemcpyAsync(sg, s.sig, sizeof(sg), hipMemcpyDeviceToHost, st));
+    MMK_HIP(hipStreamSynchronize(st));
+    hipLaunchKernelGGL(k_mse, dim3(RED_B), dim3(256), 0, st, s.Z[NLAYER - 1], dh_target, sg[1], s.dZ, s.dZb, s.dpart,
+                       s.N);
+    std::vector<double> hp(RED_B);
+    MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * RED_B, hipMemcpyDeviceToHost, st));
+    const unsigned gb = (unsigned)std::min<long long>(((s.N + 15) / 16 + 3) / 4, 4096);
+    for (int l = NLAYER - 1; l >= 0; --l) {
+        hipLaunchKernelGGL(k_conv_dw, dim3(s.nchunk), dim3(256), 0, st, s.dZ, s.X[l], s.part, s.bpart, s.nx, s.ny, s.nz,
+                           s.chunk);
+        float *gl = s.g + l * layer_stride();
+        hipLaunchKernelGGL(k_sum_chunks, dim3((WSZ + 255) / 256), dim3(256), 0, st, s.part, s.nchunk, WSZ, gl);
+        hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, st, s.bpart, s.nchunk, SC, gl + WSZ);
+        if (l > 0) {
+            hipLaunchKernelGGL(k_conv<2>, dim3(gb), dim3(256), 0, st, s.dZb, s.wt + (long long)l * WSZ, nullptr, s.dX,
+                               nullptr, nullptr, 1.f, s.nx, s.ny, s.nz);
+            hipLaunchKernelGGL(k_gelu_back, dim3(grid_for(s.N * SC)), dim3(256), 0, st, s.dX, s.Z[l - 1], s.dZ, s.dZb,
+                               s.N * SC);
+        }
+    }
+    MMK_HIP(hipStreamSynchronize(st));
+    double tot = 0.0;
+    for (double x : hp) tot += x;
+    *loss = tot / (3.0 * (double)s.N);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MM_EHIP, std::string("surrogate backward: ") + hipGetErrorString(e));
+    return MM_OK;
+}
+
+// host layout conversion: oracle [co][ci][kz][ky][kx] + b[co] per layer <-> padded masters
+static void to_masters(const float *src, std::vector<float> &dst)
+{
+    dst.assign((size_t)NLAYER * layer_stride(), 0.f);
+    long long o = 0;
+    for (int l = 0; l < NLAYER; ++l) {
+        float *W = dst.data() + l * layer_stride();
+        for (int co = 0; co < CH[l + 1]; ++co)
+            for (int ci = 0; ci < CH[l]; ++ci)
+                for (int t = 0; t < NT; ++t) W[(co * NT + t) * SC + ci] = src[o++];
+        for (int co = 0; co < CH[l + 1]; ++co) W[WSZ + co] = src[o++];
+    }
+}
+static void from_masters(const float *src, float *dst)
+{
+    long long o = 0;
+    for (int l = 0; l < NLAYER; ++l) {
+        const float *W = src + l * layer_stride();
+        for (int co = 0; co < CH[l + 1]; ++co)
+            for (int ci = 0; ci < CH[l]; ++ci)
+                for (int t = 0; t < NT; ++t) dst[o++] = W[(co * NT + t) * SC + ci];
+        for (int co = 0; co < CH[l + 1]; ++co) dst[o++] = W[WSZ + co];
+    }
+}
+
+static void free_sur(Sur *s)
+{
+    if (!s) return;
+    for (void *p : s->owned) (void)hipFree(p);
+    delete s;
+}
+
+// residual of the surrogate against an exact field: |a-b|^2 / |b|^2
+static int resid(Sur &s, const float *a, const float *b, double *r, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resid, dim3(RED_B), dim3(256), 0, st, a, b, s.dpart, 3 * s.N);
+    std::vector<double> hp(2 * RED_B);
+    MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * 2 * RED_B, hipMemcpyDeviceToHost, st));
+    MMK_HIP(hipStreamSynchronize(st));
+    double n0 = 0, n1 = 0;
+    for (int i = 0; i < RED_B; ++i) {
+        n0 += hp[2 * i];
+        n1 += hp[2 * i + 1];
+    }
+    *r = n1 > 0 ? std::sqrt(n0 / n1) : 0.0;
+    return MM_OK;
+}
+
+// H = H0 + Ms * sigma * Net((Mstage - Mn) / (Ms sigma)) on stream st (no sync)
+static void sur_field(Sur &s, const float *Mstage, const float *Mn, const float *H0, float Ms, float *H, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(3 * s.N)), dim3(256), 0, st, Mstage, Mn, 1.f / Ms, s.tmp, 3 * s.N);
+    sur_input(s, s.tmp, 1, st);
+    sur_forward(s, s.tmp2, st, true);
+    hipLaunchKernelGGL(k_anchor, dim3(grid_for(3 * s.N)), dim3(256), 0, st, H0, s.tmp2, Ms, H, 3 * s.N);
+}
+
+}  // namespace mmk
+
+using namespace mmk;
+
+struct mm_sur_s {
+    Sur *s;
+};
+
+extern "C" {
+
+int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
+{
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > (1LL << 28)) return fail(MM_EINVAL, "surrogate grid");
+    Sur *s = new Sur();
+    s->nx = nx;
+    s->ny = ny;
+    s->nz = nz;
+    s->N = (long long)nx * ny * nz;
+    s->chunk = 256;
+    s->nchunk = (int)((s->N + s->chunk - 1) / s->chunk);
+    const size_t P = (size_t)NLAYER * layer_stride();
+    int rc = MM_OK;
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->w, P * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->m, P * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->v, P * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->g, P * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->wb, (size_t)NLAYER * WSZ * 2);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->wt, (size_t)NLAYER * WSZ * 2);
+    for (int l = 0; l < NLAYER && rc == MM_OK; ++l) {
+        rc = sur_alloc(*s, (void **)&s->X[l], (size_t)s->N * SC * 2);
+        if (rc == MM_OK) rc = sur_alloc(*s, (void **)&s->Z[l], (size_t)s->N * SC * 4);
+    }
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZ, (size_t)s->N * SC * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dX, (size_t)s->N * SC * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb, (size_t)s->N * SC * 2);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->part, (size_t)s->nchunk * WSZ * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->bpart, (size_t)s->nchunk * SC * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dpart, (size_t)2 * RED_B * 8);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->sig, 16);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->tmp, (size_t)3 * s->N * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->tmp2, (size_t)3 * s->N * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->H0, (size_t)3 * s->N * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->Mprev, (size_t)3 * s->N * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->Hs, (size_t)3 * s->N * 4);
+    if (rc == MM_OK) {
+        hipError_t e = hipMemset(s->w, 0, P * 4);
+        if (e == hipSuccess) e = hipMemset(s->m, 0, P * 4);
+        if (e == hipSuccess) e = hipMemset(s->v, 0, P * 4);
+        if (e == hipSuccess) e = hipMemset(s->g, 0, P * 4);
+        if (e != hipSuccess) rc = fail(MM_EHIP, "surrogate init");
+        refresh(*s, nullptr);
+        if (hipDeviceSynchronize() != hipSuccess) rc = fail(MM_EHIP, "surrogate init sync");
+    }
+    if (rc != MM_OK) {
+        free_sur(s);
+        return rc;
+    }
+    *out = new mm_sur_s{s};
+    return MM_OK;
+}
+
+// A training pair from the solver's own trajectory: advance M by nsteps
+// exact RK4 steps; dm = (M_after - M_before) / Ms, dh = H_d(dm) (demag is
+// linear, so dh is the field increment per Ms).
+int mm_sur_make_pair(mm_plan plan, const mm_llg_params *params, float *M, int nsteps, float *dm, float *dh,
+                     void *stream)
+{
+    Plan *pp = plan_of(plan);
+    if (!pp || !params || !M || !dm || !dh || dm == dh) return fail(MM_EINVAL, "NULL or aliased argument");
+    if (nsteps < 1) return fail(MM_EINVAL, "nsteps < 1");
+    Plan &p = *pp;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t n3 = 3 * (size_t)p.cells();
+    MMK_HIP(hipMemcpyAsync(dm, M, n3 * sizeof(float), hipMemcpyDeviceToDevice, st));
+    const StageCoef c = stage_coef(p, *params);
+    for (int i = 0; i < nsteps; ++i) {
+        int rc = llg_enqueue_step(p, c, params->integrator, M, st);
+        if (rc != MM_OK) return rc;
+    }
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for((long long)n3)), dim3(256), 0, st, M, dm, (float)(1.0 / params->Ms),
+                       dm, (long long)n3);
+    return demag_enqueue(p, dm, dh, st);
+}
+
+void mm_sur_destroy(mm_sur sur)
+{
+    if (!sur) return;
+    free_sur(sur->s);
+    delete sur;
+}
+
+long long mm_sur_param_count(void) { return oracle_param_count(); }
+
+int mm_sur_set_params(mm_sur sur, const float *host, long long n)
+{
+    if (!sur || !host || n != oracle_param_count()) return fail(MM_EINVAL, "surrogate params: bad pointer or count");
+    Sur &s = *sur->s;
+    std::vector<float> w;
+    to_masters(host, w);
+    MMK_HIP(hipMemcpy(s.w, w.data(), w.size() * 4, hipMemcpyHostToDevice));
+    MMK_HIP(hipMemset(s.m, 0, w.size() * 4));
+    MMK_HIP(hipMemset(s.v, 0, w.size() * 4));
+    s.adam_t = 0;
+    refresh(s, nullptr);
+    MMK_HIP(hipDeviceSynchronize());
+    return MM_OK;
+}
+
+int mm_sur_get_params(mm_sur sur, float *host, long long n)
+{
+    if (!sur || !host || n != oracle_param_count()) return fail(MM_EINVAL, "surrogate params: bad pointer or count");
+    Sur &s = *sur->s;
+    std::vector<float> w((size_t)NLAYER * layer_stride());
+    MMK_HIP(hipDeviceSynchronize());
+    MMK_HIP(hipMemcpy(w.data(), s.w, w.size() * 4, hipMemcpyDeviceToHost));
+    from_masters(w.data(), host);
+    return MM_OK;
+}
+
+int mm_sur_forward(mm_sur sur, const float *dm, float *dh, int normalize, void *stream)
+{
+    if (!sur || !dm || !dh) return fail(MM_EINVAL, "NULL surrogate or field");
+    Sur &s = *sur->s;
+    hipStream_t st = (hipStream_t)stream;
+    sur_input(s, dm, normalize, st);
+    sur_forward(s, dh, st, true);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MM_OK : fail(MM_EHIP, std::string("surrogate forward: ") + hipGetErrorString(e));
+}
+
+int mm_sur_gradients(mm_sur sur, const float *dm, const float *dh, int normalize, double *loss, float *grads,
+                     long long n, void *stream)
+{
+    if (!sur || !dm || !dh || !loss) return fail(MM_EINVAL, "NULL surrogate argument");
+    if (grads && n != oracle_param_count()) return fail(MM_EINVAL, "gradient count");
+    Sur &s = *sur->s;
+    hipStream_t st = (hipStream_t)stream;
+    sur_input(s, dm, normalize, st);
+    sur_forward(s, s.tmp2, st, false);
+    int rc = sur_backward(s, dh, loss, st);
+    if (rc != MM_OK || !grads) return rc;
+    std::vector<float> g((size_t)NLAYER * layer_stride());
+    MMK_HIP(hipMemcpy(g.data(), s.g, g.size() * 4, hipMemcpyDeviceToHost));
+    from_masters(g.data(), grads);
+    return MM_OK;
+}
+
+int mm_sur_train_step(mm_sur sur, const float *dm, const float *dh, float lr, int normalize, double *loss,
+                      void *stream)
+{
+    if (!sur || !dm || !dh || !loss) return fail(MM_EINVAL, "NULL surrogate argument");
+    if (!(lr > 0.f)) return fail(MM_EINVAL, "learning rate must be > 0");
+    Sur &s = *sur->s;
+    hipStream_t st = (hipStream_t)stream;
+    sur_input(s, dm, normalize, st);
+    sur_forward(s, s.tmp2, st, false);
+    int rc = sur_backward(s, dh, loss, st);
+    if (rc != MM_OK) return rc;
+    s.adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow(0.9, s.adam_t)), c2 = (float)(1.0 - std::pow(0.999, s.adam_t));
+    const int P = (int)(NLAYER * layer_stride());
+    hipLaunchKernelGGL(k_adam, dim3((P + 255) / 256), dim3(256), 0, st, s.w, s.m, s.v, s.g, P, lr, b1, b2, c1, c2,
+                       1e-8f);
+    refresh(s, st);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MM_OK : fail(MM_EHIP, std::string("surrogate train: ") + hipGetErrorString(e));
+}
+
+int mm_sur_zero(mm_sur sur)
+{
+    if (!sur) return fail(MM_EINVAL, "NULL surrogate");
+    Sur &s = *sur->s;
+    const size_t P = (size_t)NLAYER * layer_stride();
+    MMK_HIP(hipMemset(s.w, 0, P * 4));
+    refresh(s, nullptr);
+    MMK_HIP(hipDeviceSynchronize());
+    return MM_OK;
+}
+
+// Steps with the learned increment in RK stages 2-4, exact demag at stage 1,
+// and the accepted state judged against the exact field of that state (the
+// next step's stage-1 field): relative residual above `tol` redoes the step
+// with exact demag everywhere and keeps the surrogate off for one step.
+int mm_llg_step_surrogate(mm_plan plan, mm_sur sur, const mm_llg_params *params, float *M, int nsteps, double tol,
+                          mm_sur_stats *stats, void *stream)
+{
+    Plan *pp = plan_of(plan);
+    if (!pp || !sur || !params || !M) return fail(MM_EINVAL, "NULL plan, surrogate, params or M");
+    if (params->integrator != MM_RK4) return fail(MM_EINVAL, "surrogate stepping needs RK4");
+    if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
+    Plan &p = *pp;
+    Sur &s = *sur->s;
+    if (s.N != p.cells()) return fail(MM_EINVAL, "surrogate and plan grids differ");
+    hipStream_t st = (hipStream_t)stream;
+    const StageCoef c = stage_coef(p, *params);
+    const size_t bytes = sizeof(float) * 3 * (size_t)p.cells();
+    float *H0 = s.H0, *Mprev = s.Mprev, *Hs = s.Hs;
+    mm_sur_stats acc{};
+    bool use = true;
+    int rc = MM_OK;
+    // exact field of the current state
+    rc = demag_enqueue(p, M, H0, st);
+    for (int n = 0; n < nsteps && rc == MM_OK; ++n) {
+        (void)hipMemcpyAsync(Mprev, M, bytes, hipMemcpyDeviceToDevice, st);
+        if (use) {
+            rc = llg_step_with_fields(p, c, M, H0, st, [&](int stage, const float *Sstate, float *Hout) {
+                (void)stage;
+                sur_field(s, Sstate, Mprev, H0, c.Ms, Hout, st);
+                return MM_OK;
+            });
+            // judge the accepted state
+            if (rc == MM_OK) rc = demag_enqueue(p, M, p.H, st);  // exact H of M_{n+1}
+            if (rc == MM_OK) sur_field(s, M, Mprev, H0, c.Ms, Hs, st);
+            double r = 0.0;
+            if (rc == MM_OK) rc = resid(s, Hs, p.H, &r, st);
+            if (rc != MM_OK) break;
+            acc.last_residual = r;
+            acc.max_residual = r > acc.max_residual ? r : acc.max_residual;
+            acc.sum_residual += r;
+            acc.checked += 1;
+            if (tol >= 0.0 && !(r <= tol)) {
+                // redo with exact demag from the saved state
+                acc.fallbacks += 1;
+                (void)hipMemcpyAsync(M, Mprev, bytes, hipMemcpyDeviceToDevice, st);
+                rc = llg_enqueue_step(p, c, MM_RK4, M, st);
+                if (rc == MM_OK) rc = demag_enqueue(p, M, H0, st);
+                use = false;
+            } else {
+                (void)hipMemcpyAsync(H0, p.H, bytes, hipMemcpyDeviceToDevice, st);
+            }
+        } else {
+            rc = llg_enqueue_step(p, c, MM_RK4, M, st);
+            if (rc == MM_OK) rc = demag_enqueue(p, M, H0, st);
+            use = true;
+        }
+        acc.steps += 1;
+    }
+    if (stats) *stats = acc;
+    if (rc == MM_OK) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(MM_EHIP, std::string("surrogate step: ") + hipGetErrorString(e));
+    }
+    return rc;
+}
+
+}  // extern "C"

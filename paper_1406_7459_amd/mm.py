@@ -26,7 +26,10 @@ SYMBOLS = ("mm_demag_setup", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_n
            "mm_plan_spectrum", "mm_plan_query", "mm_plan_set_tile", "mm_plan_autotune",
            "mm_plan_set_timing", "mm_plan_timing", "mm_destroy", "mm_status_string",
            "mm_last_error", "mm_batch_setup", "mm_batch_demag", "mm_batch_step",
-           "mm_batch_autotune", "mm_batch_query", "mm_batch_group_tile", "mm_batch_destroy")
+           "mm_batch_autotune", "mm_batch_query", "mm_batch_group_tile", "mm_batch_destroy",
+           "mm_sur_create", "mm_sur_param_count", "mm_sur_set_params", "mm_sur_get_params",
+           "mm_sur_zero", "mm_sur_forward", "mm_sur_gradients", "mm_sur_train_step",
+           "mm_llg_step_surrogate", "mm_sur_make_pair", "mm_sur_destroy")
 
 
 class MMError(RuntimeError):
@@ -67,6 +70,17 @@ class Stats(C.Structure):
     def as_dict(self):
         return dict(E_ex=self.E_ex, E_an=self.E_an, E_d=self.E_d, E_z=self.E_z, E_tot=self.E_tot,
                     torque_max=self.torque_max, m_avg=tuple(self.m_avg), nonfinite=self.nonfinite)
+
+
+class SurStats(C.Structure):
+    _fields_ = [("steps", C.c_longlong), ("checked", C.c_longlong), ("fallbacks", C.c_longlong),
+                ("last_residual", C.c_double), ("max_residual", C.c_double),
+                ("sum_residual", C.c_double)]
+
+    def as_dict(self):
+        return dict(steps=self.steps, checked=self.checked, fallbacks=self.fallbacks,
+                    last_residual=self.last_residual, max_residual=self.max_residual,
+                    mean_residual=self.sum_residual / max(1, self.checked))
 
 
 class PlanInfo(C.Structure):
@@ -110,12 +124,26 @@ def lib():
     L.mm_batch_group_tile.argtypes = [vp, i, ip, ip, ip]
     L.mm_batch_destroy.argtypes = [vp]
     L.mm_batch_destroy.restype = None
+    L.mm_sur_create.argtypes = [i, i, i, C.POINTER(vp)]
+    L.mm_sur_param_count.argtypes = []
+    L.mm_sur_set_params.argtypes = [vp, C.POINTER(C.c_float), ll]
+    L.mm_sur_get_params.argtypes = [vp, C.POINTER(C.c_float), ll]
+    L.mm_sur_zero.argtypes = [vp]
+    L.mm_sur_forward.argtypes = [vp, vp, vp, i, vp]
+    L.mm_sur_gradients.argtypes = [vp, vp, vp, i, C.POINTER(C.c_double), C.POINTER(C.c_float), ll, vp]
+    L.mm_sur_train_step.argtypes = [vp, vp, vp, C.c_float, i, C.POINTER(C.c_double), vp]
+    L.mm_llg_step_surrogate.argtypes = [vp, vp, C.POINTER(LLGParams), vp, i, C.c_double,
+                                        C.POINTER(SurStats), vp]
+    L.mm_sur_make_pair.argtypes = [vp, C.POINTER(LLGParams), vp, i, vp, vp, vp]
+    L.mm_sur_destroy.argtypes = [vp]
+    L.mm_sur_destroy.restype = None
     L.mm_status_string.argtypes = [i]
     L.mm_status_string.restype = C.c_char_p
     L.mm_last_error.argtypes = [C.c_char_p, C.c_size_t]
     for name in SYMBOLS:
-        if name not in ("mm_destroy", "mm_status_string", "mm_batch_destroy"):
+        if name not in ("mm_destroy", "mm_status_string", "mm_batch_destroy", "mm_sur_destroy"):
             getattr(L, name).restype = C.c_int
+    L.mm_sur_param_count.restype = ll
     _lib = L
     return L
 
@@ -293,3 +321,92 @@ class Batch:
                    "mm_batch_group_tile")
             out.append((PASSES[p.value], L_.value, t.value))
         return out
+
+
+class Surrogate:
+    """mm_sur_*: learned demag increment (six 3x3x3 convolutions, BF16 on the
+    matrix cores), its training and the gated RK4 stepping."""
+
+    def __init__(self, nx, ny, nz):
+        h = C.c_void_p()
+        _check(lib().mm_sur_create(int(nx), int(ny), int(nz), C.byref(h)), "mm_sur_create")
+        self._h = h
+        self.shape = (int(nx), int(ny), int(nz))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mm_sur_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().mm_sur_param_count())
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().mm_sur_set_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+               "mm_sur_set_params")
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(self.param_count(), dtype=np.float32)
+        _check(lib().mm_sur_get_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float)), a.size),
+               "mm_sur_get_params")
+        return a
+
+    def zero(self):
+        _check(lib().mm_sur_zero(self._h), "mm_sur_zero")
+
+    @property
+    def field_shape(self):
+        nx, ny, nz = self.shape
+        return (3, nz, ny, nx)
+
+    def forward(self, dm, dh=None, normalize=False, stream=None):
+        if dh is None:
+            dh = torch.empty_like(dm)
+        _check(lib().mm_sur_forward(self._h, _field(dm, self.field_shape, "dm"),
+                                    _field(dh, self.field_shape, "dh"), 1 if normalize else 0,
+                                    _stream(stream)), "mm_sur_forward")
+        return dh
+
+    def gradients(self, dm, dh, normalize=False, stream=None):
+        import numpy as np
+        g = np.zeros(self.param_count(), dtype=np.float32)
+        loss = C.c_double()
+        _check(lib().mm_sur_gradients(self._h, _field(dm, self.field_shape, "dm"),
+                                      _field(dh, self.field_shape, "dh"), 1 if normalize else 0,
+                                      C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float)), g.size,
+                                      _stream(stream)), "mm_sur_gradients")
+        return loss.value, g
+
+    def train_step(self, dm, dh, lr, normalize=True, stream=None) -> float:
+        loss = C.c_double()
+        _check(lib().mm_sur_train_step(self._h, _field(dm, self.field_shape, "dm"),
+                                       _field(dh, self.field_shape, "dh"), float(lr),
+                                       1 if normalize else 0, C.byref(loss), _stream(stream)),
+               "mm_sur_train_step")
+        return loss.value
+
+    @staticmethod
+    def make_pair(plan: Plan, params: LLGParams, M, nsteps, dm=None, dh=None, stream=None):
+        """Advance M by nsteps exact steps; return (dm, dh) = (dM/Ms, H_d(dm))."""
+        if dm is None:
+            dm = torch.empty_like(M)
+        if dh is None:
+            dh = torch.empty_like(M)
+        _check(lib().mm_sur_make_pair(plan._h, C.byref(params), _field(M, plan.field_shape, "M"),
+                                      int(nsteps), _field(dm, plan.field_shape, "dm"),
+                                      _field(dh, plan.field_shape, "dh"), _stream(stream)),
+               "mm_sur_make_pair")
+        return dm, dh
+
+    def step(self, plan: Plan, params: LLGParams, M, nsteps, tol=1e-3, stream=None) -> dict:
+        st = SurStats()
+        _check(lib().mm_llg_step_surrogate(plan._h, self._h, C.byref(params),
+                                           _field(M, plan.field_shape, "M"), int(nsteps), float(tol),
+                                           C.byref(st), _stream(stream)), "mm_llg_step_surrogate")
+        return st.as_dict()

@@ -1,0 +1,127 @@
+"""Learned demag increment: the bfloat16 matrix-core convolution stack, its
+gradients and training against the FP64 reference (oracle/surrogate.py), the
+residual gate, and what the trained network gains over no network."""
+import numpy as np
+import pytest
+import torch
+
+from gpucommon import rel_l2, say, to_dev, to_host
+from oracle import surrogate as S
+from paper_1406_7459_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def flat(params):
+    out = []
+    for w, b in params:
+        out.append(w.numpy().ravel())
+        out.append(b.numpy())
+    return np.concatenate(out).astype(np.float32)
+
+
+def unflat(vec):
+    out, o = [], 0
+    for cin, cout in zip(S.CHANNELS[:-1], S.CHANNELS[1:]):
+        n = cout * cin * 27
+        w = torch.from_numpy(vec[o:o + n].astype(np.float64).reshape(cout, cin, 3, 3, 3))
+        o += n
+        b = torch.from_numpy(vec[o:o + cout].astype(np.float64))
+        o += cout
+        out.append((w, b))
+    return out
+
+
+def ref_params(seed):
+    """Oracle initialisation with weights rounded to bfloat16 and biases made
+    nonzero and rounded to float32 (the GPU's operand precisions)."""
+    ps = S.init_params(seed)
+    g = np.random.default_rng(seed)
+    out = []
+    for w, b in ps:
+        bb = torch.from_numpy(g.uniform(-0.05, 0.05, b.shape)).float().double()
+        out.append((S.bf16(w), bb))
+    return out
+
+
+@pytest.mark.parametrize("grid", [(16, 12, 4), (10, 6, 3), (33, 5, 2)])
+def test_forward_matches_reference(grid):
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = grid
+    sur = mm.Surrogate(nx, ny, nz)
+    ps = ref_params(1)
+    sur.set_params(flat(ps))
+    assert np.array_equal(sur.get_params(), flat(ps))
+    dm = S.bf16(torch.from_numpy(W.random_unit(nx, ny, nz, 3)))
+    out = to_host(sur.forward(to_dev(dm.numpy())))
+    ref, _ = S.forward(ps, dm, bf16_between=True)
+    err = rel_l2(out, ref.numpy())
+    say("forward", grid, "rel L2", err)
+    assert err < 1e-2
+    sur.close()
+
+
+def test_gradients_match_reference():
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 12, 8, 3
+    sur = mm.Surrogate(nx, ny, nz)
+    ps = ref_params(2)
+    sur.set_params(flat(ps))
+    dm = S.bf16(torch.from_numpy(W.random_unit(nx, ny, nz, 4)))
+    dh = torch.from_numpy(0.3 * W.random_unit(nx, ny, nz, 5)).float().double()
+    loss_g, g = sur.gradients(to_dev(dm.numpy()), to_dev(dh.numpy()))
+    # reference: the same bf16 operands, FP64 arithmetic, straight-through rounding
+    pr = [(w.clone().requires_grad_(True), b.clone().requires_grad_(True)) for w, b in ps]
+    out, _ = S.forward(pr, dm, bf16_between=True)
+    loss = S.mse(out, dh)
+    loss.backward()
+    gref = flat([(w.grad, b.grad) for w, b in pr])
+    assert loss_g == pytest.approx(loss.item(), rel=2e-2)
+    o = 0
+    for li, (w, b) in enumerate(ps):
+        n = w.numel() + b.numel()
+        e = rel_l2(g[o:o + n], gref[o:o + n])
+        say("layer", li, "grad rel L2", e)
+        assert e < 5e-2
+        o += n
+
+
+def test_training_reduces_loss_on_solver_pairs():
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 32, 32, 2
+    d = (4e-9, 4e-9, 4e-9)
+    plan = mm.Plan(nx, ny, nz, *d)
+    sur = mm.Surrogate(nx, ny, nz)
+    sur.set_params(flat(S.init_params(7)))
+    p = mm.LLGParams.make(Ms=8e5, A=1.3e-11, alpha=0.1, dt=1e-14)
+    M = to_dev(8e5 * W.random_unit(nx, ny, nz, 8))
+    plan.step(p, M, 20)
+    pairs = [mm.Surrogate.make_pair(plan, p, M, 1) for _ in range(8)]
+    first = [sur.train_step(dm, dh, 2e-3) for dm, dh in pairs]
+    for _ in range(40):
+        for dm, dh in pairs:
+            sur.train_step(dm, dh, 2e-3)
+    last = [sur.gradients(dm, dh, normalize=True)[0] for dm, dh in pairs]
+    say("loss first", np.mean(first), "last", np.mean(last))
+    assert np.mean(last) < 0.3 * np.mean(first)
+
+
+def test_gate_at_zero_tolerance_is_the_exact_path():
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 32, 16, 4
+    d = (4e-9, 4e-9, 4e-9)
+    plan = mm.Plan(nx, ny, nz, *d)
+    sur = mm.Surrogate(nx, ny, nz)
+    sur.set_params(flat(S.init_params(9)))
+    p = mm.LLGParams.make(Ms=8e5, A=1.3e-11, alpha=0.1, dt=1e-14, Hext=(1e4, 0, 0))
+    M0 = to_dev(8e5 * W.random_unit(nx, ny, nz, 10))
+    a = M0.clone()
+    st = sur.step(plan, p, a, 6, tol=0.0)
+    b = M0.clone()
+    plan.step(p, b, 6)
+    assert np.array_equal(to_host(a), to_host(b))
+    assert st["steps"] == 6 and st["fallbacks"] == st["checked"]
+    c = M0.clone()
+    st2 = sur.step(plan, p, c, 6, tol=-1.0)
+    assert st2["fallbacks"] == 0 and st2["checked"] == 6 and np.isfinite(st2["max_residual"])
+    assert np.isfinite(to_host(c)).all()
