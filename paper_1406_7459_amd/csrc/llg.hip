@@ -213,17 +213,19 @@ __global__ __launch_bounds__(256) void k_reduce_cells(const float *__restrict__ 
     }
 }
 
-__global__ __launch_bounds__(64) void k_reduce_final(const double *__restrict__ part, int nblocks,
-                                                     double *__restrict__ out)
+// One wave per quantity: lane l sums partials l, l+64, ... in order, then a
+// fixed shuffle tree -- the same order on every run.
+__global__ __launch_bounds__(64 * RED_VALS) void k_reduce_final(const double *__restrict__ part, int nblocks,
+                                                                double *__restrict__ out)
 {
-    const int v = threadIdx.x;
-    if (v >= RED_VALS) return;
-    double r = part[v];
-    for (int b = 1; b < nblocks; ++b) {
+    const int v = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double r = v == 8 ? 0.0 : 0.0;
+    for (int b = lane; b < nblocks; b += 64) {
         const double x = part[(size_t)b * RED_VALS + v];
         r = v == 8 ? ((x > r || x != x) ? x : r) : r + x;
     }
-    out[v] = r;
+    r = v == 8 ? wave_max(r) : wave_sum(r);
+    if (lane == 0) out[v] = r;
 }
 
 int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float *Hd, hipStream_t s)
@@ -250,7 +252,7 @@ int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float 
     hipEvent_t ev0 = nullptr;
     timing_begin(p, MM_PASS_REDUCE, s, &ev0);
     hipLaunchKernelGGL(k_reduce_cells, dim3(p.red_blocks), dim3(256), 0, s, M, Hd, p.part, p.nx, p.ny, p.nz, c);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, p.part, p.red_blocks, p.red);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64 * RED_VALS), 0, s, p.part, p.red_blocks, p.red);
     timing_end(p, MM_PASS_REDUCE, s, ev0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MM_EHIP, std::string("reduce: ") + hipGetErrorString(e));
