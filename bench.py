@@ -157,6 +157,28 @@ def batch_measure(torch, mm, W, steps=10, warmup=2):
             "bitwise_equal_to_looped": same}
 
 
+def table1_euler(torch, mm, W):
+    """Per-step time with explicit Euler on N^3 cubes, N = 8 ... 128 (the shape
+    of the paper's Table 1; material of the cube workload)."""
+    out = []
+    for n in (8, 16, 32, 64, 128):
+        wl = W.cube(n)
+        m = wl.mat
+        plan = mm.Plan(n, n, n, *wl.cell)
+        p = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha, gamma0=m.gamma0,
+                              dt=m.dt, integrator="euler")
+        M = torch.from_numpy((m.Ms * wl.initial_unit()).astype("float32")).cuda()
+        plan.step(p, M, 5)
+        torch.cuda.synchronize()
+        k = 200 if n <= 64 else 50
+        t0 = time.perf_counter()
+        plan.step(p, M, k)
+        torch.cuda.synchronize()
+        out.append({"N": n, "euler_ms_per_step": (time.perf_counter() - t0) / k * 1e3})
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +323,10 @@ def main():
                           "note": "paper Table 1, Euler, AMD HD 7970, other hardware: context only"},
     }
     out["step_roofline"]["frac"] = out["step_roofline"]["achieved_GBs"] / HBM_PEAK_GBS
+    out["table1_shape_euler"] = {
+        "rows": table1_euler(torch, mm, W),
+        "paper_gpu_ms_HD7970": {"8": 1.95, "16": 2.723, "32": 3.151, "64": 6.558, "128": 26.34},
+        "note": "paper Table 1 (Euler, FP32, AMD HD 7970): other hardware, context only"}
     if not args.no_batch:
         out["batched"] = batch_measure(torch, mm, W)
     if not args.no_cpu_baseline:

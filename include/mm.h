@@ -136,6 +136,14 @@ int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M_dev, int nst
 int mm_reduce(mm_plan plan, const mm_llg_params *params, const float *M_dev, mm_stats *out,
               void *stream);
 
+/* Relax toward the minimum-energy state (the paper's benchmark runs, Sec. 4,
+ * relax a cube under demag, exchange and anisotropy): step with `params`
+ * until max_i |M_i x H_eff,i| / Ms <= torque_tol, checking every
+ * `check_every` steps, or until max_steps.  Fills *out with the final
+ * observables and *steps_taken.  Synchronises at every check.              */
+int mm_llg_relax(mm_plan plan, const mm_llg_params *params, float *M_dev, double torque_tol, long long max_steps,
+                 int check_every, mm_stats *out, long long *steps_taken, void *stream);
+
 /* Newell tensor N in FP64 on the device for the octant of offsets
  * (i dx, j dy, k dz), 0 <= i < nx, 0 <= j < ny, 0 <= k < nz, written to
  * N_dev[6][nz][ny][nx] (order xx, yy, zz, xy, xz, yz); N_dev is caller

@@ -2,6 +2,7 @@
 // launch configuration, step driver with HIP-graph replay, timing.
 #include <cmath>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -346,6 +347,27 @@ int mm_reduce(mm_plan plan, const mm_llg_params *params, const float *M, mm_stat
     out->nonfinite = (long long)r[7];
     out->torque_max = r[8];
     if (out->nonfinite > 0) return fail(MM_ENONFINITE, std::to_string(out->nonfinite) + " non-finite cells");
+    return MM_OK;
+}
+
+int mm_llg_relax(mm_plan plan, const mm_llg_params *params, float *M, double torque_tol, long long max_steps,
+                 int check_every, mm_stats *out, long long *steps_taken, void *stream)
+{
+    Plan *p = P(plan);
+    if (!p || !M || !out || !steps_taken) return fail(MM_EINVAL, "NULL plan, M, out or steps_taken");
+    if (!(torque_tol > 0.0) || max_steps < 0 || check_every < 1) return fail(MM_EINVAL, "bad relax controls");
+    int rc = check_params(params);
+    if (rc != MM_OK) return rc;
+    long long done = 0;
+    *steps_taken = 0;
+    if ((rc = mm_reduce(plan, params, M, out, stream)) != MM_OK) return rc;
+    while (out->torque_max > torque_tol && done < max_steps) {
+        const long long k = std::min<long long>(check_every, max_steps - done);
+        if ((rc = mm_llg_step(plan, params, M, (int)k, stream)) != MM_OK) return rc;
+        done += k;
+        *steps_taken = done;
+        if ((rc = mm_reduce(plan, params, M, out, stream)) != MM_OK) return rc;
+    }
     return MM_OK;
 }
 

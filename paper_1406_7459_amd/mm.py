@@ -22,7 +22,8 @@ MM_RK4, MM_EULER = 0, 1
 PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv", "stage", "reduce")
 PASS_INDEX = {n: i for i, n in enumerate(PASSES)}
 
-SYMBOLS = ("mm_demag_setup", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_newell_tensor",
+SYMBOLS = ("mm_demag_setup", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_llg_relax",
+           "mm_newell_tensor",
            "mm_plan_spectrum", "mm_plan_query", "mm_plan_set_tile", "mm_plan_autotune",
            "mm_plan_set_timing", "mm_plan_timing", "mm_destroy", "mm_status_string",
            "mm_last_error", "mm_batch_setup", "mm_batch_demag", "mm_batch_step",
@@ -106,6 +107,8 @@ def lib():
     L.mm_demag_apply.argtypes = [vp, vp, vp, vp]
     L.mm_llg_step.argtypes = [vp, C.POINTER(LLGParams), vp, i, vp]
     L.mm_reduce.argtypes = [vp, C.POINTER(LLGParams), vp, C.POINTER(Stats), vp]
+    L.mm_llg_relax.argtypes = [vp, C.POINTER(LLGParams), vp, d, ll, i, C.POINTER(Stats),
+                               C.POINTER(C.c_longlong), vp]
     L.mm_newell_tensor.argtypes = [i, i, i, d, d, d, vp, vp]
     L.mm_plan_spectrum.argtypes = [vp, vp, ll, vp]
     L.mm_plan_query.argtypes = [vp, C.POINTER(PlanInfo)]
@@ -212,6 +215,18 @@ class Plan:
             return st.as_dict()
         _check(rc, "mm_reduce")
         return st.as_dict()
+
+    def relax(self, params: LLGParams, M: torch.Tensor, torque_tol: float, max_steps: int,
+              check_every: int = 100, stream=None) -> dict:
+        pm = _field(M, self.field_shape, "M")
+        st = Stats()
+        n = C.c_longlong()
+        _check(lib().mm_llg_relax(self._h, C.byref(params), pm, float(torque_tol), int(max_steps),
+                                  int(check_every), C.byref(st), C.byref(n), _stream(stream)),
+               "mm_llg_relax")
+        d = st.as_dict()
+        d["steps"] = n.value
+        return d
 
     def info(self) -> dict:
         inf = PlanInfo()

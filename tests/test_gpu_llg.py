@@ -158,3 +158,18 @@ def test_energy_decreases_film32_full_run():
     E = np.array(E)
     assert np.all(np.diff(E) <= 1e-6 * np.abs(E[:-1]))
     assert E[-1] < E[0]
+
+
+def test_relax_reaches_torque_tolerance_and_lowers_energy():
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 16, 16, 16
+    d = (2e-9, 2e-9, 2e-9)
+    mat = W.cube(16).mat
+    plan = mm.Plan(nx, ny, nz, *d)
+    p = mm.LLGParams.make(Ms=mat.Ms, A=mat.A, Ku=mat.Ku, alpha=1.0, dt=1e-14)
+    M = to_dev(mat.Ms * W.random_unit(nx, ny, nz, 31))
+    e0 = plan.reduce(p, M)["E_tot"]
+    st = plan.relax(p, M, torque_tol=1e3, max_steps=200000, check_every=500)
+    say("relax", st["steps"], "steps, torque", st["torque_max"], "E", st["E_tot"])
+    assert st["torque_max"] <= 1e3
+    assert st["E_tot"] < e0
