@@ -148,8 +148,6 @@ static int build_tasks(BatchImpl &b, BGroup &g)
         const int nxc = I.nx + 1, nrows = 3 * I.nz * I.ny;
         switch (g.pass) {
         case MM_PASS_XFWD:
-            for (int bx = 0; bx < (nrows + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));
-            break;
         case MM_PASS_XINV: {
             const int pairs = (nrows + 1) / 2;
             for (int bx = 0; bx < (pairs + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));

@@ -141,8 +141,9 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
         if (var == 1 && k.E1 == k.E0) return false;
         const int E = var == 0 ? k.E0 : k.E1;
         threads = P * (L / E);
-        lds = (tws + (k.nstage > 1 ? (is_rows(pass) ? (size_t)P * (L + 1) : (size_t)L * (P + 1)) : 0)) *
-              sizeof(float2);
+        // the x forward separates its packed rows through LDS even for one stage
+        const bool needs = k.nstage > 1 || pass == MM_PASS_XFWD;
+        lds = (tws + (needs ? (is_rows(pass) ? (size_t)P * (L + 1) : (size_t)L * (P + 1)) : 0)) * sizeof(float2);
     }
     return true;
 }
@@ -268,9 +269,11 @@ static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, 
     const int nxc = p.nxc;
     const int nrows = 3 * p.nz * p.ny;
     switch (pass) {
-    case MM_PASS_XFWD:
-        hipLaunchKernelGGL((k_xfwd<L, V>), dim3((nrows + P - 1) / P), block, lds, s, M, p.X1, nrows, lp2, p.tw[0]);
+    case MM_PASS_XFWD: {
+        const int pairs = (nrows + 1) / 2;
+        hipLaunchKernelGGL((k_xfwd<L, V>), dim3((pairs + P - 1) / P), block, lds, s, M, p.X1, nrows, lp2, p.tw[0]);
         break;
+    }
     case MM_PASS_YFWD:
         hipLaunchKernelGGL((k_yfwd<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X1, p.X2, nxc, lp2,
                            p.tw[1]);

@@ -54,7 +54,10 @@ __device__ __forceinline__ const float2 *stage_twiddles(float2 *lds, const float
 
 // ----------------------------------------------------------------- kernels ---
 
-// x forward: one real row of length nx, zero-padded to L = 2nx, -> nx+1 bins.
+// x forward, two real rows per complex transform: z = a + i b (rows 2m and
+// 2m+1, length nx, zero-padded to L = 2nx), Z = FFT(z), then
+//   A_k = (Z_k + conj Z_{L-k}) / 2,   B_k = (Z_k - conj Z_{L-k}) / (2i),
+// k = 0..nx; Z_{L-k} is read back through LDS.
 template <int L, int V>
 __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int nrows, int lp2,
                                           const float2 *__restrict__ tw, int bx)
@@ -64,29 +67,46 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int t = threadIdx.x;
     const int q = t % Q, p = t / Q;
-    const int row = (bx << lp2) + p;
-    const bool ok = row < nrows;
+    const int ra = ((bx << lp2) + p) * 2, rb = ra + 1;
+    const bool oka = ra < nrows, okb = rb < nrows;
+    float2 *col = lds + tw_slots<L>() + p * (L + 1);
     const LdsView s{lds + tw_slots<L>(), 1, p * (L + 1)};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
-    const float *src = M + (size_t)row * NX;
+    const float *sa = M + (size_t)ra * NX;
+    const float *sb = M + (size_t)rb * NX;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int i = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NX;  // compile-time after unrolling
-            v[b * R0 + r] = (!upper && ok && i < NX) ? make_float2(src[i], 0.f) : make_float2(0.f, 0.f);
+            const bool in = !upper && i < NX;
+            v[b * R0 + r] = make_float2(in && oka ? sa[i] : 0.f, in && okb ? sb[i] : 0.f);
         }
     fft_e<L, E, -1, false>(v, s, q, twl);
     constexpr int RL = last_radix<L, false>();
-    float2 *dst = X1 + (size_t)row * (NX + 1);
+    // the last exchange ended with a barrier: the column is free for Z
+#pragma unroll
+    for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) col[q + Q * b + r * (L / RL)] = v[b * RL + r];
+    __syncthreads();
+    float2 *da = X1 + (size_t)ra * (NX + 1);
+    float2 *db = X1 + (size_t)rb * (NX + 1);
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int k = q + Q * b + r * (L / RL);
-            if (ok && k <= NX) dst[k] = v[b * RL + r];
+            if (k <= NX) {
+                const float2 z = v[b * RL + r];
+                const float2 w = col[k == 0 ? 0 : L - k];
+                const float2 sp = make_float2(z.x + w.x, z.y - w.y);  // Z + conj(Zm)
+                const float2 sm = make_float2(z.x - w.x, z.y + w.y);  // Z - conj(Zm)
+                if (oka) da[k] = make_float2(0.5f * sp.x, 0.5f * sp.y);
+                if (okb) db[k] = make_float2(0.5f * sm.y, -0.5f * sm.x);
+            }
         }
 }
 
