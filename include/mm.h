@@ -108,7 +108,7 @@ enum {
  * eq. (7)-(12), set-up of K~ per the remark after eq. (16)).  Computes the
  * Newell tensor in FP64 on the current device, its transform in FP64 by
  * separable cosine/sine sums, and stores the real, parity-folded octant of
- * K~ = FFT(-N)/(2nx 2ny 2nz) in FP32.  Allocates the plan's workspace with
+ * K~ = FFT(-N)/(2nx 2ny 2nz) in FP32, one six-float record per frequency.  Allocates the plan's workspace with
  * hipMalloc and synchronises the device before returning.
  * Supported n per axis: 2^a or 3*2^a, 1 <= n <= 512 (padded lengths 2n of
  * 2, 4, 6, 8, 12, 16, 24, ..., 512, 768, 1024: radices 2, 3, 4, 8).
@@ -153,8 +153,9 @@ int mm_llg_relax(mm_plan plan, const mm_llg_params *params, float *M_dev, double
 int mm_newell_tensor(int nx, int ny, int nz, double dx, double dy, double dz, double *N_dev,
                      void *stream);
 
-/* Copy the plan's stored K~ octant (FP32, [6][nzK][ny+1][nx+1], nzK = nz+1,
- * or 1 when nz = 1; scale and sign folded in) to Kt_dev, which holds
+/* Copy the plan's stored K~ octant (FP32, [nzK][ny+1][nx+1][6] with the six
+ * components xx, yy, zz, xy, xz, yz per frequency, nzK = nz+1, or 1 when
+ * nz = 1; scale and sign folded in) to Kt_dev, which holds
  * `count` floats (>= mm_plan_info.spectrum_count).  Asynchronous.           */
 int mm_plan_spectrum(mm_plan plan, float *Kt_dev, long long count, void *stream);
 

@@ -159,8 +159,9 @@ static int build_tasks(BatchImpl &b, BGroup &g)
                 for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, pl, 0));
             break;
         case MM_PASS_ZCONV:
-            for (int ky = 0; ky < 2 * I.ny; ++ky)
-                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, ky, 0));
+            for (int y = 0; y < 2 * I.ny; ++y)
+                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx)
+                    g.tasks.push_back(make_int4(i, bx, ky_of_slot(y, I.ny), 0));
             break;
         case MM_PASS_YCONV:
             for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));

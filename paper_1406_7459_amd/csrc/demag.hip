@@ -25,13 +25,13 @@ __global__ __launch_bounds__(conv_max_threads<L>()) void k_conv_reg3(float2 *__r
                                                                       const float *__restrict__ Kt, int nxc, int ny,
                                                                       int lp2, const float2 *__restrict__ tw)
 {
-    conv_reg3_body<L, ZAXIS>(X, Kt, nxc, ny, lp2, tw, blockIdx.x, ZAXIS ? (int)blockIdx.y : 0);
+    conv_reg3_body<L, ZAXIS>(X, Kt, nxc, ny, lp2, tw, blockIdx.x, ZAXIS ? ky_of_slot(blockIdx.y, ny) : 0);
 }
 template <int L, int V, bool ZAXIS>
 __global__ __launch_bounds__(1024) void k_conv_split(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc,
                                                       int ny, int lp2, const float2 *__restrict__ tw)
 {
-    conv_split_body<L, V, ZAXIS>(X, Kt, nxc, ny, lp2, tw, blockIdx.x, ZAXIS ? (int)blockIdx.y : 0);
+    conv_split_body<L, V, ZAXIS>(X, Kt, nxc, ny, lp2, tw, blockIdx.x, ZAXIS ? ky_of_slot(blockIdx.y, ny) : 0);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yinv(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc,

@@ -154,6 +154,16 @@ __device__ __forceinline__ float2 krow(float k0, float k1, float k2, float2 m0, 
     return make_float2(fmaf(k2, m2.x, fmaf(k1, m1.x, k0 * m0.x)), fmaf(k2, m2.y, fmaf(k1, m1.y, k0 * m0.y)));
 }
 
+// Order of the ky rows of the z pass: 0, ny, 1, 2ny-1, 2, 2ny-2, ... so that
+// a row and its mirror 2ny - ky (the same K~ octant row) run back to back.
+__device__ __host__ __forceinline__ int ky_of_slot(int y, int ny)
+{
+    if (y == 0) return 0;
+    if (y == 1) return ny;
+    const int m = (y - 2) / 2 + 1;
+    return (y & 1) ? 2 * ny - m : m;
+}
+
 // Spectral product at one frequency: H~ = K~ . M~ with K~ real and symmetric
 // (eq. (13)/(15)); the off-diagonal entries carry the parity signs of the
 // folded octant.
@@ -211,8 +221,9 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const int nyk = ny + 1;
     const int kyf = ky <= ny ? ky : 2 * ny - ky;
     const float sy0 = ky <= ny ? 1.f : -1.f;
-    const size_t kc = ZAXIS ? (size_t)(NH + 1) * nyk * nxc : (size_t)(NH + 1) * nxc;
-    const float *Kb = Kt + (ZAXIS ? (size_t)kyf * nxc : 0) + (ok ? kx : 0);
+    // K~ records of six floats (xx, yy, zz, xy, xz, yz) per octant frequency
+    const float2 *Kb = reinterpret_cast<const float2 *>(Kt) +
+                       3 * ((ZAXIS ? (size_t)kyf * nxc : 0) + (size_t)(ok ? kx : 0));
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -221,13 +232,12 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             const int kf = k <= NH ? k : L - k;
             const float sk = k <= NH ? 1.f : -1.f;
             const int i = b * RL + r;
+            const float2 *K = Kb + 3 * (ZAXIS ? (size_t)kf * nyk * nxc : (size_t)kf * nxc);
+            const float2 k01 = K[0], k23 = K[1], k45 = K[2];
             if constexpr (ZAXIS) {
-                const float *K = Kb + (size_t)kf * nyk * nxc;
-                kdot(va[i], vb[i], vc[i], K[0], K[kc], K[2 * kc], sy0 * K[3 * kc], sk * K[4 * kc],
-                     sy0 * sk * K[5 * kc]);
+                kdot(va[i], vb[i], vc[i], k01.x, k01.y, k23.x, sy0 * k23.y, sk * k45.x, sy0 * sk * k45.y);
             } else {
-                const float *K = Kb + (size_t)kf * nxc;
-                kdot(va[i], vb[i], vc[i], K[0], K[kc], K[2 * kc], sk * K[3 * kc], 0.f, 0.f);
+                kdot(va[i], vb[i], vc[i], k01.x, k01.y, k23.x, sk * k23.y, 0.f, 0.f);
             }
         }
 
@@ -302,8 +312,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     const int nyk = ny + 1;
     const int kyf = ky <= ny ? ky : 2 * ny - ky;
     const float sy0 = ky <= ny ? 1.f : -1.f;
-    const size_t kc = ZAXIS ? (size_t)(NH + 1) * nyk * nxc : (size_t)(NH + 1) * nxc;
-    const float *Kb = Kt + (ZAXIS ? (size_t)kyf * nxc : 0) + (ok ? kx : 0);
+    const float *Kb = Kt + 6 * ((ZAXIS ? (size_t)kyf * nxc : 0) + (size_t)(ok ? kx : 0));
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -316,8 +325,8 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
             const float w0 = g == 0 ? 1.f : (g == 1 ? sxy : sxz);
             const float w1 = g == 0 ? sxy : (g == 1 ? 1.f : syz);
             const float w2 = g == 0 ? sxz : (g == 1 ? syz : 1.f);
-            const float *K = Kb + (ZAXIS ? (size_t)kf * nyk * nxc : (size_t)kf * nxc);
-            const float k0 = w0 * K[c0 * kc], k1 = w1 * K[c1 * kc], k2 = w2 * K[c2 * kc];
+            const float *K = Kb + 6 * (ZAXIS ? (size_t)kf * nyk * nxc : (size_t)kf * nxc);
+            const float k0 = w0 * K[c0], k1 = w1 * K[c1], k2 = w2 * K[c2];
             const float2 m0 = buf[((size_t)0 * L + k) * rsl + p];
             const float2 m1 = buf[((size_t)1 * L + k) * rsl + p];
             const float2 m2 = buf[((size_t)2 * L + k) * rsl + p];

@@ -64,7 +64,7 @@ struct Plan {
     int device = 0;
     size_t lds_limit = 65536;
 
-    float *Kt = nullptr;         // [6][nzK][ny+1][nx+1]
+    float *Kt = nullptr;         // [nzK][ny+1][nx+1][6]
     long long nK = 0;
     float2 *X1 = nullptr;        // [3][nz][ny][nx+1]
     float2 *X2 = nullptr;        // [3][nz][2ny][nx+1] (nz > 1 only)

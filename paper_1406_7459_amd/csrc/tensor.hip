@@ -19,8 +19,10 @@
 //     dense FP64 contractions (x, then y, then z) produce the octant
 //     0..n of every axis, which holds the whole spectrum by parity.
 //  3. K~ is scaled by the inverse-transform normalisation 1/(2nx 2ny 2nz)
-//     (for nz = 1 the trivial z axis is dropped and 1/(2nx 2ny) is used) and
-//     rounded once to FP32.
+//     (for nz = 1 the trivial z axis is dropped and 1/(2nx 2ny) is used),
+//     rounded once to FP32 and stored as a six-float record per octant
+//     frequency, [kz][ky][kx][xx yy zz xy xz yz]: the spectral product reads
+//     one 24-byte record per frequency.
 #include <cmath>
 
 #include "mm_internal.hpp"
@@ -211,10 +213,11 @@ __global__ void k_spectrum_store(const double *__restrict__ D, float *__restrict
     for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < total;
          id += (long long)gridDim.x * blockDim.x) {
         const int c = (int)(id / per_c);
+        const long long f = id - (long long)c * per_c;  // octant frequency
         const double sgn = c < 3 ? -1.0 : 1.0;
         double v = sgn * scale * D[id];
         if (zero_xz_yz && c >= 4) v = 0.0;
-        Kt[id] = (float)v;
+        Kt[6 * f + c] = (float)v;  // six-float record per frequency
     }
 }
 

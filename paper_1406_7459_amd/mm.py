@@ -236,11 +236,11 @@ class Plan:
                     tiles={PASSES[k]: inf.cfg[k] for k in range(8)})
 
     def spectrum(self, stream=None) -> torch.Tensor:
-        """The stored K~ octant, float32 [6][nzK][ny+1][nx+1]."""
+        """The stored K~ octant, float32 [nzK][ny+1][nx+1][6]."""
         inf = self.info()
         nx, ny, nz = self.shape
         nzk = nz + 1 if nz > 1 else 1
-        out = torch.empty((6, nzk, ny + 1, nx + 1), dtype=torch.float32, device="cuda")
+        out = torch.empty((nzk, ny + 1, nx + 1, 6), dtype=torch.float32, device="cuda")
         _check(lib().mm_plan_spectrum(self._h, out.data_ptr(), out.numel(), _stream(stream)),
                "mm_plan_spectrum")
         assert out.numel() == inf["spectrum_count"]
