@@ -48,11 +48,14 @@ struct TimingAcc {
     long long n = 0;
 };
 
+typedef std::pair<int, std::pair<hipEvent_t, hipEvent_t>> TimedPair;
+
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     const float *M = nullptr;
     std::string key;
+    std::vector<TimedPair> events;  // event records captured in the graph (timing mode)
 };
 
 struct Plan {
@@ -80,8 +83,9 @@ struct Plan {
 
     bool timing = false;
     TimingAcc acc[MM_PASS_COUNT];
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<TimedPair> pending;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;
+    size_t graph_owned = 0;               // pending entries [0, graph_owned) belong to a graph
 
     GraphCache graph;
     hipStream_t cap_stream = nullptr;
