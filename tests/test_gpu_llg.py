@@ -173,3 +173,24 @@ def test_relax_reaches_torque_tolerance_and_lowers_energy():
     say("relax", st["steps"], "steps, torque", st["torque_max"], "E", st["E_tot"])
     assert st["torque_max"] <= 1e3
     assert st["E_tot"] < e0
+
+
+def test_timed_graph_counts_every_kernel_and_matches_untimed():
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 32, 16, 4
+    d = (2e-9, 2e-9, 2e-9)
+    p = mm.LLGParams.make(Ms=8e5, A=1.3e-11, alpha=0.2, dt=1e-14)
+    plan = mm.Plan(nx, ny, nz, *d)
+    M0 = to_dev(8e5 * W.random_unit(nx, ny, nz, 12))
+    a = M0.clone()
+    plan.step(p, a, 10)
+    b = M0.clone()
+    plan.set_timing(True)
+    plan.step(p, b, 5)
+    plan.step(p, b, 5)     # replays the captured 5-step graph
+    t = plan.timing()
+    plan.set_timing(False)
+    assert np.array_equal(to_host(a), to_host(b))
+    for k in ("xfwd", "yfwd", "zconv", "yinv", "xinv", "stage"):
+        assert t[k][1] == 20, (k, t[k])   # the last replay: 5 steps x 4 stages
+        assert t[k][0] > 0.0
