@@ -54,20 +54,16 @@ void timing_end(Plan &p, int pass, hipStream_t s, hipEvent_t ev0)
 
 static int drain_timing(Plan &p)
 {
-    for (size_t i = 0; i < p.pending.size(); ++i) {
-        const TimedPair &t = p.pending[i];
+    for (const TimedPair &t : p.pending) {
         MMK_HIP(hipEventSynchronize(t.second.second));
         float ms = 0.f;
         MMK_HIP(hipEventElapsedTime(&ms, t.second.first, t.second.second));
         p.acc[t.first].ms += ms;
         p.acc[t.first].n += 1;
-        if (i >= p.graph_owned) {  // events of a captured graph stay with it
-            p.event_pool.push_back(t.second.first);
-            p.event_pool.push_back(t.second.second);
-        }
+        p.event_pool.push_back(t.second.first);
+        p.event_pool.push_back(t.second.second);
     }
     p.pending.clear();
-    p.graph_owned = 0;
     return MM_OK;
 }
 
@@ -75,10 +71,6 @@ static void drop_plan_graph(Plan &p)
 {
     if (p.graph.exec) (void)hipGraphExecDestroy(p.graph.exec);
     if (p.graph.graph) (void)hipGraphDestroy(p.graph.graph);
-    for (auto &t : p.graph.events) {
-        p.event_pool.push_back(t.second.first);
-        p.event_pool.push_back(t.second.second);
-    }
     p.graph = GraphCache{};
 }
 
@@ -299,38 +291,23 @@ int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M, int nsteps,
     hipStream_t s = (hipStream_t)stream;
     const StageCoef c = stage_coef(*p, *params);
     static const bool no_graph = std::getenv("MM_NO_GRAPH") != nullptr;
-    if (no_graph || (nsteps < 2 && !p->timing)) {
+    if (p->timing || no_graph || nsteps < 2) {
+        // direct launches (timing mode brackets every one with HIP events)
         for (int i = 0; i < nsteps; ++i)
             if ((rc = llg_enqueue_step(*p, c, params->integrator, M, s)) != MM_OK) return rc;
         return MM_OK;
     }
-    // Without timing one step is captured and replayed nsteps times.  With
-    // timing all nsteps steps are captured together with an event record
-    // around every kernel, and the graph is replayed once: per-kernel
-    // durations come from the same replay as the wall-clock time.
-    const int per_graph = p->timing ? nsteps : 1;
     std::string key((const char *)&c, sizeof(c));
     key += std::string((const char *)&params->integrator, sizeof(int));
     key += std::string((const char *)p->tile, sizeof(p->tile));
-    key += "|" + std::to_string(per_graph) + (p->timing ? "T" : "");
     if (!p->graph.exec || p->graph.M != M || p->graph.key != key) {
         drop_plan_graph(*p);
-        const size_t before = p->pending.size();
         MMK_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < per_graph && rc == MM_OK; ++i)
-            rc = llg_enqueue_step(*p, c, params->integrator, M, p->cap_stream);
+        rc = llg_enqueue_step(*p, c, params->integrator, M, p->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
-        // the event records made during capture belong to the graph
-        GraphCache gc;
-        gc.events.assign(p->pending.begin() + before, p->pending.end());
-        p->pending.resize(before);
         if (rc != MM_OK || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
-            for (auto &t : gc.events) {
-                p->event_pool.push_back(t.second.first);
-                p->event_pool.push_back(t.second.second);
-            }
             return rc != MM_OK ? rc : fail(MM_EHIP, std::string("capture: ") + hipGetErrorString(e));
         }
         hipGraphExec_t x = nullptr;
@@ -339,21 +316,12 @@ int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M, int nsteps,
             (void)hipGraphDestroy(g);
             return fail(MM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
-        gc.graph = g;
-        gc.exec = x;
-        gc.M = M;
-        gc.key = key;
-        p->graph = gc;
+        p->graph.graph = g;
+        p->graph.exec = x;
+        p->graph.M = M;
+        p->graph.key = key;
     }
-    for (int i = 0; i < nsteps / per_graph; ++i) MMK_HIP(hipGraphLaunch(p->graph.exec, s));
-    if (p->timing) {
-        // read after this replay: graph-owned pairs go first in the pending list
-        // a replay overwrites the previous one's records: keep one copy
-        std::vector<TimedPair> rest(p->pending.begin() + p->graph_owned, p->pending.end());
-        p->pending.assign(p->graph.events.begin(), p->graph.events.end());
-        p->graph_owned = p->pending.size();
-        p->pending.insert(p->pending.end(), rest.begin(), rest.end());
-    }
+    for (int i = 0; i < nsteps; ++i) MMK_HIP(hipGraphLaunch(p->graph.exec, s));
     return MM_OK;
 }
 

@@ -55,7 +55,6 @@ struct GraphCache {
     hipGraph_t graph = nullptr;
     const float *M = nullptr;
     std::string key;
-    std::vector<TimedPair> events;  // event records captured in the graph (timing mode)
 };
 
 struct Plan {
@@ -85,7 +84,6 @@ struct Plan {
     TimingAcc acc[MM_PASS_COUNT];
     std::vector<TimedPair> pending;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;
-    size_t graph_owned = 0;               // pending entries [0, graph_owned) belong to a graph
 
     GraphCache graph;
     hipStream_t cap_stream = nullptr;

@@ -175,7 +175,7 @@ def test_relax_reaches_torque_tolerance_and_lowers_energy():
     assert st["E_tot"] < e0
 
 
-def test_timed_graph_counts_every_kernel_and_matches_untimed():
+def test_timing_mode_counts_every_kernel_and_matches_untimed():
     from paper_1406_7459_amd import mm
     nx, ny, nz = 32, 16, 4
     d = (2e-9, 2e-9, 2e-9)
@@ -186,11 +186,11 @@ def test_timed_graph_counts_every_kernel_and_matches_untimed():
     plan.step(p, a, 10)
     b = M0.clone()
     plan.set_timing(True)
-    plan.step(p, b, 5)
-    plan.step(p, b, 5)     # replays the captured 5-step graph
+    plan.timing()
+    plan.step(p, b, 10)
     t = plan.timing()
     plan.set_timing(False)
     assert np.array_equal(to_host(a), to_host(b))
     for k in ("xfwd", "yfwd", "zconv", "yinv", "xinv", "stage"):
-        assert t[k][1] == 20, (k, t[k])   # the last replay: 5 steps x 4 stages
+        assert t[k][1] == 40, (k, t[k])   # 10 steps x 4 stages
         assert t[k][0] > 0.0
