@@ -183,6 +183,7 @@ int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_p
     p.dx = dx; p.dy = dy; p.dz = dz;
     p.Lx = 2 * nx; p.Ly = 2 * ny; p.Lz = nz > 1 ? 2 * nz : 1;
     p.nxc = nx + 1;
+    p.xp = x_pitch(p.nxc);
     p.nzK = nz > 1 ? nz + 1 : 1;
     if (hipGetDevice(&p.device) != hipSuccess) {
         free_plan(o);
@@ -197,9 +198,9 @@ int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_p
     const size_t N = (size_t)nx * ny * nz;
     p.nK = 6LL * p.nzK * (ny + 1) * (nx + 1);
     p.red_blocks = 1024;
-    const size_t szK = sizeof(float) * (size_t)p.nK;
-    const size_t szX1 = sizeof(float2) * 3 * (size_t)nz * ny * p.nxc;
-    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * 2 * ny * p.nxc : 0;
+    const size_t szK = sizeof(float) * 6 * (size_t)p.nzK * (ny + 1) * p.xp;
+    const size_t szX1 = sizeof(float2) * 3 * (size_t)nz * ny * p.xp;
+    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * 2 * ny * p.xp : 0;
     const size_t szF = sizeof(float) * 3 * N;
     const size_t szPart = sizeof(double) * 9 * (size_t)p.red_blocks;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
@@ -394,7 +395,9 @@ int mm_plan_spectrum(mm_plan plan, float *Kt, long long count, void *stream)
     Plan *p = P(plan);
     if (!p || !Kt) return fail(MM_EINVAL, "NULL plan or Kt");
     if (count < p->nK) return fail(MM_EINVAL, "Kt too small");
-    MMK_HIP(hipMemcpyAsync(Kt, p->Kt, sizeof(float) * (size_t)p->nK, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    const size_t rec = 6 * sizeof(float);
+    MMK_HIP(hipMemcpy2DAsync(Kt, rec * p->nxc, p->Kt, rec * p->xp, rec * p->nxc, (size_t)p->nzK * (p->ny + 1),
+                             hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return MM_OK;
 }
 

@@ -8,13 +8,15 @@
 // a real-to-complex FFT that never touches the zero half of the padded grid
 // (forward) nor computes the discarded half (inverse):
 //
-//   XFWD   M [3][nz][ny][nx] f32   -> X1 [3][nz][ny][nx+1] c64   x: R2C, input i < nx
-//   YFWD   X1                      -> X2 [3][nz][2ny][nx+1]      y: input j < ny
+//   XFWD   M [3][nz][ny][nx] f32   -> X1 [3][nz][ny][xp] c64     x: R2C, input i < nx
+//   YFWD   X1                      -> X2 [3][nz][2ny][xp]        y: input j < ny
 //   ZCONV  X2 -> X2 in place: z forward (input k < nz), H~ = K~ . M~
 //          (eq. (13)/(15), six real K~ components with parity signs),
 //          z inverse, rows k < nz written back
 //   YINV   X2 -> X1                                               y: keep j < ny
 //   XINV   X1 -> H [3][nz][ny][nx] f32                            x: C2R, keep i < nx
+// (xp = x_pitch(nx + 1): rows of nx + 1 values padded to 64 bytes; the
+// padding is never read or written.)
 // For nz = 1 the padded z axis has length 2 with the second slot zero, so the
 // z transform is the identity up to a factor folded into K~; YCONV then does
 // y forward, product and y inverse in one pass (XFWD, YCONV, XINV).
@@ -25,6 +27,7 @@
 // (fft_engine.hpp).
 #pragma once
 #include "fft_engine.hpp"
+#include "layout.hpp"
 
 namespace mmk {
 
@@ -62,7 +65,7 @@ template <int L, int V>
 __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int nrows, int lp2,
                                           const float2 *__restrict__ tw, int bx)
 {
-    constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2;
+    constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int t = threadIdx.x;
@@ -92,8 +95,8 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
 #pragma unroll
         for (int r = 0; r < RL; ++r) col[q + Q * b + r * (L / RL)] = v[b * RL + r];
     __syncthreads();
-    float2 *da = X1 + (size_t)ra * (NX + 1);
-    float2 *db = X1 + (size_t)rb * (NX + 1);
+    float2 *da = X1 + (size_t)ra * XP;
+    float2 *db = X1 + (size_t)rb * XP;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -123,27 +126,28 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
     const int p = t & (P - 1), q = t >> lp2;
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
+    const int xp = x_pitch(nxc);
     const LdsView s{lds + tw_slots<L>(), P + 1, p};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
-    const float2 *src = X1 + (size_t)plane * NY * nxc + kx;
+    const float2 *src = X1 + (size_t)plane * NY * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int j = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NY;
-            v[b * R0 + r] = (!upper && ok && j < NY) ? src[(size_t)j * nxc] : make_float2(0.f, 0.f);
+            v[b * R0 + r] = (!upper && ok && j < NY) ? src[(size_t)j * xp] : make_float2(0.f, 0.f);
         }
     fft_e<L, E, -1, false>(v, s, q, twl);
     constexpr int RL = last_radix<L, false>();
-    float2 *dst = X2 + (size_t)plane * L * nxc + kx;
+    float2 *dst = X2 + (size_t)plane * L * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int k = q + Q * b + r * (L / RL);
-            if (ok) dst[(size_t)k * nxc] = v[b * RL + r];
+            if (ok) dst[(size_t)k * xp] = v[b * RL + r];
         }
 }
 
@@ -195,10 +199,11 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const int p = t & (P - 1), q = t >> lp2;
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
+    const int xp = x_pitch(nxc);
     const LdsView s{lds + tw_slots<L>(), P + 1, p};
-    const size_t rs = ZAXIS ? (size_t)2 * ny * nxc : (size_t)nxc;  // stride along the transform
-    const size_t cs = (size_t)NH * rs;                              // component stride
-    float2 *base = X + (size_t)ky * nxc + kx;
+    const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;  // stride along the transform
+    const size_t cs = (size_t)NH * rs;                            // component stride
+    float2 *base = X + (size_t)ky * xp + kx;
     float2 va[E], vb[E], vc[E];
     constexpr int R0 = first_radix<L, false>();
 #pragma unroll
@@ -223,7 +228,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const float sy0 = ky <= ny ? 1.f : -1.f;
     // K~ records of six floats (xx, yy, zz, xy, xz, yz) per octant frequency
     const float2 *Kb = reinterpret_cast<const float2 *>(Kt) +
-                       3 * ((ZAXIS ? (size_t)kyf * nxc : 0) + (size_t)(ok ? kx : 0));
+                       3 * ((ZAXIS ? (size_t)kyf * xp : 0) + (size_t)(ok ? kx : 0));
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -232,7 +237,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             const int kf = k <= NH ? k : L - k;
             const float sk = k <= NH ? 1.f : -1.f;
             const int i = b * RL + r;
-            const float2 *K = Kb + 3 * (ZAXIS ? (size_t)kf * nyk * nxc : (size_t)kf * nxc);
+            const float2 *K = Kb + 3 * (ZAXIS ? (size_t)kf * nyk * xp : (size_t)kf * xp);
             const float2 k01 = K[0], k23 = K[1], k45 = K[2];
             if constexpr (ZAXIS) {
                 kdot(va[i], vb[i], vc[i], k01.x, k01.y, k23.x, sy0 * k23.y, sk * k45.x, sy0 * sk * k45.y);
@@ -278,12 +283,13 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     const int p = t & (P - 1), q = t >> lp2;
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
+    const int xp = x_pitch(nxc);
     const int rsl = P + 1;
     float2 *buf = lds + tw_slots<L>();
     const LdsView s{buf + (size_t)g * L * rsl, rsl, p};
-    const size_t rs = ZAXIS ? (size_t)2 * ny * nxc : (size_t)nxc;
+    const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;
     const size_t cs = (size_t)NH * rs;
-    float2 *base = X + (size_t)g * cs + (size_t)ky * nxc + kx;
+    float2 *base = X + (size_t)g * cs + (size_t)ky * xp + kx;
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
 #pragma unroll
@@ -312,7 +318,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     const int nyk = ny + 1;
     const int kyf = ky <= ny ? ky : 2 * ny - ky;
     const float sy0 = ky <= ny ? 1.f : -1.f;
-    const float *Kb = Kt + 6 * ((ZAXIS ? (size_t)kyf * nxc : 0) + (size_t)(ok ? kx : 0));
+    const float *Kb = Kt + 6 * ((ZAXIS ? (size_t)kyf * xp : 0) + (size_t)(ok ? kx : 0));
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -325,7 +331,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
             const float w0 = g == 0 ? 1.f : (g == 1 ? sxy : sxz);
             const float w1 = g == 0 ? sxy : (g == 1 ? 1.f : syz);
             const float w2 = g == 0 ? sxz : (g == 1 ? syz : 1.f);
-            const float *K = Kb + 6 * (ZAXIS ? (size_t)kf * nyk * nxc : (size_t)kf * nxc);
+            const float *K = Kb + 6 * (ZAXIS ? (size_t)kf * nyk * xp : (size_t)kf * xp);
             const float k0 = w0 * K[c0], k1 = w1 * K[c1], k2 = w2 * K[c2];
             const float2 m0 = buf[((size_t)0 * L + k) * rsl + p];
             const float2 m1 = buf[((size_t)1 * L + k) * rsl + p];
@@ -357,27 +363,28 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
     const int p = t & (P - 1), q = t >> lp2;
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
+    const int xp = x_pitch(nxc);
     const LdsView s{lds + tw_slots<L>(), P + 1, p};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
-    const float2 *src = X2 + (size_t)plane * L * nxc + kx;
+    const float2 *src = X2 + (size_t)plane * L * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k = q + Q * b + r * (L / R0);
-            v[b * R0 + r] = ok ? src[(size_t)k * nxc] : make_float2(0.f, 0.f);
+            v[b * R0 + r] = ok ? src[(size_t)k * xp] : make_float2(0.f, 0.f);
         }
     fft_e<L, E, +1, false>(v, s, q, twl);
     constexpr int RL = last_radix<L, false>();
-    float2 *dst = X1 + (size_t)plane * NY * nxc + kx;
+    float2 *dst = X1 + (size_t)plane * NY * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int j = q + Q * b + r * (L / RL);
             const bool upper = r * (L / RL) >= NY;
-            if (!upper && ok && j < NY) dst[(size_t)j * nxc] = v[b * RL + r];
+            if (!upper && ok && j < NY) dst[(size_t)j * xp] = v[b * RL + r];
         }
 }
 
@@ -388,7 +395,7 @@ template <int L, int V>
 __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *__restrict__ H, int nrows, int lp2,
                                           const float2 *__restrict__ tw, int bx)
 {
-    constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, NXC = NX + 1;
+    constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int t = threadIdx.x;
@@ -396,8 +403,8 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
     const int ra = ((bx << lp2) + p) * 2, rb = ra + 1;
     const bool oka = ra < nrows, okb = rb < nrows;
     const LdsView s{lds + tw_slots<L>(), 1, p * (L + 1)};
-    const float2 *sa = X1 + (size_t)ra * NXC;
-    const float2 *sb = X1 + (size_t)rb * NXC;
+    const float2 *sa = X1 + (size_t)ra * XP;
+    const float2 *sb = X1 + (size_t)rb * XP;
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
 #pragma unroll

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/mm.h"
+#include "layout.hpp"
 
 namespace mmk {
 
@@ -62,14 +63,15 @@ struct Plan {
     double dx = 0, dy = 0, dz = 0;
     int Lx = 0, Ly = 0, Lz = 0;  // Lz = 1 when nz == 1 (z collapsed)
     int nxc = 0;                 // nx + 1
+    int xp = 0;                  // x_pitch(nxc): row pitch of X1, X2 and K~
     int nzK = 0;                 // octant depth of K~: nz + 1, or 1 when nz == 1
     int device = 0;
     size_t lds_limit = 65536;
 
-    float *Kt = nullptr;         // [nzK][ny+1][nx+1][6]
-    long long nK = 0;
-    float2 *X1 = nullptr;        // [3][nz][ny][nx+1]
-    float2 *X2 = nullptr;        // [3][nz][2ny][nx+1] (nz > 1 only)
+    float *Kt = nullptr;         // [nzK][ny+1][xp][6], kx < nx + 1 used
+    long long nK = 0;            // 6 nzK (ny+1) (nx+1): the exported (unpadded) count
+    float2 *X1 = nullptr;        // [3][nz][ny][xp]
+    float2 *X2 = nullptr;        // [3][nz][2ny][xp] (nz > 1 only)
     float *H = nullptr;          // [3][N] demag field scratch for the step driver
     float *Sa = nullptr, *Sb = nullptr, *kacc = nullptr;  // stage states and RK4 accumulator
     double *part = nullptr;      // reduction partials

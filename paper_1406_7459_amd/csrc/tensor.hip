@@ -206,8 +206,8 @@ __global__ void k_axis_transform(const double *__restrict__ in, double *__restri
 // K~ = sign * scale * D in FP32; sign -1 for the diagonal (K = -N, all-cosine
 // sums), +1 for the off-diagonals ((-i)^2 from the two sine axes times -1).
 // For nz = 1 the odd-in-z components vanish identically and are written 0.
-__global__ void k_spectrum_store(const double *__restrict__ D, float *__restrict__ Kt, long long per_c,
-                                 double scale, int zero_xz_yz)
+__global__ void k_spectrum_store(const double *__restrict__ D, float *__restrict__ Kt, long long per_c, int nxc,
+                                 int xp, double scale, int zero_xz_yz)
 {
     const long long total = 6 * per_c;
     for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < total;
@@ -217,7 +217,8 @@ __global__ void k_spectrum_store(const double *__restrict__ D, float *__restrict
         const double sgn = c < 3 ? -1.0 : 1.0;
         double v = sgn * scale * D[id];
         if (zero_xz_yz && c >= 4) v = 0.0;
-        Kt[6 * f + c] = (float)v;  // six-float record per frequency
+        const long long row = f / nxc;
+        Kt[6 * (row * xp + (f - row * nxc)) + c] = (float)v;  // six-float record per frequency
     }
 }
 
@@ -281,7 +282,7 @@ int build_spectrum(Plan &p, hipStream_t s)
         const long long per_c = (long long)p.nzK * (ny + 1) * (nx + 1);
         long long blocks = (6 * per_c + 255) / 256;
         if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(k_spectrum_store, dim3((unsigned)blocks), dim3(256), 0, s, D, p.Kt, per_c, scale,
+        hipLaunchKernelGGL(k_spectrum_store, dim3((unsigned)blocks), dim3(256), 0, s, D, p.Kt, per_c, nx + 1, p.xp, scale,
                            nz == 1 ? 1 : 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = fail(MM_EHIP, std::string("k_spectrum_store: ") + hipGetErrorString(e));
