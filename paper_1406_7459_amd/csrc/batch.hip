@@ -3,7 +3,9 @@
 // runs through the same kernel bodies as a single plan (demag_kernels.hpp,
 // stage_body.hpp); a batched launch covers one pass kind for all instances
 // that share the transform length of that pass, reading its workgroups'
-// (instance, block) coordinates from a task table.  A whole RK4 step is a
+// (instance, block) coordinates from a task table (column passes read it
+// through the XCD mapping of layout.hpp, so neighbouring tasks share an
+// L2).  A whole RK4 step is a
 // fixed sequence of such launches and is captured once into a HIP graph.
 //
 // Grouping by length keeps each launch's register and LDS budget that of its
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(1024) void kb_xfwd(const BInst *__restrict__ B, con
 template <int L, int V>
 __global__ __launch_bounds__(1024) void kb_yfwd(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
 {
-    const int4 t = T[blockIdx.x];
+    const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
     yfwd_body<L, V>(I.X1, I.X2, I.nx + 1, lp2, I.tw1, t.y, t.z);
 }
@@ -53,21 +55,21 @@ template <int L, bool Z>
 __global__ __launch_bounds__(conv_max_threads<L>()) void kb_reg3(const BInst *__restrict__ B,
                                                                   const int4 *__restrict__ T, int lp2)
 {
-    const int4 t = T[blockIdx.x];
+    const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
     conv_reg3_body<L, Z>(Z ? I.X2 : I.X1, I.Kt, I.nx + 1, I.ny, lp2, Z ? I.tw2 : I.tw1, t.y, t.z);
 }
 template <int L, int V, bool Z>
 __global__ __launch_bounds__(1024) void kb_split(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
 {
-    const int4 t = T[blockIdx.x];
+    const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
     conv_split_body<L, V, Z>(Z ? I.X2 : I.X1, I.Kt, I.nx + 1, I.ny, lp2, Z ? I.tw2 : I.tw1, t.y, t.z);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void kb_yinv(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
 {
-    const int4 t = T[blockIdx.x];
+    const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
     yinv_body<L, V>(I.X2, I.X1, I.nx + 1, lp2, I.tw1, t.y, t.z);
 }
@@ -158,10 +160,10 @@ static int build_tasks(BatchImpl &b, BGroup &g)
             for (int pl = 0; pl < 3 * I.nz; ++pl)
                 for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, pl, 0));
             break;
-        case MM_PASS_ZCONV:
-            for (int y = 0; y < 2 * I.ny; ++y)
+        case MM_PASS_ZCONV:  // the two rows of a mirror pair next to each other, then the tile
+            for (int m = 0; m < I.ny; ++m)
                 for (int bx = 0; bx < (nxc + P - 1) / P; ++bx)
-                    g.tasks.push_back(make_int4(i, bx, ky_of_slot(y, I.ny), 0));
+                    for (int h = 0; h < 2; ++h) g.tasks.push_back(make_int4(i, bx, ky_of_slot(2 * m + h, I.ny), 0));
             break;
         case MM_PASS_YCONV:
             for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));

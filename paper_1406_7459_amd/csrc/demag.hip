@@ -7,6 +7,26 @@
 
 namespace mmk {
 
+// Tile and plane (or mirror-paired ky row) of this workgroup for the column
+// passes, through the XCD mapping: logical order is kx tile fastest, so
+// neighbouring tiles of one row share their L2; in the z pass the two ky
+// rows of a mirror pair (one K~ octant row) come first, then the tile.
+__device__ __forceinline__ void column_coords(int &bx, int &plane)
+{
+    const unsigned nt = gridDim.x, nb = nt * gridDim.y;
+    const unsigned l = xcd_block(blockIdx.y * nt + blockIdx.x, nb);
+    bx = (int)(l % nt);
+    plane = (int)(l / nt);
+}
+__device__ __forceinline__ void conv_coords(int ny, int &bx, int &ky)
+{
+    const unsigned nt = gridDim.x, nb = nt * gridDim.y;  // gridDim.y = 2 ny slots
+    const unsigned l = xcd_block(blockIdx.y * nt + blockIdx.x, nb);
+    const unsigned r = l >> 1;
+    bx = (int)(r % nt);
+    ky = ky_of_slot((int)(2 * (r / nt) + (l & 1)), ny);
+}
+
 // Per-plan kernels: one launch covers one pass of one grid.
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_xfwd(const float *__restrict__ M, float2 *__restrict__ X1, int nrows,
@@ -18,26 +38,36 @@ template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yfwd(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc,
                                                int lp2, const float2 *__restrict__ tw)
 {
-    yfwd_body<L, V>(X1, X2, nxc, lp2, tw, blockIdx.x, blockIdx.y);
+    int bx, plane;
+    column_coords(bx, plane);
+    yfwd_body<L, V>(X1, X2, nxc, lp2, tw, bx, plane);
 }
 template <int L, bool ZAXIS>
 __global__ __launch_bounds__(conv_max_threads<L>()) void k_conv_reg3(float2 *__restrict__ X,
                                                                       const float *__restrict__ Kt, int nxc, int ny,
                                                                       int lp2, const float2 *__restrict__ tw)
 {
-    conv_reg3_body<L, ZAXIS>(X, Kt, nxc, ny, lp2, tw, blockIdx.x, ZAXIS ? ky_of_slot(blockIdx.y, ny) : 0);
+    int bx, ky = 0;
+    if constexpr (ZAXIS) conv_coords(ny, bx, ky);
+    else bx = (int)xcd_block(blockIdx.x, gridDim.x);
+    conv_reg3_body<L, ZAXIS>(X, Kt, nxc, ny, lp2, tw, bx, ky);
 }
 template <int L, int V, bool ZAXIS>
 __global__ __launch_bounds__(1024) void k_conv_split(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc,
                                                       int ny, int lp2, const float2 *__restrict__ tw)
 {
-    conv_split_body<L, V, ZAXIS>(X, Kt, nxc, ny, lp2, tw, blockIdx.x, ZAXIS ? ky_of_slot(blockIdx.y, ny) : 0);
+    int bx, ky = 0;
+    if constexpr (ZAXIS) conv_coords(ny, bx, ky);
+    else bx = (int)xcd_block(blockIdx.x, gridDim.x);
+    conv_split_body<L, V, ZAXIS>(X, Kt, nxc, ny, lp2, tw, bx, ky);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yinv(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc,
                                                int lp2, const float2 *__restrict__ tw)
 {
-    yinv_body<L, V>(X2, X1, nxc, lp2, tw, blockIdx.x, blockIdx.y);
+    int bx, plane;
+    column_coords(bx, plane);
+    yinv_body<L, V>(X2, X1, nxc, lp2, tw, bx, plane);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_xinv(const float2 *__restrict__ X1, float *__restrict__ H, int nrows,

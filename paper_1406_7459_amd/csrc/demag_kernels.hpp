@@ -15,7 +15,7 @@
 //          z inverse, rows k < nz written back
 //   YINV   X2 -> X1                                               y: keep j < ny
 //   XINV   X1 -> H [3][nz][ny][nx] f32                            x: C2R, keep i < nx
-// (xp = x_pitch(nx + 1): rows of nx + 1 values padded to 64 bytes; the
+// (xp = x_pitch(nx + 1): rows of nx + 1 values padded to 128 bytes; the
 // padding is never read or written.)
 // For nz = 1 the padded z axis has length 2 with the second slot zero, so the
 // z transform is the identity up to a factor folded into K~; YCONV then does

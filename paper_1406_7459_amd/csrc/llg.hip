@@ -11,21 +11,12 @@
 
 namespace mmk {
 
-// Blocks are dealt round-robin to the 8 XCDs; remap so that each XCD walks
-// a contiguous slab of cells and its own L2 keeps the y/z neighbour planes.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
-{
-    const unsigned per = nb / 8u;
-    if (per == 0u || b >= per * 8u) return b;
-    return (b % 8u) * per + b / 8u;
-}
-
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_stage(const float *S, const float *__restrict__ Hd, const float *Mn,
                                                float *__restrict__ kacc, float *out, int nx, int ny, int nz,
                                                StageCoef c)
 {
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);  // each XCD a slab of cells
     stage_body<STAGE>(S, Hd, Mn, kacc, out, nx, ny, nz, c, (size_t)b * blockDim.x + threadIdx.x);
 }
 
