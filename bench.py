@@ -54,9 +54,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources; else None."""
+def read_traffic(workload, kernel, tile):
+    """HBM bytes per launch of pass `kernel` with launch configuration `tile`
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
     if not os.path.exists(path):
         return None
@@ -67,8 +68,109 @@ def read_traffic(workload, kernel):
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_hash") != kernel_source_hash():
         return None
-    v = kv.get("hbm_bytes_per_launch.%s" % kernel)
+    v = kv.get("hbm_bytes_per_launch.%s.%d" % (kernel, tile))
     return float(v) if v else None
+
+
+def summarize_traffic(workload, pmc_dir):
+    """Text of profiles/traffic_<workload>.txt from four rocprofv3 --pmc
+    databases under pmc_dir: sweep_FETCH_SIZE, sweep_WRITE_SIZE (bench.py
+    --sweep-tiles) and copy_FETCH_SIZE, copy_WRITE_SIZE (--calibrate-copy).
+    Each counter is scaled by what it reads for the 512 MiB copy; per pass
+    and tile the median over that configuration's dispatches is kept."""
+    import glob
+    import re
+    import sqlite3
+    import statistics
+    from paper_1406_7459_amd import workloads as W
+
+    def load(kind, counter):
+        db = glob.glob(os.path.join(pmc_dir, "%s_%s" % (kind, counter), "*.db"))[0]
+        con = sqlite3.connect(db)
+        per = {}
+        for disp, kname, gx, wx, v in con.execute(
+                "select dispatch_id, kernel_name, grid_size_x, workgroup_size_x, value "
+                "from counters_collection where counter_name = ?", (counter,)):
+            e = per.setdefault(disp, [kname, gx, wx, 0.0])
+            e[3] += v
+        return per
+
+    copy_bytes = 512 * 1024 * 1024
+    scale = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals = [e[3] for e in load("copy", c).values() if "MulFunctor" in e[0]]
+        scale[c] = copy_bytes / (1024.0 * statistics.median(vals))
+    wl = W.cube(int(workload[4:])) if workload.startswith("cube") else getattr(W, workload)()
+    nx, ny, nz = wl.shape
+    nxc, pairs = nx + 1, (3 * nz * ny + 1) // 2
+
+    def p2(x):
+        p = 1
+        while p < x:
+            p *= 2
+        return p
+
+    def config(kname, gx, wx):
+        blocks = max(1, gx // max(1, wx))
+        lens = {"xfwd": 2 * nx, "xinv": 2 * nx, "yfwd": 2 * ny, "yinv": 2 * ny, "yconv": 2 * ny, "zconv": 2 * nz}
+        m = re.search(r"mmk::k_(xfwd|yfwd|yinv|xinv)<(\d+), (\d+)>", kname)
+        if m and int(m.group(2)) != lens[m.group(1)]:
+            return None
+        if m:
+            rows = m.group(1) in ("xfwd", "xinv")
+            P = p2(-(-pairs // blocks)) if rows else p2(-(-nxc // blocks))
+            return m.group(1), P + 256 * int(m.group(3))
+        m = re.search(r"mmk::k_conv_reg3<(\d+), (true|false)>", kname)
+        if m and int(m.group(1)) != lens["zconv" if m.group(2) == "true" else "yconv"]:
+            return None
+        if m:
+            return ("zconv" if m.group(2) == "true" else "yconv"), p2(-(-nxc // blocks))
+        m = re.search(r"mmk::k_conv_split<(\d+), (\d+), (true|false)>", kname)
+        if m and int(m.group(1)) != lens["zconv" if m.group(3) == "true" else "yconv"]:
+            return None
+        if m:
+            return ("zconv" if m.group(3) == "true" else "yconv"), p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2)))
+        m = re.search(r"mmk::k_stage<([1-4])>", kname)
+        if m:
+            return "stage", int(m.group(1))
+        return None
+
+    acc = {}
+    for c in ("FETCH_SIZE", "WRITE_SIZE"):
+        for kname, gx, wx, v in load("sweep", c).values():
+            key = config(kname, gx, wx)
+            if key:
+                acc.setdefault(key, {}).setdefault(c, []).append(v * 1024.0 * scale[c])
+    alg = pass_bytes(nx, ny, nz)
+    out = ["# HBM traffic per launch, %s (%dx%dx%d cells), rocprofv3 hardware counters" % (workload, nx, ny, nz),
+           "# commands (from /tmp on the GPU, REPO = repository root):",
+           "#   rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/pmc/sweep_FETCH_SIZE -o sweep -- python3 $REPO/bench.py --sweep-tiles",
+           "#   rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/pmc/sweep_WRITE_SIZE -o sweep -- python3 $REPO/bench.py --sweep-tiles",
+           "#   rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/pmc/copy_FETCH_SIZE -o copy -- python3 $REPO/bench.py --calibrate-copy",
+           "#   rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/pmc/copy_WRITE_SIZE -o copy -- python3 $REPO/bench.py --calibrate-copy",
+           "#   python3 bench.py --summarize-traffic %s $REPO/gpurun_out/pmc" % workload,
+           "# scale: a 512 MiB copy (512 MiB read + 512 MiB written) reads back FETCH_SIZE x%.4f, WRITE_SIZE x%.4f"
+           % (scale["FETCH_SIZE"], scale["WRITE_SIZE"]),
+           "# per pass and tile (P + 256 * variant): median fetch / write bytes per launch; stage: mean of RK4 stages 1-4",
+           "kernel_source_hash: %s" % kernel_source_hash()]
+    stage = []
+    for (pname, tile) in sorted(acc):
+        d = acc[(pname, tile)]
+        if "FETCH_SIZE" not in d or "WRITE_SIZE" not in d:
+            continue
+        f, w = statistics.median(d["FETCH_SIZE"]), statistics.median(d["WRITE_SIZE"])
+        if pname == "stage":
+            stage.append(f + w)
+            continue
+        a = alg.get(pname)
+        out.append("# %-6s tile %4d: fetch %11.0f write %11.0f  (x%.2f of algorithmic %d)"
+                   % (pname, tile, f, w, (f + w) / a if a else 0.0, a or 0))
+        out.append("hbm_bytes_per_launch.%s.%d: %.0f" % (pname, tile, f + w))
+    if stage:
+        out.append("# stage  RK4 stages 1-4 mean: %.0f (x%.2f of algorithmic %d)"
+                   % (sum(stage) / len(stage), sum(stage) / len(stage) / alg["stage"], alg["stage"]))
+        out.append("hbm_bytes_per_launch.stage.0: %.0f" % (sum(stage) / len(stage)))
+    return "\n".join(out) + "\n"
 
 
 def cpu_baseline(budget_s=30.0):
@@ -188,12 +290,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("WORKLOAD", "PMC_DIR"),
+                    help="print the traffic summary of rocprofv3 counter databases and exit")
+    ap.add_argument("--sweep-tiles", action="store_true",
+                    help="run only five demag evaluations with every valid tile of every pass "
+                         "(for per-tile hardware counters)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain elementwise copy of 512 MiB (known traffic) for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        sys.stdout.write(summarize_traffic(*args.summarize_traffic))
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (got --gpus %d)"
+        print("bench.py measures one GPU; the library has no multi-GPU path (got --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -227,6 +337,30 @@ def main():
     t0 = time.perf_counter()
     plan = mm.Plan(nx, ny, nz, *wl.cell)
     setup_s = time.perf_counter() - t0
+    if args.sweep_tiles:
+        Mw = torch.from_numpy((m.Ms * wl.initial_unit()).astype("float32")).cuda()
+        Hw = torch.empty_like(Mw)
+        dflt = plan.info()["tiles"]
+        done = []
+        for pname in ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv"):
+            if not dflt.get(pname):
+                continue
+            for tile in [P + 256 * v for v in (0, 1, 2) for P in (1, 2, 4, 8, 16, 32, 64, 128)]:
+                try:
+                    plan.set_tile(pname, tile)
+                except mm.MMError:
+                    continue
+                for _ in range(5):
+                    plan.demag(Mw, Hw)
+                done.append("%s.%d" % (pname, tile))
+            plan.set_tile(pname, dflt[pname])
+        pw = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha,
+                               gamma0=m.gamma0, Hext=m.Hext, dt=m.dt)
+        for _ in range(3):
+            plan.step(pw, Mw, 1)  # the four RK4 stage kernels, launched directly
+        torch.cuda.synchronize()
+        print(json.dumps({"sweep": name, "tiles": done}))
+        return
     tiles = plan.autotune(reps=5) if not args.no_autotune else plan.info()["tiles"]
     params = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha,
                                gamma0=m.gamma0, Hext=m.Hext, dt=m.dt)
@@ -285,7 +419,7 @@ def main():
                            gbs=(bytes_per.get(k, 0) / (ms / n * 1e-3) / 1e9) if k in bytes_per else None)
     dom = max((k for k in kern if k in bytes_per), key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     ach = kern[dom]["gbs"]
-    traffic = read_traffic(name, dom)
+    traffic = read_traffic(name, dom, tiles[dom])
     err, nobs = oracle_error_sample(plan, wl, torch)
     cells = nx * ny * nz
     out = {

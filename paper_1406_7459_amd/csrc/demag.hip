@@ -157,12 +157,12 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
         if (var == 0) {
             threads = P * (L / k.E0);
             maxt = k.conv_max;
-            lds = (tws + (k.nstage > 1 ? (size_t)L * (P + 1) : 0)) * sizeof(float2);
+            lds = (tws + (k.nstage > 1 ? (size_t)lds_rows(L) * P : 0)) * sizeof(float2);
         } else if (var == 1 || var == 2) {
             const int E = var == 1 ? k.E0 : k.E1;
             if (var == 2 && k.E1 == k.E0) return false;
             threads = 3 * P * (L / E);
-            lds = (tws + 3 * (size_t)L * (P + 1)) * sizeof(float2);
+            lds = (tws + 3 * (size_t)lds_rows(L) * P) * sizeof(float2);
         } else {
             return false;
         }
@@ -173,7 +173,8 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
         threads = P * (L / E);
         // the x forward separates its packed rows through LDS even for one stage
         const bool needs = k.nstage > 1 || pass == MM_PASS_XFWD;
-        lds = (tws + (needs ? (is_rows(pass) ? (size_t)P * (L + 1) : (size_t)L * (P + 1)) : 0)) * sizeof(float2);
+        lds = (tws + (needs ? (is_rows(pass) ? (size_t)P * (lds_rows(L) + 1) : (size_t)lds_rows(L) * P) : 0)) *
+              sizeof(float2);
     }
     return true;
 }

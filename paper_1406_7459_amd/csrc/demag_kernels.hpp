@@ -72,8 +72,9 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
     const int q = t % Q, p = t / Q;
     const int ra = ((bx << lp2) + p) * 2, rb = ra + 1;
     const bool oka = ra < nrows, okb = rb < nrows;
-    float2 *col = lds + tw_slots<L>() + p * (L + 1);
-    const LdsView s{lds + tw_slots<L>(), 1, p * (L + 1)};
+    constexpr int XS = lds_rows(L) + 1;  // slots per transform (odd)
+    float2 *col = lds + tw_slots<L>() + p * XS;
+    const LdsView s{lds + tw_slots<L>(), 1, p * XS};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
     const float *sa = M + (size_t)ra * NX;
@@ -93,7 +94,7 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-        for (int r = 0; r < RL; ++r) col[q + Q * b + r * (L / RL)] = v[b * RL + r];
+        for (int r = 0; r < RL; ++r) col[lds_slot(q + Q * b + r * (L / RL))] = v[b * RL + r];
     __syncthreads();
     float2 *da = X1 + (size_t)ra * XP;
     float2 *db = X1 + (size_t)rb * XP;
@@ -104,7 +105,7 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
             const int k = q + Q * b + r * (L / RL);
             if (k <= NX) {
                 const float2 z = v[b * RL + r];
-                const float2 w = col[k == 0 ? 0 : L - k];
+                const float2 w = col[lds_slot(k == 0 ? 0 : L - k)];
                 const float2 sp = make_float2(z.x + w.x, z.y - w.y);  // Z + conj(Zm)
                 const float2 sm = make_float2(z.x - w.x, z.y + w.y);  // Z - conj(Zm)
                 if (oka) da[k] = make_float2(0.5f * sp.x, 0.5f * sp.y);
@@ -127,7 +128,7 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
     const int xp = x_pitch(nxc);
-    const LdsView s{lds + tw_slots<L>(), P + 1, p};
+    const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
     const float2 *src = X1 + (size_t)plane * NY * xp + kx;
@@ -200,7 +201,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
     const int xp = x_pitch(nxc);
-    const LdsView s{lds + tw_slots<L>(), P + 1, p};
+    const LdsView s{lds + tw_slots<L>(), P, p};
     const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;  // stride along the transform
     const size_t cs = (size_t)NH * rs;                            // component stride
     float2 *base = X + (size_t)ky * xp + kx;
@@ -213,10 +214,12 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             const int k = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NH;
             const bool ld = !upper && ok && k < NH;
-            const float2 z = make_float2(0.f, 0.f);
-            va[b * R0 + r] = ld ? base[k * rs] : z;
-            vb[b * R0 + r] = ld ? base[cs + k * rs] : z;
-            vc[b * R0 + r] = ld ? base[2 * cs + k * rs] : z;
+            // (values, not lvalues, on both sides: a select between two
+            // lvalues of class type would become a flat load through a
+            // selected pointer to either global or private memory)
+            va[b * R0 + r] = ld ? float2(base[k * rs]) : make_float2(0.f, 0.f);
+            vb[b * R0 + r] = ld ? float2(base[cs + k * rs]) : make_float2(0.f, 0.f);
+            vc[b * R0 + r] = ld ? float2(base[2 * cs + k * rs]) : make_float2(0.f, 0.f);
         }
     fft<L, -1, false>(va, s, q, twl);
     fft<L, -1, false>(vb, s, q, twl);
@@ -246,6 +249,10 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             }
         }
 
+    // Keep the inverse transforms from being interleaved with the product:
+    // mixing them lifts the register peak from ~106 to ~134 VGPRs at L = 256
+    // (three waves per SIMD instead of four).
+    __builtin_amdgcn_sched_barrier(0);
     fft<L, +1, true>(va, s, q, twl);
     fft<L, +1, true>(vb, s, q, twl);
     fft<L, +1, true>(vc, s, q, twl);
@@ -284,9 +291,9 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
     const int xp = x_pitch(nxc);
-    const int rsl = P + 1;
+    constexpr int GS = lds_rows(L);  // slots per component group
     float2 *buf = lds + tw_slots<L>();
-    const LdsView s{buf + (size_t)g * L * rsl, rsl, p};
+    const LdsView s{buf + (size_t)g * GS * P, P, p};
     const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;
     const size_t cs = (size_t)NH * rs;
     float2 *base = X + (size_t)g * cs + (size_t)ky * xp + kx;
@@ -308,7 +315,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int k = q + Q * b + r * (L / RL);
-            buf[((size_t)g * L + k) * rsl + p] = v[b * RL + r];
+            buf[((size_t)g * GS + lds_slot(k)) * P + p] = v[b * RL + r];
         }
     __syncthreads();
     // this group's row of the symmetric tensor: (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
@@ -333,9 +340,10 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
             const float w2 = g == 0 ? sxz : (g == 1 ? syz : 1.f);
             const float *K = Kb + 6 * (ZAXIS ? (size_t)kf * nyk * xp : (size_t)kf * xp);
             const float k0 = w0 * K[c0], k1 = w1 * K[c1], k2 = w2 * K[c2];
-            const float2 m0 = buf[((size_t)0 * L + k) * rsl + p];
-            const float2 m1 = buf[((size_t)1 * L + k) * rsl + p];
-            const float2 m2 = buf[((size_t)2 * L + k) * rsl + p];
+            const int ks = lds_slot(k) * P + p;
+            const float2 m0 = buf[ks];
+            const float2 m1 = buf[(size_t)GS * P + ks];
+            const float2 m2 = buf[(size_t)2 * GS * P + ks];
             v[b * RL + r] = krow(k0, k1, k2, m0, m1, m2);
         }
     __syncthreads();  // every product read is done before the inverse reuses LDS
@@ -364,7 +372,7 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
     const int xp = x_pitch(nxc);
-    const LdsView s{lds + tw_slots<L>(), P + 1, p};
+    const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
     const float2 *src = X2 + (size_t)plane * L * xp + kx;
@@ -402,7 +410,7 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
     const int q = t % Q, p = t / Q;
     const int ra = ((bx << lp2) + p) * 2, rb = ra + 1;
     const bool oka = ra < nrows, okb = rb < nrows;
-    const LdsView s{lds + tw_slots<L>(), 1, p * (L + 1)};
+    const LdsView s{lds + tw_slots<L>(), 1, p * (lds_rows(L) + 1)};
     const float2 *sa = X1 + (size_t)ra * XP;
     const float2 *sb = X1 + (size_t)rb * XP;
     float2 v[E];

@@ -150,12 +150,20 @@ __device__ __host__ constexpr int first_radix() { return radix_at<L, REV>(0); }
 template <int L, bool REV>
 __device__ __host__ constexpr int last_radix() { return radix_at<L, REV>(Factors<L>::N - 1); }
 
-// LDS view of a tile of transforms: element (row, col) at
-// base[row * rs + col * cs].
+// LDS rows are padded: row r of a transform sits in slot r + r/8 (one spare
+// slot after every 8 rows).  The exchanges write with lane strides of R*NS
+// rows and read with stride 1; without the spare slots the strided writes
+// fall into a few banks.  A transform of L rows takes lds_rows(L) slots.
+__host__ __device__ constexpr int lds_rows(int L) { return L + L / 8; }
+__device__ __forceinline__ int lds_slot(int r) { return r + (r >> 3); }
+
+// LDS view of a tile of transforms: slot s of this thread's transform at
+// base[s * rs + co].
 struct LdsView {
     float2 *base;
-    int rs;  // stride between rows of one transform
-    int co;  // this thread's column offset (col * cs), precomputed
+    int rs;  // stride between slots of one transform
+    int co;  // this thread's offset (its transform's column or start)
+    __device__ __forceinline__ float2 &at(int slot) const { return base[slot * rs + co]; }
 };
 
 // -------------------------------------------------------------- stages ---
@@ -183,6 +191,10 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[E], int q, const float
 // Write the outputs of a stage (radix R, NS) to LDS, then read the inputs
 // of the next stage (radix R2).  Two barriers: the second keeps the next
 // exchange's writes from overtaking this exchange's reads.
+// Where a thread's rows are base + c with c a compile-time offset that never
+// carries base into the next group of 8 (c a multiple of 8, or base a
+// multiple of R with c < R | 8), slot(base + c) = slot(base) + slot(c) and
+// the per-access offsets fold into the LDS instructions.
 template <int L, int E, int R, int NS, int R2>
 __device__ __forceinline__ void exchange(float2 (&v)[E], const LdsView &s, int q)
 {
@@ -191,14 +203,28 @@ __device__ __forceinline__ void exchange(float2 (&v)[E], const LdsView &s, int q
     for (int b = 0; b < E / R; ++b) {
         const int j = q + Q * b;
         const int row = (j / NS) * NS * R + (j % NS);
+        if constexpr (NS % 8 == 0 || (NS == 1 && 8 % R == 0)) {
+            const int sb = lds_slot(row);
 #pragma unroll
-        for (int r = 0; r < R; ++r) s.base[(row + r * NS) * s.rs + s.co] = v[b * R + r];
+            for (int r = 0; r < R; ++r) s.at(sb + r * NS + ((r * NS) >> 3)) = v[b * R + r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) s.at(lds_slot(row + r * NS)) = v[b * R + r];
+        }
     }
     __syncthreads();
+    constexpr int ST = L / R2;
 #pragma unroll
     for (int b = 0; b < E / R2; ++b) {
+        const int row = q + Q * b;
+        if constexpr (ST % 8 == 0) {
+            const int sb = lds_slot(row);
 #pragma unroll
-        for (int r = 0; r < R2; ++r) v[b * R2 + r] = s.base[(q + Q * b + r * (L / R2)) * s.rs + s.co];
+            for (int r = 0; r < R2; ++r) v[b * R2 + r] = s.at(sb + r * ST + ((r * ST) >> 3));
+        } else {
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[b * R2 + r] = s.at(lds_slot(row + r * ST));
+        }
     }
     __syncthreads();
 }

@@ -40,7 +40,8 @@ def main(argv=None):
     ap.add_argument("--seconds", type=float, default=120.0, help="training time budget")
     ap.add_argument("--pairs", type=int, default=20000, help="training pairs at most")
     ap.add_argument("--per-traj", type=int, default=100)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4,
+                    help="initial Adam step; decays tenfold over the budget (1e-3 diverged after ~2000 pairs)")
     ap.add_argument("--eval-steps", type=int, default=40)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--out", default=None)
@@ -65,6 +66,8 @@ def main(argv=None):
     # ---- training on solver pairs
     t0 = time.perf_counter()
     losses = []
+    tvar = []   # mean square of the normalised target (the loss of a zero network)
+    curve = []
     pairs = 0
     traj = 0
     dm = torch.empty((3, nz, ny, nx), device="cuda")
@@ -76,9 +79,16 @@ def main(argv=None):
         plan.step(p, M, 20)
         for _ in range(args.per_traj):
             mm.Surrogate.make_pair(plan, p, M, 1, dm, dh)
-            lr = args.lr * (0.1 ** (pairs / max(1, args.pairs)))
+            frac = max(pairs / max(1, args.pairs), (time.perf_counter() - t0) / args.seconds)
+            lr = args.lr * (0.1 ** min(1.0, frac))
             losses.append(sur.train_step(dm, dh, lr))
+            tvar.append(float((dh.pow(2).mean() / dm.pow(2).mean()).item()))
             pairs += 1
+            if pairs % 250 == 0:
+                curve.append({"pairs": pairs, "loss": float(np.mean(losses[-250:])),
+                              "zero_net_loss": float(np.mean(tvar[-250:])), "s": time.perf_counter() - t0})
+                print("pairs %d loss %.5f zero-net %.5f" % (pairs, curve[-1]["loss"], curve[-1]["zero_net_loss"]),
+                      file=sys.stderr, flush=True)
             if pairs >= args.pairs or time.perf_counter() - t0 >= args.seconds:
                 break
         traj += 1
@@ -146,6 +156,7 @@ def main(argv=None):
         "pairs": pairs, "trajectories": traj, "train_s": train_s,
         "loss_first": float(np.mean(losses[:20])) if losses else None,
         "loss_last": float(np.mean(losses[-20:])) if losses else None,
+        "curve": curve,
         "tol": args.tol, "eval_steps": args.eval_steps, "eval": evals,
         "inference_ms": inf_ms, "exact_demag_ms": demag_ms,
         "speedup_vs_plain_fp32": (np.mean([e["exact_ms_per_step"] for e in evals])

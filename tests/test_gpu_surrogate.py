@@ -125,3 +125,46 @@ def test_gate_at_zero_tolerance_is_the_exact_path():
     st2 = sur.step(plan, p, c, 6, tol=-1.0)
     assert st2["fallbacks"] == 0 and st2["checked"] == 6 and np.isfinite(st2["max_residual"])
     assert np.isfinite(to_host(c)).all()
+
+
+def test_trained_network_beats_no_network_at_the_gate():
+    """Train online on solver pairs of a 64x64x4 film (a few hundred Adam
+    steps), then step a held-out trajectory through the gate: the residual of
+    the trained network's field at every accepted state is a fraction of the
+    residual with no network (the stage-1 field reused), and its accepted
+    state stays close to the exact path's."""
+    from paper_1406_7459_amd import mm
+    from paper_1406_7459_amd.surrogate_train import init_params
+    nx, ny, nz = 64, 64, 4
+    d = (4e-9, 4e-9, 4e-9)
+    plan = mm.Plan(nx, ny, nz, *d)
+    sur = mm.Surrogate(nx, ny, nz)
+    sur.set_params(init_params(6, 5000))
+    p = mm.LLGParams.make(Ms=8e5, A=1.3e-11, alpha=0.1, dt=1e-14, Hext=(2e4, 1e4, 0))
+    dm = torch.empty((3, nz, ny, nx), device="cuda")
+    dh = torch.empty_like(dm)
+    losses = []
+    for traj in range(6):
+        M = to_dev(8e5 * W.random_unit(nx, ny, nz, 300 + traj))
+        plan.step(p, M, 20)
+        for _ in range(100):
+            mm.Surrogate.make_pair(plan, p, M, 1, dm, dh)
+            losses.append(sur.train_step(dm, dh, 3e-4))
+    trained = sur.get_params()
+    M0 = to_dev(8e5 * W.random_unit(nx, ny, nz, 399))
+    plan.step(p, M0, 20)
+    exact = M0.clone()
+    plan.step(p, exact, 10)
+    a = M0.clone()
+    st_t = sur.step(plan, p, a, 10, tol=-1.0)  # never fall back: judge every step
+    sur.zero()
+    b = M0.clone()
+    st_z = sur.step(plan, p, b, 10, tol=-1.0)
+    sur.set_params(trained)
+    say("loss first", np.mean(losses[:20]), "last", np.mean(losses[-20:]),
+        "residual trained", st_t["mean_residual"], "no network", st_z["mean_residual"],
+        "state err trained", rel_l2(to_host(a), to_host(exact)), "no network", rel_l2(to_host(b), to_host(exact)))
+    assert np.mean(losses[-20:]) < 0.1 * np.mean(losses[:20])
+    assert st_t["checked"] == 10 and st_z["checked"] == 10
+    assert st_t["mean_residual"] < 0.3 * st_z["mean_residual"]
+    assert rel_l2(to_host(a), to_host(exact)) < rel_l2(to_host(b), to_host(exact))
