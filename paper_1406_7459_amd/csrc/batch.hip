@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void kb_stage(const BInst *__restrict__ B, con
     const int2 t = T[blockIdx.x];
     const BInst &I = B[t.x];
     stage_body<STAGE>(bsel(I, ssel), I.H, I.M, I.kacc, bsel(I, osel), I.nx, I.ny, I.nz, I.c,
-                      (size_t)t.y * 256 + threadIdx.x);
+                      (unsigned)t.y * 256u + threadIdx.x);
 }
 // Euler: the new state, written to Sa, becomes M
 __global__ __launch_bounds__(256) void kb_copy(const BInst *__restrict__ B, const int2 *__restrict__ T)

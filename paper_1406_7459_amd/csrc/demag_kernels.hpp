@@ -131,25 +131,26 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
     const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
-    const float2 *src = X1 + (size_t)plane * NY * xp + kx;
+    // this thread's row q; the other rows are compile-time multiples of the
+    // (uniform) row pitch away
+    const float2 *src = X1 + ((size_t)plane * NY + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int j = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NY;
-            v[b * R0 + r] = (!upper && ok && j < NY) ? src[(size_t)j * xp] : make_float2(0.f, 0.f);
+            v[b * R0 + r] = (!upper && ok && j < NY) ? float2(src[(size_t)(Q * b + r * (L / R0)) * xp])
+                                                     : make_float2(0.f, 0.f);
         }
     fft_e<L, E, -1, false>(v, s, q, twl);
     constexpr int RL = last_radix<L, false>();
-    float2 *dst = X2 + (size_t)plane * L * xp + kx;
+    float2 *dst = X2 + ((size_t)plane * L + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
-        for (int r = 0; r < RL; ++r) {
-            const int k = q + Q * b + r * (L / RL);
-            if (ok) dst[(size_t)k * xp] = v[b * RL + r];
-        }
+        for (int r = 0; r < RL; ++r)
+            if (ok) dst[(size_t)(Q * b + r * (L / RL)) * xp] = v[b * RL + r];
 }
 
 // One row of the product, k0 m0 + k1 m1 + k2 m2, in a fixed operation order
@@ -204,7 +205,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const LdsView s{lds + tw_slots<L>(), P, p};
     const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;  // stride along the transform
     const size_t cs = (size_t)NH * rs;                            // component stride
-    float2 *base = X + (size_t)ky * xp + kx;
+    float2 *base = X + (size_t)ky * xp + kx + (size_t)q * rs;  // this thread's row q
     float2 va[E], vb[E], vc[E];
     constexpr int R0 = first_radix<L, false>();
 #pragma unroll
@@ -212,14 +213,15 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k = q + Q * b + r * (L / R0);
+            const size_t o = (size_t)(Q * b + r * (L / R0)) * rs;  // uniform
             const bool upper = r * (L / R0) >= NH;
             const bool ld = !upper && ok && k < NH;
             // (values, not lvalues, on both sides: a select between two
             // lvalues of class type would become a flat load through a
             // selected pointer to either global or private memory)
-            va[b * R0 + r] = ld ? float2(base[k * rs]) : make_float2(0.f, 0.f);
-            vb[b * R0 + r] = ld ? float2(base[cs + k * rs]) : make_float2(0.f, 0.f);
-            vc[b * R0 + r] = ld ? float2(base[2 * cs + k * rs]) : make_float2(0.f, 0.f);
+            va[b * R0 + r] = ld ? float2(base[o]) : make_float2(0.f, 0.f);
+            vb[b * R0 + r] = ld ? float2(base[cs + o]) : make_float2(0.f, 0.f);
+            vc[b * R0 + r] = ld ? float2(base[2 * cs + o]) : make_float2(0.f, 0.f);
         }
     fft<L, -1, false>(va, s, q, twl);
     fft<L, -1, false>(vb, s, q, twl);
@@ -240,7 +242,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             const int kf = k <= NH ? k : L - k;
             const float sk = k <= NH ? 1.f : -1.f;
             const int i = b * RL + r;
-            const float2 *K = Kb + 3 * (ZAXIS ? (size_t)kf * nyk * xp : (size_t)kf * xp);
+            const float2 *K = Kb + 3u * __umul24((unsigned)kf, ZAXIS ? (unsigned)(nyk * xp) : (unsigned)xp);
             const float2 k01 = K[0], k23 = K[1], k45 = K[2];
             if constexpr (ZAXIS) {
                 kdot(va[i], vb[i], vc[i], k01.x, k01.y, k23.x, sy0 * k23.y, sk * k45.x, sy0 * sk * k45.y);
@@ -262,11 +264,12 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int k = q + Q * b + r * (L / R0);
+            const size_t o = (size_t)(Q * b + r * (L / R0)) * rs;
             const bool upper = r * (L / R0) >= NH;
             if (!upper && ok && k < NH) {
-                base[k * rs] = va[b * R0 + r];
-                base[cs + k * rs] = vb[b * R0 + r];
-                base[2 * cs + k * rs] = vc[b * R0 + r];
+                base[o] = va[b * R0 + r];
+                base[cs + o] = vb[b * R0 + r];
+                base[2 * cs + o] = vc[b * R0 + r];
             }
         }
 }
@@ -296,7 +299,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     const LdsView s{buf + (size_t)g * GS * P, P, p};
     const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;
     const size_t cs = (size_t)NH * rs;
-    float2 *base = X + (size_t)g * cs + (size_t)ky * xp + kx;
+    float2 *base = X + (size_t)g * cs + (size_t)ky * xp + kx + (size_t)q * rs;
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
 #pragma unroll
@@ -305,7 +308,8 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
         for (int r = 0; r < R0; ++r) {
             const int k = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NH;
-            v[b * R0 + r] = (!upper && ok && k < NH) ? base[k * rs] : make_float2(0.f, 0.f);
+            v[b * R0 + r] = (!upper && ok && k < NH) ? float2(base[(size_t)(Q * b + r * (L / R0)) * rs])
+                                                     : make_float2(0.f, 0.f);
         }
     fft_e<L, E, -1, false>(v, s, q, twl);
 
@@ -338,7 +342,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
             const float w0 = g == 0 ? 1.f : (g == 1 ? sxy : sxz);
             const float w1 = g == 0 ? sxy : (g == 1 ? 1.f : syz);
             const float w2 = g == 0 ? sxz : (g == 1 ? syz : 1.f);
-            const float *K = Kb + 6 * (ZAXIS ? (size_t)kf * nyk * xp : (size_t)kf * xp);
+            const float *K = Kb + 6u * __umul24((unsigned)kf, ZAXIS ? (unsigned)(nyk * xp) : (unsigned)xp);
             const float k0 = w0 * K[c0], k1 = w1 * K[c1], k2 = w2 * K[c2];
             const int ks = lds_slot(k) * P + p;
             const float2 m0 = buf[ks];
@@ -354,7 +358,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
         for (int r = 0; r < R0; ++r) {
             const int k = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NH;
-            if (!upper && ok && k < NH) base[k * rs] = v[b * R0 + r];
+            if (!upper && ok && k < NH) base[(size_t)(Q * b + r * (L / R0)) * rs] = v[b * R0 + r];
         }
 }
 
@@ -375,24 +379,22 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
     const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
-    const float2 *src = X2 + (size_t)plane * L * xp + kx;
+    const float2 *src = X2 + ((size_t)plane * L + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            const int k = q + Q * b + r * (L / R0);
-            v[b * R0 + r] = ok ? src[(size_t)k * xp] : make_float2(0.f, 0.f);
-        }
+        for (int r = 0; r < R0; ++r)
+            v[b * R0 + r] = ok ? float2(src[(size_t)(Q * b + r * (L / R0)) * xp]) : make_float2(0.f, 0.f);
     fft_e<L, E, +1, false>(v, s, q, twl);
     constexpr int RL = last_radix<L, false>();
-    float2 *dst = X1 + (size_t)plane * NY * xp + kx;
+    float2 *dst = X1 + ((size_t)plane * NY + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int j = q + Q * b + r * (L / RL);
             const bool upper = r * (L / RL) >= NY;
-            if (!upper && ok && j < NY) dst[(size_t)j * xp] = v[b * RL + r];
+            if (!upper && ok && j < NY) dst[(size_t)(Q * b + r * (L / RL)) * xp] = v[b * RL + r];
         }
 }
 

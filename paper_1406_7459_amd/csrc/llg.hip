@@ -17,7 +17,7 @@ __global__ __launch_bounds__(256) void k_stage(const float *S, const float *__re
                                                StageCoef c)
 {
     const unsigned b = xcd_block(blockIdx.x, gridDim.x);  // each XCD a slab of cells
-    stage_body<STAGE>(S, Hd, Mn, kacc, out, nx, ny, nz, c, (size_t)b * blockDim.x + threadIdx.x);
+    stage_body<STAGE>(S, Hd, Mn, kacc, out, nx, ny, nz, c, b * blockDim.x + threadIdx.x);
 }
 
 StageCoef stage_coef(const Plan &p, const mm_llg_params &q)
