@@ -72,6 +72,91 @@ def read_traffic(workload, kernel, tile):
     return float(v) if v else None
 
 
+def _workload(name):
+    from paper_1406_7459_amd import workloads as W
+    return W.cube(int(name[4:])) if name.startswith("cube") else getattr(W, name)()
+
+
+def pass_tile_of(kname, blocks, threads, shape):
+    """(pass, tile) of a dispatch of this library on a grid of `shape` from
+    its kernel name, its number of workgroups along x and its total threads;
+    stage kernels map to ("stage", RK4 stage); None for anything else (other
+    transform lengths, set-up kernels)."""
+    import re
+    nx, ny, nz = shape
+    nxc, pairs = nx + 1, (3 * nz * ny + 1) // 2
+    blocks = max(1, blocks)
+
+    def p2(x):
+        p = 1
+        while p < x:
+            p *= 2
+        return p
+
+    lens = {"xfwd": 2 * nx, "xinv": 2 * nx, "yfwd": 2 * ny, "yinv": 2 * ny, "yconv": 2 * ny, "zconv": 2 * nz}
+    m = re.search(r"mmk::k_(xfwd|yfwd|yinv|xinv)<(\d+), (\d+)>", kname)
+    if m:
+        if int(m.group(2)) != lens[m.group(1)]:
+            return None
+        rows = m.group(1) in ("xfwd", "xinv")
+        P = p2(-(-pairs // blocks)) if rows else p2(-(-nxc // blocks))
+        return m.group(1), P + 256 * int(m.group(3))
+    m = re.search(r"mmk::k_conv_reg3<(\d+), (true|false)>", kname)
+    if m:
+        pname = "zconv" if m.group(2) == "true" else "yconv"
+        return (pname, p2(-(-nxc // blocks))) if int(m.group(1)) == lens[pname] else None
+    m = re.search(r"mmk::k_conv_split<(\d+), (\d+), (true|false)>", kname)
+    if m:
+        pname = "zconv" if m.group(3) == "true" else "yconv"
+        if int(m.group(1)) != lens[pname]:
+            return None
+        return pname, p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2)))
+    m = re.search(r"mmk::k_stage<([0-4])>", kname)
+    if m and threads >= nx * ny * nz:
+        return "stage", int(m.group(1))
+    return None
+
+
+def summarize_trace(workload, db):
+    """Text of profiles/kernels_<workload>.txt from a rocprofv3 --kernel-trace
+    database of bench.py: per (pass, tile) of the workload's grid, the
+    dispatch count and durations (the autotuner's candidates appear as their
+    own rows), then the other kernels by name."""
+    import sqlite3
+    import statistics
+    shape = _workload(workload).shape
+    con = sqlite3.connect(db)
+    groups, other = {}, {}
+    for name, gx, gy, gz, wx, wy, wz, dur in con.execute(
+            "select name, grid_x, grid_y, grid_z, workgroup_x, workgroup_y, workgroup_z, duration from kernels"):
+        key = pass_tile_of(name, gx // max(1, wx), gx * gy * gz, shape)
+        if key:
+            groups.setdefault(key, []).append(dur / 1e3)
+        else:
+            other.setdefault(name.split("(")[0].replace("void ", ""), []).append(dur / 1e3)
+    alg = pass_bytes(*shape)
+    out = ["# kernel trace, %s (%dx%dx%d cells), rocprofv3 --kernel-trace" % ((workload,) + tuple(shape)),
+           "# command (from /tmp on the GPU, REPO = repository root):",
+           "#   rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof_%s -o %s -- python3 $REPO/bench.py "
+           "--workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs"
+           % (workload, workload, workload),
+           "#   python3 bench.py --summarize-trace %s $REPO/gpurun_out/prof_%s/%s_results.db" % (workload, workload, workload),
+           "# durations in microseconds; tile = P + 256 * variant (stage: RK4 stage 1-4, 0 = Euler); GB/s from the",
+           "# algorithmic bytes per launch (bench.pass_bytes) over the median duration",
+           "%-7s %6s %6s %9s %9s %9s %9s %8s" % ("pass", "tile", "calls", "median", "mean", "min", "max", "GB/s")]
+    for (pname, tile) in sorted(groups):
+        d = groups[(pname, tile)]
+        med = statistics.median(d)
+        a = alg.get(pname)
+        out.append("%-7s %6d %6d %9.2f %9.2f %9.2f %9.2f %8s" % (
+            pname, tile, len(d), med, statistics.mean(d), min(d), max(d), ("%.0f" % (a / med / 1e3)) if a else "-"))
+    out.append("# other kernels")
+    for name in sorted(other, key=lambda n: -sum(other[n])):
+        d = other[name]
+        out.append("#   %-56s calls %6d mean %9.2f total %10.1f" % (name[:56], len(d), statistics.mean(d), sum(d)))
+    return "\n".join(out) + "\n"
+
+
 def summarize_traffic(workload, pmc_dir):
     """Text of profiles/traffic_<workload>.txt from four rocprofv3 --pmc
     databases under pmc_dir: sweep_FETCH_SIZE, sweep_WRITE_SIZE (bench.py
@@ -79,19 +164,17 @@ def summarize_traffic(workload, pmc_dir):
     Each counter is scaled by what it reads for the 512 MiB copy; per pass
     and tile the median over that configuration's dispatches is kept."""
     import glob
-    import re
     import sqlite3
     import statistics
-    from paper_1406_7459_amd import workloads as W
 
     def load(kind, counter):
         db = glob.glob(os.path.join(pmc_dir, "%s_%s" % (kind, counter), "*.db"))[0]
         con = sqlite3.connect(db)
         per = {}
-        for disp, kname, gx, wx, v in con.execute(
-                "select dispatch_id, kernel_name, grid_size_x, workgroup_size_x, value "
+        for disp, kname, gx, wx, gt, v in con.execute(
+                "select dispatch_id, kernel_name, grid_size_x, workgroup_size_x, grid_size, value "
                 "from counters_collection where counter_name = ?", (counter,)):
-            e = per.setdefault(disp, [kname, gx, wx, 0.0])
+            e = per.setdefault(disp, [kname, gx // max(1, wx), gt, 0.0])
             e[3] += v
         return per
 
@@ -100,46 +183,13 @@ def summarize_traffic(workload, pmc_dir):
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         vals = [e[3] for e in load("copy", c).values() if "MulFunctor" in e[0]]
         scale[c] = copy_bytes / (1024.0 * statistics.median(vals))
-    wl = W.cube(int(workload[4:])) if workload.startswith("cube") else getattr(W, workload)()
-    nx, ny, nz = wl.shape
-    nxc, pairs = nx + 1, (3 * nz * ny + 1) // 2
-
-    def p2(x):
-        p = 1
-        while p < x:
-            p *= 2
-        return p
-
-    def config(kname, gx, wx):
-        blocks = max(1, gx // max(1, wx))
-        lens = {"xfwd": 2 * nx, "xinv": 2 * nx, "yfwd": 2 * ny, "yinv": 2 * ny, "yconv": 2 * ny, "zconv": 2 * nz}
-        m = re.search(r"mmk::k_(xfwd|yfwd|yinv|xinv)<(\d+), (\d+)>", kname)
-        if m and int(m.group(2)) != lens[m.group(1)]:
-            return None
-        if m:
-            rows = m.group(1) in ("xfwd", "xinv")
-            P = p2(-(-pairs // blocks)) if rows else p2(-(-nxc // blocks))
-            return m.group(1), P + 256 * int(m.group(3))
-        m = re.search(r"mmk::k_conv_reg3<(\d+), (true|false)>", kname)
-        if m and int(m.group(1)) != lens["zconv" if m.group(2) == "true" else "yconv"]:
-            return None
-        if m:
-            return ("zconv" if m.group(2) == "true" else "yconv"), p2(-(-nxc // blocks))
-        m = re.search(r"mmk::k_conv_split<(\d+), (\d+), (true|false)>", kname)
-        if m and int(m.group(1)) != lens["zconv" if m.group(3) == "true" else "yconv"]:
-            return None
-        if m:
-            return ("zconv" if m.group(3) == "true" else "yconv"), p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2)))
-        m = re.search(r"mmk::k_stage<([1-4])>", kname)
-        if m:
-            return "stage", int(m.group(1))
-        return None
-
+    shape = _workload(workload).shape
+    nx, ny, nz = shape
     acc = {}
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         for kname, gx, wx, v in load("sweep", c).values():
-            key = config(kname, gx, wx)
-            if key:
+            key = pass_tile_of(kname, gx, wx, shape)
+            if key and not (key[0] == "stage" and key[1] == 0):
                 acc.setdefault(key, {}).setdefault(c, []).append(v * 1024.0 * scale[c])
     alg = pass_bytes(nx, ny, nz)
     out = ["# HBM traffic per launch, %s (%dx%dx%d cells), rocprofv3 hardware counters" % (workload, nx, ny, nz),
@@ -281,6 +331,47 @@ def table1_euler(torch, mm, W):
     return out
 
 
+def other_configs(torch, mm, W):
+    """RK4 step and isolated demag times of the other grid sizes of the
+    throughput table (64^3 and 256^3 cubes) and of the learned-form film
+    (256x256x4), each with its own autotuned tiles; the step roofline uses
+    the same algorithmic bytes as the headline line."""
+    out = {}
+    for wl, steps in ((W.cube(64), 40), (W.cube(256), 10), (W.film256(0), 40)):
+        m = wl.mat
+        nx, ny, nz = wl.shape
+        plan = mm.Plan(nx, ny, nz, *wl.cell)
+        tiles = plan.autotune(reps=3)
+        p = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha, gamma0=m.gamma0,
+                              Hext=m.Hext, dt=m.dt)
+        M = torch.from_numpy((m.Ms * wl.initial_unit()).astype("float32")).cuda()
+        H = torch.empty_like(M)
+        plan.step(p, M, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(p, M, steps)
+        torch.cuda.synchronize()
+        st = (time.perf_counter() - t0) / steps
+        for _ in range(5):
+            plan.demag(M, H)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(50):
+            plan.demag(M, H)
+        torch.cuda.synchronize()
+        dm = (time.perf_counter() - t0) / 50
+        b = pass_bytes(nx, ny, nz)
+        step_bytes = sum(4 * v for v in b.values())
+        demag_bytes = sum(v for k, v in b.items() if k != "stage")
+        out[wl.name] = {"grid": [nx, ny, nz], "ms_per_step": st * 1e3,
+                        "cell_updates_per_s": nx * ny * nz / st,
+                        "step_roofline_frac": step_bytes / st / 1e9 / HBM_PEAK_GBS,
+                        "demag_ms": dm * 1e3, "demag_roofline_frac": demag_bytes / dm / 1e9 / HBM_PEAK_GBS,
+                        "tiles": tiles}
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,8 +381,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("WORKLOAD", "PMC_DIR"),
                     help="print the traffic summary of rocprofv3 counter databases and exit")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("WORKLOAD", "DB"),
+                    help="print the per-(pass, tile) summary of a rocprofv3 kernel-trace database and exit")
     ap.add_argument("--sweep-tiles", action="store_true",
                     help="run only five demag evaluations with every valid tile of every pass "
                          "(for per-tile hardware counters)")
@@ -301,6 +395,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_traffic:
         sys.stdout.write(summarize_traffic(*args.summarize_traffic))
+        return
+    if args.summarize_trace:
+        sys.stdout.write(summarize_trace(*args.summarize_trace))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU; the library has no multi-GPU path (got --gpus %d)"
@@ -466,6 +563,8 @@ def main():
         "rows": table1_euler(torch, mm, W),
         "paper_gpu_ms_HD7970": {"8": 1.95, "16": 2.723, "32": 3.151, "64": 6.558, "128": 26.34},
         "note": "paper Table 1 (Euler, FP32, AMD HD 7970): other hardware, context only"}
+    if not args.no_other_configs:
+        out["other_configs"] = other_configs(torch, mm, W)
     if not args.no_batch:
         out["batched"] = batch_measure(torch, mm, W)
     if not args.no_cpu_baseline:

@@ -173,9 +173,11 @@ int mm_plan_query(mm_plan plan, mm_plan_info *info);
 int mm_plan_set_tile(mm_plan plan, int pass, int tile);
 
 /* Time every candidate tile of every pass on this plan's buffers and keep
- * the fastest (hipEvent timing, `reps` launches each).  Candidates must
- * agree numerically; the chosen tiles are readable with mm_plan_query.
- * Synchronises.  Errors: MM_ETUNE if no candidate ran.                       */
+ * the fastest: a candidate is timed as `reps` complete demag evaluations
+ * (hipEvents around the loop only), the other passes keeping their current
+ * tiles, and the passes are swept twice.  Overwrites the plan's stage
+ * buffers.  Candidates agree bitwise; the chosen tiles are readable with
+ * mm_plan_query.  Synchronises.  Errors: MM_ETUNE if no candidate ran.       */
 int mm_plan_autotune(mm_plan plan, int reps, void *stream);
 
 /* Per-kernel timing: when enabled, every launch of the plan is bracketed
