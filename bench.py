@@ -317,6 +317,7 @@ def table1_euler(torch, mm, W):
         wl = W.cube(n)
         m = wl.mat
         plan = mm.Plan(n, n, n, *wl.cell)
+        plan.autotune(reps=3)
         p = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha, gamma0=m.gamma0,
                               dt=m.dt, integrator="euler")
         M = torch.from_numpy((m.Ms * wl.initial_unit()).astype("float32")).cuda()

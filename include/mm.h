@@ -168,8 +168,11 @@ int mm_plan_query(mm_plan plan, mm_plan_info *info);
  * default values per thread E, 1 = 2E; for the product passes (ZCONV, YCONV)
  * 0 = all three components in one thread's registers, 1 = one component per
  * thread group with the 3x3 product exchanged through LDS, 2 = as 1 with 2E.
- * Every configuration computes bitwise the same result.  Returns MM_EINVAL
- * for a configuration the pass cannot launch.                              */
+ * For MM_PASS_STAGE the tile is the vector width W in {1, 2, 4}: W
+ * consecutive cells of an x row per thread (nx % W == 0; default 4 when
+ * nx % 4 == 0; a launch whose arrays are not aligned to 4W bytes falls back
+ * to a narrower width).  Every configuration computes bitwise the same
+ * result.  Returns MM_EINVAL for a configuration the pass cannot launch.    */
 int mm_plan_set_tile(mm_plan plan, int pass, int tile);
 
 /* Time every candidate tile of every pass on this plan's buffers and keep

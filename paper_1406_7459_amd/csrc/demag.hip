@@ -230,8 +230,11 @@ int default_tile_for(int pass, int L, size_t lds_limit)
     return best;
 }
 
+// The stage kernel's "tile" is its vector width W: W consecutive cells of
+// an x row per thread (1, 2 or 4; nx % W == 0).
 bool pass_tile_valid(const Plan &p, int pass, int tile)
 {
+    if (pass == MM_PASS_STAGE) return (tile == 1 || tile == 2 || tile == 4) && p.nx % tile == 0;
     return pass_active(p, pass) && tile_valid_for(pass, pass_length(p, pass), tile, p.lds_limit);
 }
 
@@ -243,6 +246,7 @@ std::vector<int> pass_tile_candidates(const Plan &p, int pass)
 
 int pass_default_tile(const Plan &p, int pass)
 {
+    if (pass == MM_PASS_STAGE) return p.nx % 4 == 0 ? 4 : (p.nx % 2 == 0 ? 2 : 1);
     if (!pass_active(p, pass)) return 0;
     return default_tile_for(pass, pass_length(p, pass), p.lds_limit);
 }

@@ -20,6 +20,15 @@ __global__ __launch_bounds__(256) void k_stage(const float *S, const float *__re
     stage_body<STAGE>(S, Hd, Mn, kacc, out, nx, ny, nz, c, b * blockDim.x + threadIdx.x);
 }
 
+template <int STAGE, int W>
+__global__ __launch_bounds__(256) void k_stage_vec(const float *S, const float *__restrict__ Hd, const float *Mn,
+                                                   float *__restrict__ kacc, float *out, int nx, int ny, int nz,
+                                                   StageCoef c)
+{
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    stage_body_vec<STAGE, W>(S, Hd, Mn, kacc, out, nx, ny, nz, c, b * blockDim.x + threadIdx.x);
+}
+
 StageCoef stage_coef(const Plan &p, const mm_llg_params &q)
 {
     const double mu0 = 4e-7 * M_PI;
@@ -51,10 +60,22 @@ static int launch_stage(Plan &p, const float *S, const float *Mn, float *out, co
     if (!Hd) Hd = p.H;
     const size_t n = (size_t)p.cells();
     const int bs = 256;
+    // vector width: the plan's stage tile, if every array is aligned for it
+    int W = p.tile[MM_PASS_STAGE];
+    auto aligned = [](const void *q, int w) { return ((uintptr_t)q % (sizeof(float) * w)) == 0; };
+    while (W > 1 && (p.nx % W != 0 || !aligned(S, W) || !aligned(Hd, W) || !aligned(Mn, W) || !aligned(out, W) ||
+                     !aligned(p.kacc, W)))
+        W /= 2;
+    const size_t threads = (n + W - 1) / W;
+    const dim3 grid((unsigned)((threads + bs - 1) / bs));
     hipEvent_t ev0 = nullptr;
     timing_begin(p, MM_PASS_STAGE, s, &ev0);
-    hipLaunchKernelGGL(k_stage<STAGE>, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, S, Hd, Mn, p.kacc,
-                       out, p.nx, p.ny, p.nz, c);
+    if (W == 4)
+        hipLaunchKernelGGL((k_stage_vec<STAGE, 4>), grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
+    else if (W == 2)
+        hipLaunchKernelGGL((k_stage_vec<STAGE, 2>), grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
+    else
+        hipLaunchKernelGGL(k_stage<STAGE>, grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
     timing_end(p, MM_PASS_STAGE, s, ev0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MM_EHIP, std::string("k_stage: ") + hipGetErrorString(e));

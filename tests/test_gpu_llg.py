@@ -194,3 +194,32 @@ def test_timing_mode_counts_every_kernel_and_matches_untimed():
     for k in ("xfwd", "yfwd", "zconv", "yinv", "xinv", "stage"):
         assert t[k][1] == 40, (k, t[k])   # 10 steps x 4 stages
         assert t[k][0] > 0.0
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "euler"])
+@pytest.mark.parametrize("grid", [(24, 12, 3), (6, 4, 3), (64, 32, 8)])
+def test_stage_vector_widths_are_bitwise_identical(grid, integrator):
+    """The stage kernel with 1, 2 or 4 cells per thread (its tile) computes
+    bitwise the same states, including at the x boundaries of every group,
+    and a width that does not divide nx is rejected."""
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = grid
+    mat = W.Material(Ms=8e5, A=1.3e-11, Ku=2e4, axis=(0.6, 0.0, 0.8), alpha=0.3, Hext=(1e4, -5e3, 2e4))
+    pg, _ = _params(mm, mat, integrator=integrator)
+    plan = mm.Plan(nx, ny, nz, 4e-9, 4e-9, 2e-9)
+    M0 = to_dev(mat.Ms * W.random_unit(nx, ny, nz, seed=33))
+    out = {}
+    for w in (1, 2, 4):
+        if nx % w:
+            with pytest.raises(mm.MMError):
+                plan.set_tile("stage", w)
+            continue
+        plan.set_tile("stage", w)
+        M = M0.clone()
+        plan.step(pg, M, 3)
+        out[w] = to_host(M)
+    ws = sorted(out)
+    say("stage widths", ws)
+    assert len(ws) >= 2 or nx % 2
+    for w in ws[1:]:
+        assert np.array_equal(out[w], out[ws[0]])
