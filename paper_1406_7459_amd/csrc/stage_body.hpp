@@ -68,6 +68,19 @@ __device__ __forceinline__ void stage_cell(const float (&m)[3], const float (&xm
     }
 }
 
+// Element idx of a float array through a 32-bit byte offset from a uniform
+// base: the load/store takes the scalar-base form (base in SGPRs, one 32-bit
+// VGPR offset) instead of a 64-bit per-lane address.  Byte offsets stay
+// below 2^32 (at most 512^3 cells per component).
+__device__ __forceinline__ float ld32(const float *base, unsigned idx)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + (idx << 2));
+}
+__device__ __forceinline__ void st32(float *base, unsigned idx, float v)
+{
+    *reinterpret_cast<float *>(reinterpret_cast<char *>(base) + (idx << 2)) = v;
+}
+
 // One cell per thread: reads the stage state S (with its six neighbours),
 // the demag field Hd of S, the step's start state Mn and the accumulator;
 // writes the accumulator and the next stage state `out`.
@@ -93,22 +106,22 @@ __device__ __forceinline__ void stage_body(const float *S, const float *__restri
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float *s = S + (size_t)a * n;
-        m[a] = s[id];
-        vxm[a] = s[xm];
-        vxp[a] = s[xp];
-        vym[a] = s[ym];
-        vyp[a] = s[yp];
-        vzm[a] = s[zm];
-        vzp[a] = s[zp];
-        hd[a] = (Hd + (size_t)a * n)[id];
-        mn[a] = (Mn + (size_t)a * n)[id];
-        ka[a] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? (kacc + (size_t)a * n)[id] : 0.f;
+        m[a] = ld32(s, id);
+        vxm[a] = ld32(s, xm);
+        vxp[a] = ld32(s, xp);
+        vym[a] = ld32(s, ym);
+        vyp[a] = ld32(s, yp);
+        vzm[a] = ld32(s, zm);
+        vzp[a] = ld32(s, zp);
+        hd[a] = ld32(Hd + (size_t)a * n, id);
+        mn[a] = ld32(Mn + (size_t)a * n, id);
+        ka[a] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? ld32(kacc + (size_t)a * n, id) : 0.f;
     }
     stage_cell<STAGE>(m, vxm, vxp, vym, vyp, vzm, vzp, hd, mn, ka, o, c);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) (kacc + (size_t)a * n)[id] = ka[a];
-        (out + (size_t)a * n)[id] = o[a];
+        if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) st32(kacc + (size_t)a * n, id, ka[a]);
+        st32(out + (size_t)a * n, id, o[a]);
     }
 }
 
@@ -119,6 +132,17 @@ __device__ __forceinline__ void stage_body(const float *S, const float *__restri
 template <int W> struct VecOf;
 template <> struct VecOf<2> { typedef float2 T; };
 template <> struct VecOf<4> { typedef float4 T; };
+
+template <typename V>
+__device__ __forceinline__ V ldv32(const float *base, unsigned idx)
+{
+    return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(base) + (idx << 2));
+}
+template <typename V>
+__device__ __forceinline__ void stv32(float *base, unsigned idx, const V &v)
+{
+    *reinterpret_cast<V *>(reinterpret_cast<char *>(base) + (idx << 2)) = v;
+}
 
 template <int W>
 __device__ __forceinline__ float lane_of(const typename VecOf<W>::T &v, int e)
@@ -154,17 +178,16 @@ __device__ __forceinline__ void stage_body_vec(const float *S, const float *__re
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const float *s = S + (size_t)a * n;
-        vs[a] = *reinterpret_cast<const V *>(s + id);
-        vym[a] = *reinterpret_cast<const V *>(s + ym);
-        vyp[a] = *reinterpret_cast<const V *>(s + yp);
-        vzm[a] = *reinterpret_cast<const V *>(s + zm);
-        vzp[a] = *reinterpret_cast<const V *>(s + zp);
-        left[a] = i > 0 ? s[id - 1] : lane_of<W>(vs[a], 0);
-        right[a] = i + W < (unsigned)nx ? s[id + W] : lane_of<W>(vs[a], W - 1);
-        vhd[a] = *reinterpret_cast<const V *>(Hd + (size_t)a * n + id);
-        vmn[a] = *reinterpret_cast<const V *>(Mn + (size_t)a * n + id);
-        if constexpr (STAGE == 2 || STAGE == 3 || STAGE == 4)
-            vka[a] = *reinterpret_cast<const V *>(kacc + (size_t)a * n + id);
+        vs[a] = ldv32<V>(s, id);
+        vym[a] = ldv32<V>(s, ym);
+        vyp[a] = ldv32<V>(s, yp);
+        vzm[a] = ldv32<V>(s, zm);
+        vzp[a] = ldv32<V>(s, zp);
+        left[a] = i > 0 ? ld32(s, id - 1) : lane_of<W>(vs[a], 0);
+        right[a] = i + W < (unsigned)nx ? ld32(s, id + W) : lane_of<W>(vs[a], W - 1);
+        vhd[a] = ldv32<V>(Hd + (size_t)a * n, id);
+        vmn[a] = ldv32<V>(Mn + (size_t)a * n, id);
+        if constexpr (STAGE == 2 || STAGE == 3 || STAGE == 4) vka[a] = ldv32<V>(kacc + (size_t)a * n, id);
     }
     V vo[3], vk[3];
 #pragma unroll
@@ -192,9 +215,8 @@ __device__ __forceinline__ void stage_body_vec(const float *S, const float *__re
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3)
-            *reinterpret_cast<V *>(kacc + (size_t)a * n + id) = vk[a];
-        *reinterpret_cast<V *>(out + (size_t)a * n + id) = vo[a];
+        if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) stv32<V>(kacc + (size_t)a * n, id, vk[a]);
+        stv32<V>(out + (size_t)a * n, id, vo[a]);
     }
 }
 
