@@ -217,8 +217,10 @@ int mm_batch_demag(mm_batch batch, const float *const *M_dev, float *const *H_de
  * instance table (synchronising) and re-captures the step graph.           */
 int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M_dev, int nsteps, void *stream);
 
-/* Tune the tile of every (pass, length) group on the batch's buffers
- * (hipEvent timing, `reps` launches per candidate).  Synchronises.          */
+/* Tune the tile of every (pass, length) group on the batch's buffers: a
+ * candidate is timed as `reps` complete batched demag evaluations (hipEvents
+ * around the loop), the other groups keeping their tiles.  Overwrites the
+ * instances' stage buffers.  Synchronises.                                  */
 int mm_batch_autotune(mm_batch batch, int reps, void *stream);
 
 /* Number of (pass, length) groups, kernel launches per RK4 step, total cells. */

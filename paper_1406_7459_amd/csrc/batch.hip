@@ -499,6 +499,9 @@ int mm_batch_autotune(mm_batch batch, int reps, void *stream)
     MMK_HIP(hipEventCreate(&e0));
     MMK_HIP(hipEventCreate(&e1));
     int rc = MM_OK, tuned = 0;
+    // a candidate is timed as `reps` complete batched demag evaluations
+    // (every group launched in step order, events only around the loop), so
+    // it is judged in the cache state and launch overlap of a real step
     for (BGroup &g : b.groups) {
         const int keep = g.tile;
         float best = 1e30f;
@@ -506,9 +509,9 @@ int mm_batch_autotune(mm_batch batch, int reps, void *stream)
         for (int t : tile_candidates_for(g.pass, g.L, b.lds_limit)) {
             g.tile = t;
             if ((rc = build_tasks(b, g)) != MM_OK) break;
-            if ((rc = launch_group(g, b.d_inst, 1, s, false)) != MM_OK) break;
+            if ((rc = batch_demag_enqueue(b, b.d_inst, 1, s)) != MM_OK) break;
             (void)hipEventRecord(e0, s);
-            for (int r = 0; r < reps && rc == MM_OK; ++r) rc = launch_group(g, b.d_inst, 1, s, false);
+            for (int r = 0; r < reps && rc == MM_OK; ++r) rc = batch_demag_enqueue(b, b.d_inst, 1, s);
             (void)hipEventRecord(e1, s);
             if (rc != MM_OK || hipEventSynchronize(e1) != hipSuccess) {
                 if (rc == MM_OK) rc = fail(MM_EHIP, "batch autotune event");
