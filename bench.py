@@ -111,9 +111,9 @@ def pass_tile_of(kname, blocks, threads, shape):
         if int(m.group(1)) != lens[pname]:
             return None
         return pname, p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2)))
-    m = re.search(r"mmk::k_stage<([0-4])>", kname)
-    if m and threads >= nx * ny * nz:
-        return "stage", int(m.group(1))
+    m = re.search(r"mmk::k_stage(_vec)?<([0-4])(?:, (\d))?>", kname)
+    if m and threads * (int(m.group(3)) if m.group(3) else 1) >= nx * ny * nz:
+        return "stage", int(m.group(2))
     return None
 
 
