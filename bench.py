@@ -78,9 +78,10 @@ def _workload(name):
 
 
 def pass_tile_of(kname, blocks, threads, shape):
-    """(pass, tile) of a dispatch of this library on a grid of `shape` from
-    its kernel name, its number of workgroups along x and its total threads;
-    stage kernels map to ("stage", RK4 stage); None for anything else (other
+    """(pass, tile, sub) of a dispatch of this library on a grid of `shape`
+    from its kernel name, its number of workgroups along x and its total
+    threads: sub is the RK4 stage (0 = Euler) for the stage kernel, whose tile
+    is its vector width, and 0 otherwise; None for anything else (other
     transform lengths, set-up kernels)."""
     import re
     nx, ny, nz = shape
@@ -100,20 +101,21 @@ def pass_tile_of(kname, blocks, threads, shape):
             return None
         rows = m.group(1) in ("xfwd", "xinv")
         P = p2(-(-pairs // blocks)) if rows else p2(-(-nxc // blocks))
-        return m.group(1), P + 256 * int(m.group(3))
+        return m.group(1), P + 256 * int(m.group(3)), 0
     m = re.search(r"mmk::k_conv_reg3<(\d+), (true|false)>", kname)
     if m:
         pname = "zconv" if m.group(2) == "true" else "yconv"
-        return (pname, p2(-(-nxc // blocks))) if int(m.group(1)) == lens[pname] else None
+        return (pname, p2(-(-nxc // blocks)), 0) if int(m.group(1)) == lens[pname] else None
     m = re.search(r"mmk::k_conv_split<(\d+), (\d+), (true|false)>", kname)
     if m:
         pname = "zconv" if m.group(3) == "true" else "yconv"
         if int(m.group(1)) != lens[pname]:
             return None
-        return pname, p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2)))
+        return pname, p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2))), 0
     m = re.search(r"mmk::k_stage(_vec)?<([0-4])(?:, (\d))?>", kname)
-    if m and threads * (int(m.group(3)) if m.group(3) else 1) >= nx * ny * nz:
-        return "stage", int(m.group(2))
+    w = int(m.group(3)) if m and m.group(3) else 1
+    if m and threads * w >= nx * ny * nz:
+        return "stage", w, int(m.group(2))
     return None
 
 
@@ -141,15 +143,19 @@ def summarize_trace(workload, db):
            "--workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs"
            % (workload, workload, workload),
            "#   python3 bench.py --summarize-trace %s $REPO/gpurun_out/prof_%s/%s_results.db" % (workload, workload, workload),
-           "# durations in microseconds; tile = P + 256 * variant (stage: RK4 stage 1-4, 0 = Euler); GB/s from the",
-           "# algorithmic bytes per launch (bench.pass_bytes) over the median duration",
-           "%-7s %6s %6s %9s %9s %9s %9s %8s" % ("pass", "tile", "calls", "median", "mean", "min", "max", "GB/s")]
-    for (pname, tile) in sorted(groups):
-        d = groups[(pname, tile)]
+           "# durations in microseconds; tile = P + 256 * variant, for the stage kernel its vector width, with",
+           "# the RK4 stage (1-4, 0 = Euler) in column s; GB/s from the algorithmic bytes per launch",
+           "# (bench.pass_bytes; stage: 48N, 72N, 72N, 60N bytes, Euler 60N) over the median duration",
+           "%-7s %6s %2s %6s %9s %9s %9s %9s %8s" % ("pass", "tile", "s", "calls", "median", "mean", "min", "max", "GB/s")]
+    N = shape[0] * shape[1] * shape[2]
+    stage_bytes = {0: 60 * N, 1: 48 * N, 2: 72 * N, 3: 72 * N, 4: 60 * N}
+    for key in sorted(groups):
+        pname, tile, sub = key
+        d = groups[key]
         med = statistics.median(d)
-        a = alg.get(pname)
-        out.append("%-7s %6d %6d %9.2f %9.2f %9.2f %9.2f %8s" % (
-            pname, tile, len(d), med, statistics.mean(d), min(d), max(d), ("%.0f" % (a / med / 1e3)) if a else "-"))
+        a = stage_bytes[sub] if pname == "stage" else alg.get(pname)
+        out.append("%-7s %6d %2d %6d %9.2f %9.2f %9.2f %9.2f %8s" % (
+            pname, tile, sub, len(d), med, statistics.mean(d), min(d), max(d), ("%.0f" % (a / med / 1e3)) if a else "-"))
     out.append("# other kernels")
     for name in sorted(other, key=lambda n: -sum(other[n])):
         d = other[name]
@@ -189,7 +195,7 @@ def summarize_traffic(workload, pmc_dir):
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         for kname, gx, wx, v in load("sweep", c).values():
             key = pass_tile_of(kname, gx, wx, shape)
-            if key and not (key[0] == "stage" and key[1] == 0):
+            if key and not (key[0] == "stage" and key[2] == 0):
                 acc.setdefault(key, {}).setdefault(c, []).append(v * 1024.0 * scale[c])
     alg = pass_bytes(nx, ny, nz)
     out = ["# HBM traffic per launch, %s (%dx%dx%d cells), rocprofv3 hardware counters" % (workload, nx, ny, nz),
@@ -203,23 +209,25 @@ def summarize_traffic(workload, pmc_dir):
            % (scale["FETCH_SIZE"], scale["WRITE_SIZE"]),
            "# per pass and tile (P + 256 * variant): median fetch / write bytes per launch; stage: mean of RK4 stages 1-4",
            "kernel_source_hash: %s" % kernel_source_hash()]
-    stage = []
-    for (pname, tile) in sorted(acc):
-        d = acc[(pname, tile)]
+    stage = {}
+    for key in sorted(acc):
+        pname, tile, sub = key
+        d = acc[key]
         if "FETCH_SIZE" not in d or "WRITE_SIZE" not in d:
             continue
         f, w = statistics.median(d["FETCH_SIZE"]), statistics.median(d["WRITE_SIZE"])
         if pname == "stage":
-            stage.append(f + w)
+            stage.setdefault(tile, []).append(f + w)
             continue
         a = alg.get(pname)
         out.append("# %-6s tile %4d: fetch %11.0f write %11.0f  (x%.2f of algorithmic %d)"
                    % (pname, tile, f, w, (f + w) / a if a else 0.0, a or 0))
         out.append("hbm_bytes_per_launch.%s.%d: %.0f" % (pname, tile, f + w))
-    if stage:
-        out.append("# stage  RK4 stages 1-4 mean: %.0f (x%.2f of algorithmic %d)"
-                   % (sum(stage) / len(stage), sum(stage) / len(stage) / alg["stage"], alg["stage"]))
-        out.append("hbm_bytes_per_launch.stage.0: %.0f" % (sum(stage) / len(stage)))
+    for tile in sorted(stage):
+        v = sum(stage[tile]) / len(stage[tile])
+        out.append("# stage  tile %4d: RK4 stages 1-4 mean %.0f (x%.2f of algorithmic %d)"
+                   % (tile, v, v / alg["stage"], alg["stage"]))
+        out.append("hbm_bytes_per_launch.stage.%d: %.0f" % (tile, v))
     return "\n".join(out) + "\n"
 
 
