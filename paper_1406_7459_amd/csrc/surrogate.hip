@@ -50,9 +50,20 @@ __device__ __forceinline__ float gelu_d(float x)
 
 // EPI 0: hidden layer, Z = acc + b (FP32) and Xn = bf16(gelu(Z));
 // EPI 1: last layer, dh[co][cell] = scale * (acc + b) for co < 3 (SoA FP32);
-// EPI 2: raw Z = acc (input gradient, no bias).
+// EPI 2: raw Z = acc (input gradient, no bias);
+// EPI 3: hidden layer for inference only, Xn = bf16(gelu(acc + b)) (no Z).
+//
+// A wave computes CT = 4 column tiles of 16 cells (64 consecutive cells) for
+// all 32 output channels: per tap it reads the two 16x32 weight fragments
+// from LDS once and reuses them for the four tiles (eight MFMAs), so the LDS
+// traffic per MFMA is a quarter of a one-tile wave's and four independent
+// activation loads are in flight per tap.  Eight waves share one copy of the
+// layer's weights in LDS (55 KB), so two workgroups (sixteen waves) fit a CU.
+constexpr int CT = 4;
+constexpr int CONV_WAVES = 8;
+
 template <int EPI>
-__global__ __launch_bounds__(256) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ W,
+__global__ __launch_bounds__(64 * CONV_WAVES) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ W,
                                               const float *__restrict__ bias, float *__restrict__ Z,
                                               __bf16 *__restrict__ Xn, float *__restrict__ dh, float scale, int nx,
                                               int ny, int nz)
@@ -64,54 +75,79 @@ __global__ __launch_bounds__(256) void k_conv(const __bf16 *__restrict__ X, cons
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const long long N = (long long)nx * ny * nz;
-    const long long ntiles = (N + 15) / 16;
+    const long long ngroups = (N + 16 * CT - 1) / (16 * CT);
     const bf8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (long long tile = (long long)blockIdx.x * 4 + wv; tile < ntiles; tile += (long long)gridDim.x * 4) {
-        const long long cell = tile * 16 + col;
-        const bool live = cell < N;
-        const int i = live ? (int)(cell % nx) : 0;
-        const int j = live ? (int)((cell / nx) % ny) : 0;
-        const int k = live ? (int)(cell / ((long long)nx * ny)) : 0;
-        f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
+    for (long long grp = (long long)blockIdx.x * CONV_WAVES + wv; grp < ngroups;
+         grp += (long long)gridDim.x * CONV_WAVES) {
+        long long cell[CT];
+        bool live[CT];
+        int ci[CT], cj[CT], ck[CT];
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+            cell[u] = (grp * CT + u) * 16 + col;
+            live[u] = cell[u] < N;
+            ci[u] = live[u] ? (int)(cell[u] % nx) : 0;
+            cj[u] = live[u] ? (int)((cell[u] / nx) % ny) : 0;
+            ck[u] = live[u] ? (int)(cell[u] / ((long long)nx * ny)) : 0;
+        }
+        f4 acc0[CT], acc1[CT];
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+            acc0[u] = f4{0.f, 0.f, 0.f, 0.f};
+            acc1[u] = f4{0.f, 0.f, 0.f, 0.f};
+        }
         for (int t = 0; t < NT; ++t) {
-            const int ii = i + t % 3 - 1, jj = j + (t / 3) % 3 - 1, kk = k + t / 9 - 1;
-            const bool in = live && ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz;
-            const bf8 b = in ? *reinterpret_cast<const bf8 *>(X + (((long long)kk * ny + jj) * nx + ii) * SC + 8 * kq)
-                             : zero8;
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
             const bf8 a0 = wl[(col * NT + t) * 4 + kq];
             const bf8 a1 = wl[((16 + col) * NT + t) * 4 + kq];
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc1, 0, 0, 0);
+            bf8 bv[CT];
+#pragma unroll
+            for (int u = 0; u < CT; ++u) {
+                const int ii = ci[u] + dx, jj = cj[u] + dy, kk = ck[u] + dz;
+                const bool in = live[u] && ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz;
+                bv[u] = in ? *reinterpret_cast<const bf8 *>(X + (((long long)kk * ny + jj) * nx + ii) * SC + 8 * kq)
+                           : zero8;
+            }
+#pragma unroll
+            for (int u = 0; u < CT; ++u) {
+                acc0[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv[u], acc0[u], 0, 0, 0);
+                acc1[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv[u], acc1[u], 0, 0, 0);
+            }
         }
-        if (!live) continue;
         // lane holds D[co = 4 kq + r][cell] (acc0) and D[16 + 4 kq + r][cell] (acc1)
-        if constexpr (EPI == 0) {
-            f4 z0, z1;
-            bf4 g0, g1;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                z0[r] = acc0[r] + bias[4 * kq + r];
-                z1[r] = acc1[r] + bias[16 + 4 * kq + r];
-                g0[r] = (__bf16)gelu_f(z0[r]);
-                g1[r] = (__bf16)gelu_f(z1[r]);
-            }
-            *reinterpret_cast<f4 *>(Z + cell * SC + 4 * kq) = z0;
-            *reinterpret_cast<f4 *>(Z + cell * SC + 16 + 4 * kq) = z1;
-            *reinterpret_cast<bf4 *>(Xn + cell * SC + 4 * kq) = g0;
-            *reinterpret_cast<bf4 *>(Xn + cell * SC + 16 + 4 * kq) = g1;
-        } else if constexpr (EPI == 1) {
-            if (kq == 0) {
+        for (int u = 0; u < CT; ++u) {
+            if (!live[u]) continue;
+            const long long c = cell[u];
+            if constexpr (EPI == 0 || EPI == 3) {
+                f4 z0, z1;
+                bf4 g0, g1;
 #pragma unroll
-                for (int r = 0; r < 3; ++r) {
-                    const float z = acc0[r] + bias[r];
-                    Z[cell * SC + r] = z;
-                    dh[r * N + cell] = scale * z;
+                for (int r = 0; r < 4; ++r) {
+                    z0[r] = acc0[u][r] + bias[4 * kq + r];
+                    z1[r] = acc1[u][r] + bias[16 + 4 * kq + r];
+                    g0[r] = (__bf16)gelu_f(z0[r]);
+                    g1[r] = (__bf16)gelu_f(z1[r]);
                 }
+                if constexpr (EPI == 0) {
+                    *reinterpret_cast<f4 *>(Z + c * SC + 4 * kq) = z0;
+                    *reinterpret_cast<f4 *>(Z + c * SC + 16 + 4 * kq) = z1;
+                }
+                *reinterpret_cast<bf4 *>(Xn + c * SC + 4 * kq) = g0;
+                *reinterpret_cast<bf4 *>(Xn + c * SC + 16 + 4 * kq) = g1;
+            } else if constexpr (EPI == 1) {
+                if (kq == 0) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        const float z = acc0[u][r] + bias[r];
+                        Z[c * SC + r] = z;
+                        dh[r * N + c] = scale * z;
+                    }
+                }
+            } else {
+                *reinterpret_cast<f4 *>(Z + c * SC + 4 * kq) = acc0[u];
+                *reinterpret_cast<f4 *>(Z + c * SC + 16 + 4 * kq) = acc1[u];
             }
-        } else {
-            *reinterpret_cast<f4 *>(Z + cell * SC + 4 * kq) = acc0;
-            *reinterpret_cast<f4 *>(Z + cell * SC + 16 + 4 * kq) = acc1;
         }
     }
 }
@@ -405,18 +441,29 @@ static void refresh(Sur &s, hipStream_t st)
 
 static unsigned grid_for(long long n) { return (unsigned)std::min<long long>((n + 255) / 256, 4096); }
 
-// forward of the whole stack on X[0] (already filled); last layer -> dh
-static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale)
+// workgroups of a convolution launch: CONV_WAVES waves, CT tiles of 16 cells each
+static unsigned conv_grid(long long N)
 {
-    const unsigned gb = (unsigned)std::min<long long>(((s.N + 15) / 16 + 3) / 4, 4096);
+    return (unsigned)std::min<long long>(((N + 16 * CT - 1) / (16 * CT) + CONV_WAVES - 1) / CONV_WAVES, 4096);
+}
+
+// forward of the whole stack on X[0] (already filled); last layer -> dh.
+// keep_z: store the pre-activations Z of the hidden layers (needed by the
+// backward pass; inference skips them).
+static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool keep_z)
+{
+    const unsigned gb = conv_grid(s.N);
     for (int l = 0; l < NLAYER; ++l) {
         const __bf16 *W = s.wb + (long long)l * WSZ;
         const float *b = s.w + l * layer_stride() + WSZ;
-        if (l < NLAYER - 1)
-            hipLaunchKernelGGL(k_conv<0>, dim3(gb), dim3(256), 0, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, 1.f,
+        if (l < NLAYER - 1 && keep_z)
+            hipLaunchKernelGGL(k_conv<0>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, 1.f,
+                               s.nx, s.ny, s.nz);
+        else if (l < NLAYER - 1)
+            hipLaunchKernelGGL(k_conv<3>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, 1.f,
                                s.nx, s.ny, s.nz);
         else
-            hipLaunchKernelGGL(k_conv<1>, dim3(gb), dim3(256), 0, st, s.X[l], W, b, s.Z[l], nullptr, dh, 1.f, s.nx,
+            hipLaunchKernelGGL(k_conv<1>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.X[l], W, b, s.Z[l], nullptr, dh, 1.f, s.nx,
                                s.ny, s.nz);
     }
     if (dev_scale) hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(3 * s.N)), dim3(256), 0, st, dh, s.sig, 3 * s.N);
@@ -441,7 +488,7 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
                        s.N);
     std::vector<double> hp(RED_B);
     MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * RED_B, hipMemcpyDeviceToHost, st));
-    const unsigned gb = (unsigned)std::min<long long>(((s.N + 15) / 16 + 3) / 4, 4096);
+    const unsigned gb = conv_grid(s.N);
     for (int l = NLAYER - 1; l >= 0; --l) {
         hipLaunchKernelGGL(k_conv_dw, dim3(s.nchunk), dim3(256), 0, st, s.dZ, s.X[l], s.part, s.bpart, s.nx, s.ny, s.nz,
                            s.chunk);
@@ -449,7 +496,7 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
         hipLaunchKernelGGL(k_sum_chunks, dim3((WSZ + 255) / 256), dim3(256), 0, st, s.part, s.nchunk, WSZ, gl);
         hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, st, s.bpart, s.nchunk, SC, gl + WSZ);
         if (l > 0) {
-            hipLaunchKernelGGL(k_conv<2>, dim3(gb), dim3(256), 0, st, s.dZb, s.wt + (long long)l * WSZ, nullptr, s.dX,
+            hipLaunchKernelGGL(k_conv<2>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.dZb, s.wt + (long long)l * WSZ, nullptr, s.dX,
                                nullptr, nullptr, 1.f, s.nx, s.ny, s.nz);
             hipLaunchKernelGGL(k_gelu_back, dim3(grid_for(s.N * SC)), dim3(256), 0, st, s.dX, s.Z[l - 1], s.dZ, s.dZb,
                                s.N * SC);
@@ -517,7 +564,7 @@ static void sur_field(Sur &s, const float *Mstage, const float *Mn, const float 
 {
     hipLaunchKernelGGL(k_axpby, dim3(grid_for(3 * s.N)), dim3(256), 0, st, Mstage, Mn, 1.f / Ms, s.tmp, 3 * s.N);
     sur_input(s, s.tmp, 1, st);
-    sur_forward(s, s.tmp2, st, true);
+    sur_forward(s, s.tmp2, st, true, false);
     hipLaunchKernelGGL(k_anchor, dim3(grid_for(3 * s.N)), dim3(256), 0, st, H0, s.tmp2, Ms, H, 3 * s.N);
 }
 
@@ -648,7 +695,7 @@ int mm_sur_forward(mm_sur sur, const float *dm, float *dh, int normalize, void *
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
     sur_input(s, dm, normalize, st);
-    sur_forward(s, dh, st, true);
+    sur_forward(s, dh, st, true, false);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MM_OK : fail(MM_EHIP, std::string("surrogate forward: ") + hipGetErrorString(e));
 }
@@ -661,7 +708,7 @@ int mm_sur_gradients(mm_sur sur, const float *dm, const float *dh, int normalize
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
     sur_input(s, dm, normalize, st);
-    sur_forward(s, s.tmp2, st, false);
+    sur_forward(s, s.tmp2, st, false, true);
     int rc = sur_backward(s, dh, loss, st);
     if (rc != MM_OK || !grads) return rc;
     std::vector<float> g((size_t)NLAYER * layer_stride());
@@ -678,7 +725,7 @@ int mm_sur_train_step(mm_sur sur, const float *dm, const float *dh, float lr, in
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
     sur_input(s, dm, normalize, st);
-    sur_forward(s, s.tmp2, st, false);
+    sur_forward(s, s.tmp2, st, false, true);
     int rc = sur_backward(s, dh, loss, st);
     if (rc != MM_OK) return rc;
     s.adam_t += 1;
