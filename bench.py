@@ -140,7 +140,7 @@ def summarize_trace(workload, db):
     out = ["# kernel trace, %s (%dx%dx%d cells), rocprofv3 --kernel-trace" % ((workload,) + tuple(shape)),
            "# command (from /tmp on the GPU, REPO = repository root):",
            "#   rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof_%s -o %s -- python3 $REPO/bench.py "
-           "--workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs"
+           "--workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs --no-surrogate"
            % (workload, workload, workload),
            "#   python3 bench.py --summarize-trace %s $REPO/gpurun_out/prof_%s/%s_results.db" % (workload, workload, workload),
            "# durations in microseconds; tile = P + 256 * variant, for the stage kernel its vector width, with",
@@ -317,6 +317,84 @@ def batch_measure(torch, mm, W, steps=10, warmup=2):
             "bitwise_equal_to_looped": same}
 
 
+def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
+    """Learned form on the 256x256x4 film: a short online training on the
+    solver's own pairs (train_s seconds), then `steps` gated RK4 steps
+    (tolerance 1e-3, exact demag judging every accepted state) against the
+    same steps on the plain FP32 path, from the same held-out state; plus the
+    time of one network evaluation (6.07e10 FLOP, BF16 matrix cores)."""
+    import numpy as np
+    from paper_1406_7459_amd.surrogate_train import init_params
+    wl = W.film256(0)
+    nx, ny, nz = wl.shape
+    m = wl.mat
+    plan = mm.Plan(nx, ny, nz, *wl.cell)
+    plan.autotune(reps=3)
+    sur = mm.Surrogate(nx, ny, nz)
+    sur.set_params(init_params(6, 5000))
+    dm = torch.empty((3, nz, ny, nx), device="cuda")
+    dh = torch.empty_like(dm)
+    t0 = time.perf_counter()
+    pairs, traj, losses = 0, 0, []
+    while time.perf_counter() - t0 < train_s:
+        w = W.film256(traj)
+        p = mm.LLGParams.make(Ms=w.mat.Ms, A=w.mat.A, alpha=w.mat.alpha, gamma0=w.mat.gamma0, Hext=w.mat.Hext,
+                              dt=w.mat.dt)
+        M = torch.from_numpy((w.mat.Ms * w.initial_unit()).astype("float32")).cuda()
+        plan.step(p, M, 20)
+        for _ in range(100):
+            mm.Surrogate.make_pair(plan, p, M, 1, dm, dh)
+            frac = (time.perf_counter() - t0) / train_s
+            losses.append(sur.train_step(dm, dh, 3e-4 * 0.1 ** min(1.0, frac)))
+            pairs += 1
+            if time.perf_counter() - t0 >= train_s:
+                break
+        traj += 1
+    w = W.film256(900)
+    p = mm.LLGParams.make(Ms=w.mat.Ms, A=w.mat.A, alpha=w.mat.alpha, gamma0=w.mat.gamma0, Hext=w.mat.Hext,
+                          dt=w.mat.dt)
+    M0 = torch.from_numpy((w.mat.Ms * w.initial_unit()).astype("float32")).cuda()
+    plan.step(p, M0, 20)
+    Me = M0.clone()
+    plan.step(p, Me, 2)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.step(p, Me, steps)
+    torch.cuda.synchronize()
+    te = (time.perf_counter() - t1) / steps
+    Me = M0.clone()
+    plan.step(p, Me, steps)
+    Ms_ = M0.clone()
+    sur.step(plan, p, Ms_, 2, tol=1e-3)
+    Ms_ = M0.clone()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = sur.step(plan, p, Ms_, steps, tol=1e-3)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t1) / steps
+    err = float((Ms_ - Me).norm() / Me.norm())
+    x = torch.randn((3, nz, ny, nx), device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        sur.forward(x, y, normalize=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        sur.forward(x, y, normalize=True)
+    torch.cuda.synchronize()
+    inf = (time.perf_counter() - t1) / 20
+    sur.close()
+    plan.close()
+    return {"workload": "film256 (256x256x4, 4 nm, alpha 0.1, in-plane |mu0 H| <= 50 mT); pairs from the solver",
+            "training": {"seconds": train_s, "pairs": pairs, "loss_first": float(np.mean(losses[:20])),
+                         "loss_last": float(np.mean(losses[-20:]))},
+            "gated_steps": steps, "tol": 1e-3, "stats": st,
+            "exact_ms_per_step": te * 1e3, "surrogate_ms_per_step": ts * 1e3,
+            "speedup_vs_plain_fp32": te / ts, "state_rel_l2_vs_exact": err,
+            "inference_ms": inf * 1e3, "inference_tflops": 6.07e10 / inf / 1e12,
+            "inference_mfma_frac": 6.07e10 / inf / 2.5e15}
+
+
 def table1_euler(torch, mm, W):
     """Per-step time with explicit Euler on N^3 cubes, N = 8 ... 128 (the shape
     of the paper's Table 1; material of the cube workload)."""
@@ -391,6 +469,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-other-configs", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("WORKLOAD", "PMC_DIR"),
                     help="print the traffic summary of rocprofv3 counter databases and exit")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("WORKLOAD", "DB"),
@@ -576,6 +655,8 @@ def main():
         out["other_configs"] = other_configs(torch, mm, W)
     if not args.no_batch:
         out["batched"] = batch_measure(torch, mm, W)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_measure(torch, mm, W)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
