@@ -17,7 +17,10 @@ FULL = [("cube128", (128, 128, 128), (2e-9, 2e-9, 2e-9)),
         ("sweep-512x384x8", (512, 384, 8), (4e-9, 4e-9, 2e-9)),
         ("sweep-96x192x1", (96, 192, 1), (4e-9, 4e-9, 2e-9)),
         ("sweep-384x64x2", (384, 64, 2), (4e-9, 4e-9, 2e-9)),
-        ("film128", (128, 32, 1), (3.90625e-9, 3.90625e-9, 3e-9))]
+        ("film128", (128, 32, 1), (3.90625e-9, 3.90625e-9, 3e-9)),
+        # the largest supported axis (512 cells, transform length 1024) along z and y
+        ("max-z-16x8x512", (16, 8, 512), (2e-9, 2e-9, 2e-9)),
+        ("max-y-12x512x6", (12, 512, 6), (2e-9, 2e-9, 2e-9))]
 
 
 @pytest.mark.parametrize("name,grid,d", FULL)
