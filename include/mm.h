@@ -253,7 +253,8 @@ typedef struct {
     double last_residual, max_residual, sum_residual;  /* |H_s - H_d| / |H_d| */
 } mm_sur_stats;
 
-/* Network and training buffers for an nx x ny x nz grid; weights zero. */
+/* Network and training buffers for an nx x ny x nz grid of at most 2^25
+ * cells (MM_EINVAL otherwise, before any device work); weights zero. */
 int mm_sur_create(int nx, int ny, int nz, mm_sur *out);
 long long mm_sur_param_count(void);
 int mm_sur_set_params(mm_sur sur, const float *params, long long n);  /* host; resets Adam state */

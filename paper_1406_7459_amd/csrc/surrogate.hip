@@ -49,99 +49,170 @@ __device__ __forceinline__ float gelu_d(float x)
 }
 
 // EPI 0: hidden layer, Z = acc + b (FP32) and Xn = bf16(gelu(Z));
-// EPI 1: last layer, dh[co][cell] = scale * (acc + b) for co < 3 (SoA FP32);
+// EPI 1: last layer, dh[co][cell] = s * (acc + b) for co < 3 (SoA FP32),
+//        s = sig[0] if sig is given (device sigma) else scale;
 // EPI 2: raw Z = acc (input gradient, no bias);
 // EPI 3: hidden layer for inference only, Xn = bf16(gelu(acc + b)) (no Z).
 //
-// A wave computes CT = 4 column tiles of 16 cells (64 consecutive cells) for
-// all 32 output channels: per tap it reads the two 16x32 weight fragments
-// from LDS once and reuses them for the four tiles (eight MFMAs), so the LDS
-// traffic per MFMA is a quarter of a one-tile wave's and four independent
-// activation loads are in flight per tap.  Eight waves share one copy of the
-// layer's weights in LDS (55 KB), so two workgroups (sixteen waves) fit a CU.
-constexpr int CT = 4;
+// A wave owns a 16-cell run along x at one y and TZ = 4 consecutive z levels
+// (four column tiles), for all 32 output channels (two accumulators per
+// tile).  For each in-plane offset (dx, dy) it loads the six source rows
+// z0-1 .. z0+4 once and applies each to every output level it reaches
+// (dz = -1, 0, 1): 13.5 activation loads per tile instead of 27, and each
+// weight fragment read from LDS feeds up to eight MFMAs.  The loads of the
+// next offset are issued before the current offset's MFMAs.  A block at the
+// bottom (top) of the grid has no source row z0-1 (z0+4): that row is
+// neither loaded nor multiplied (separate instances of the task body, so
+// that the load counts stay static), and a 4-level film does 9 loads per
+// tile and 5/6 of the MFMAs of an interior block.  The last layer has 3
+// output channels: rows 16..31 of its weights are zero and are neither
+// staged nor multiplied.  Eight waves share one copy of the layer's weights
+// in LDS (55 KB, rows padded to stagger the banks), so two workgroups
+// (sixteen waves) fit a CU.
+constexpr int TZ = 4;
 constexpr int CONV_WAVES = 8;
+constexpr int WROW = NT * 4 + 1;  // 16-byte slots per output channel in LDS
 
-template <int EPI>
-__global__ __launch_bounds__(64 * CONV_WAVES) void k_conv(const __bf16 *__restrict__ X, const __bf16 *__restrict__ W,
-                                              const float *__restrict__ bias, float *__restrict__ Z,
-                                              __bf16 *__restrict__ Xn, float *__restrict__ dh, float scale, int nx,
-                                              int ny, int nz)
+// fragments travel as raw 16-byte words (a bf16 vector in a phi or a select
+// is repacked element by element) and become bf16 at the MFMA
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// One launch covers the z blocks zb0 .. zb0+nzbr-1 of one kind: ZLO (the
+// block starts at z = 0) and ZHI (it reaches the top level).
+template <int EPI, bool ZLO, bool ZHI>
+__global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_conv(
+    const __bf16 *__restrict__ X, const __bf16 *__restrict__ W, const float *__restrict__ bias, float *__restrict__ Z,
+    __bf16 *__restrict__ Xn, float *__restrict__ dh, float scale, const float *__restrict__ sig, int nx, int ny,
+    int nz, int zb0, int nzbr)
 {
-    __shared__ bf8 wl[SC * NT * (SC / 8)];
-    const bf8 *Wv = reinterpret_cast<const bf8 *>(W);
-    for (int i = threadIdx.x; i < SC * NT * (SC / 8); i += blockDim.x) wl[i] = Wv[i];
+    constexpr bool HALF = EPI == 1;
+    constexpr int NCO = HALF ? 16 : 32;
+    constexpr int J0 = ZLO ? 1 : 0, J1 = ZHI ? TZ + 1 : TZ + 2;  // source rows that exist
+    __shared__ u4 wl[NCO * WROW];
+    const u4 *Wv = reinterpret_cast<const u4 *>(W);
+    for (int i = threadIdx.x; i < NCO * NT * 4; i += blockDim.x) {
+        const int co = i / (NT * 4);
+        wl[co * WROW + (i - co * NT * 4)] = Wv[i];
+    }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index is uniform: read it into a scalar so that the task
+    // coordinates, the validity flags and the row offsets live in SGPRs
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int col = lane & 15, kq = lane >> 4;
-    const long long N = (long long)nx * ny * nz;
-    const long long ngroups = (N + 16 * CT - 1) / (16 * CT);
-    const bf8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (long long grp = (long long)blockIdx.x * CONV_WAVES + wv; grp < ngroups;
-         grp += (long long)gridDim.x * CONV_WAVES) {
-        long long cell[CT];
-        bool live[CT];
-        int ci[CT], cj[CT], ck[CT];
+    const int nxt = (nx + 15) >> 4;
+    const long long ntask = (long long)nxt * ny * nzbr;
+    const u4 zero = {0u, 0u, 0u, 0u};
+    const u4 *wa = wl + col * WROW + kq;
+    // raw buffer over the activations (byte size <= 2^31, checked by the host);
+    // an offset past the end reads as zero
+    const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<__bf16 *>(X), 0, (int)((long long)nx * ny * nz * SC * 2), 0x00020000);
+    const unsigned OUT_OF_RANGE = 0x80000000u;
+    // XCD-contiguous workgroup order: the rows y-1..y+1 and levels z0-1..z0+4
+    // a task reads were read by its neighbours in the same L2
+    for (long long task = (long long)xcd_block(blockIdx.x, gridDim.x) * CONV_WAVES + wv; task < ntask;
+         task += (long long)gridDim.x * CONV_WAVES) {
+        const int xt = (int)(task % nxt);
+        const long long rest = task / nxt;
+        const int y = (int)(rest % ny);
+        const int z0 = (zb0 + (int)(rest / ny)) * TZ;
+        const int x = xt * 16 + col;
+        // an index the compiler cannot see through keeps the weight reads
+        // inside the task loop (hoisted, 54 fragments would not fit the registers)
+        int wofs = 0;
+        asm volatile("" : "+v"(wofs));
+        const u4 *wt = wa + wofs;
+        f4 acc0[TZ], acc1[TZ];
 #pragma unroll
-        for (int u = 0; u < CT; ++u) {
-            cell[u] = (grp * CT + u) * 16 + col;
-            live[u] = cell[u] < N;
-            ci[u] = live[u] ? (int)(cell[u] % nx) : 0;
-            cj[u] = live[u] ? (int)((cell[u] / nx) % ny) : 0;
-            ck[u] = live[u] ? (int)(cell[u] / ((long long)nx * ny)) : 0;
-        }
-        f4 acc0[CT], acc1[CT];
-#pragma unroll
-        for (int u = 0; u < CT; ++u) {
+        for (int u = 0; u < TZ; ++u) {
             acc0[u] = f4{0.f, 0.f, 0.f, 0.f};
             acc1[u] = f4{0.f, 0.f, 0.f, 0.f};
         }
-        for (int t = 0; t < NT; ++t) {
-            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-            const bf8 a0 = wl[(col * NT + t) * 4 + kq];
-            const bf8 a1 = wl[((16 + col) * NT + t) * 4 + kq];
-            bf8 bv[CT];
+        // uniform validity of the source levels z0-1+j and the rows y-1..y+1;
+        // a row outside the grid loads as zero, so its MFMAs add nothing
+        bool vz[TZ + 2], vy[3];
 #pragma unroll
-            for (int u = 0; u < CT; ++u) {
-                const int ii = ci[u] + dx, jj = cj[u] + dy, kk = ck[u] + dz;
-                const bool in = live[u] && ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz;
-                bv[u] = in ? *reinterpret_cast<const bf8 *>(X + (((long long)kk * ny + jj) * nx + ii) * SC + 8 * kq)
-                           : zero8;
-            }
+        for (int j = 0; j < TZ + 2; ++j) vz[j] = z0 - 1 + j >= 0 && z0 - 1 + j < nz;
 #pragma unroll
-            for (int u = 0; u < CT; ++u) {
-                acc0[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv[u], acc0[u], 0, 0, 0);
-                acc1[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv[u], acc1[u], 0, 0, 0);
-            }
+        for (int d = 0; d < 3; ++d) vy[d] = y - 1 + d >= 0 && y - 1 + d < ny;
+        // byte offset of the lane's cell within a row, per dx; a lane whose
+        // neighbour lies outside the row reads past the end of the buffer
+        unsigned xo[3];
+        bool vx[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int xx = x - 1 + d;
+            vx[d] = xx >= 0 && xx < nx;
+            xo[d] = (unsigned)(xx * SC + 8 * kq) * 2u;
         }
+        const int rs = nx * SC, ps = rs * ny;  // elements per row and per level
+        // source rows of offset g = 3 (dy + 1) + (dx + 1), levels z0-1+j
+        auto fetch = [&](int g, u4 *s) {
+            const int dy = g / 3, dx = g % 3;
+#pragma unroll
+            for (int j = J0; j < J1; ++j) {
+                const bool ok = vy[dy] && vz[j] && vx[dx];
+                const unsigned row = (unsigned)((z0 - 1 + j) * ps + (y - 1 + dy) * rs) * 2u;
+                s[j] = __builtin_amdgcn_raw_buffer_load_b128(src, ok ? row + xo[dx] : OUT_OF_RANGE, 0, 0);
+            }
+        };
+        u4 cur[TZ + 2], nxt_s[TZ + 2];
+        fetch(0, cur);
+#pragma unroll
+        for (int g = 0; g < 9; ++g) {
+            if (g < 8) fetch(g + 1, nxt_s);
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int t = (dz + 1) * 9 + g;
+                const bf8 a0 = __builtin_bit_cast(bf8, wt[t * 4]);
+                const bf8 a1 = __builtin_bit_cast(bf8, HALF ? zero : wt[16 * WROW + t * 4]);
+#pragma unroll
+                for (int u = 0; u < TZ; ++u) {
+                    const int j = u + dz + 1;
+                    if (j < J0 || j >= J1) continue;
+                    const bf8 bv = __builtin_bit_cast(bf8, cur[j]);
+                    acc0[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, bv, acc0[u], 0, 0, 0);
+                    if (!HALF) acc1[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc1[u], 0, 0, 0);
+                }
+            }
+            if (g < 8) {
+#pragma unroll
+                for (int j = J0; j < J1; ++j) cur[j] = nxt_s[j];
+            }
+            // keep the prefetch one offset ahead (deeper would not fit the registers)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (x >= nx) continue;
         // lane holds D[co = 4 kq + r][cell] (acc0) and D[16 + 4 kq + r][cell] (acc1)
 #pragma unroll
-        for (int u = 0; u < CT; ++u) {
-            if (!live[u]) continue;
-            const long long c = cell[u];
+        for (int u = 0; u < TZ; ++u) {
+            if (z0 + u >= nz) break;
+            const long long c = ((long long)(z0 + u) * ny + y) * nx + x;
             if constexpr (EPI == 0 || EPI == 3) {
-                f4 z0, z1;
+                f4 z0v, z1v;
                 bf4 g0, g1;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    z0[r] = acc0[u][r] + bias[4 * kq + r];
-                    z1[r] = acc1[u][r] + bias[16 + 4 * kq + r];
-                    g0[r] = (__bf16)gelu_f(z0[r]);
-                    g1[r] = (__bf16)gelu_f(z1[r]);
+                    z0v[r] = acc0[u][r] + bias[4 * kq + r];
+                    z1v[r] = acc1[u][r] + bias[16 + 4 * kq + r];
+                    g0[r] = (__bf16)gelu_f(z0v[r]);
+                    g1[r] = (__bf16)gelu_f(z1v[r]);
                 }
                 if constexpr (EPI == 0) {
-                    *reinterpret_cast<f4 *>(Z + c * SC + 4 * kq) = z0;
-                    *reinterpret_cast<f4 *>(Z + c * SC + 16 + 4 * kq) = z1;
+                    *reinterpret_cast<f4 *>(Z + c * SC + 4 * kq) = z0v;
+                    *reinterpret_cast<f4 *>(Z + c * SC + 16 + 4 * kq) = z1v;
                 }
                 *reinterpret_cast<bf4 *>(Xn + c * SC + 4 * kq) = g0;
                 *reinterpret_cast<bf4 *>(Xn + c * SC + 16 + 4 * kq) = g1;
             } else if constexpr (EPI == 1) {
                 if (kq == 0) {
+                    const long long N = (long long)nx * ny * nz;
+                    const float s = sig ? sig[0] : scale;
 #pragma unroll
                     for (int r = 0; r < 3; ++r) {
                         const float z = acc0[u][r] + bias[r];
                         Z[c * SC + r] = z;
-                        dh[r * N + c] = scale * z;
+                        dh[r * N + c] = s * z;
                     }
                 }
             } else {
@@ -152,20 +223,20 @@ __global__ __launch_bounds__(64 * CONV_WAVES) void k_conv(const __bf16 *__restri
     }
 }
 
-// dm [3][N] FP32 (SoA) / scale -> bf16 channel-last [N][32], channels >= 3 zero
-__global__ __launch_bounds__(256) void k_to_cl(const float *__restrict__ dm, __bf16 *__restrict__ X, float inv, long long N)
+// dm [3][N] FP32 (SoA) * (1/sigma) -> channels 0..7 of bf16 channel-last
+// [N][32] (channels 3..7 zero; channels 8..31 are zeroed once at creation
+// and never written); sigma is read from device memory (the step driver
+// never synchronises for it)
+__global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm, __bf16 *__restrict__ X,
+                                                   const float *__restrict__ sig, long long N)
 {
+    const float inv = sig[1];
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
         bf8 v = {0, 0, 0, 0, 0, 0, 0, 0};
         v[0] = (__bf16)(dm[c] * inv);
         v[1] = (__bf16)(dm[N + c] * inv);
         v[2] = (__bf16)(dm[2 * N + c] * inv);
-        bf8 *o = reinterpret_cast<bf8 *>(X + c * SC);
-        o[0] = v;
-        const bf8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-        o[1] = z;
-        o[2] = z;
-        o[3] = z;
+        *reinterpret_cast<bf8 *>(X + c * SC) = v;
     }
 }
 
@@ -354,42 +425,24 @@ namespace mmk {
 
 // sigma = sqrt(sum / count) (1 if the sum is 0 or normalisation is off);
 // out[0] = sigma, out[1] = 1 / sigma
-__global__ void k_sigma(const double *__restrict__ part, int nb, double count, int normalize, float *__restrict__ out)
+__global__ __launch_bounds__(256) void k_sigma(const double *__restrict__ part, int nb, double count, int normalize,
+                                               float *__restrict__ out)
 {
-    if (threadIdx.x != 0) return;
+    // fixed-order tree over the partials (deterministic)
+    __shared__ double red[256];
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b];
-    double sg = normalize ? sqrt(s / count) : 1.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double sg = normalize ? sqrt(red[0] / count) : 1.0;
     if (!(sg > 0.0) || !isfinite(sg)) sg = 1.0;
     out[0] = (float)sg;
     out[1] = (float)(1.0 / sg);
-}
-
-// k_to_cl / last-layer scale read from device memory (the step driver never
-// synchronises for sigma)
-__global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm, __bf16 *__restrict__ X,
-                                                   const float *__restrict__ sig, long long N)
-{
-    const float inv = sig[1];
-    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
-        bf8 v = {0, 0, 0, 0, 0, 0, 0, 0};
-        v[0] = (__bf16)(dm[c] * inv);
-        v[1] = (__bf16)(dm[N + c] * inv);
-        v[2] = (__bf16)(dm[2 * N + c] * inv);
-        bf8 *o = reinterpret_cast<bf8 *>(X + c * SC);
-        o[0] = v;
-        const bf8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-        o[1] = z;
-        o[2] = z;
-        o[3] = z;
-    }
-}
-// dh *= sigma (device scalar), in place on [3][N]
-__global__ __launch_bounds__(256) void k_scale_dev(float *__restrict__ dh, const float *__restrict__ sig, long long n)
-{
-    const float s = sig[0];
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
-        dh[e] *= s;
 }
 
 struct Sur {
@@ -441,10 +494,28 @@ static void refresh(Sur &s, hipStream_t st)
 
 static unsigned grid_for(long long n) { return (unsigned)std::min<long long>((n + 255) / 256, 4096); }
 
-// workgroups of a convolution launch: CONV_WAVES waves, CT tiles of 16 cells each
-static unsigned conv_grid(long long N)
+// A convolution over the whole grid: one launch per kind of z block (bottom,
+// interior, top; a single launch when one block spans the thickness), each
+// with CONV_WAVES waves per workgroup and one (16-cell x run, y, TZ-level z
+// block) task per wave and pass.
+template <int EPI>
+static void launch_conv(const Sur &s, hipStream_t st, const __bf16 *X, const __bf16 *W, const float *bias, float *Z,
+                        __bf16 *Xn, float *dh, const float *sig)
 {
-    return (unsigned)std::min<long long>(((N + 16 * CT - 1) / (16 * CT) + CONV_WAVES - 1) / CONV_WAVES, 4096);
+    const int nzb = (s.nz + TZ - 1) / TZ;
+    auto go = [&](auto kern, int zb0, int nzbr) {
+        const long long tasks = (long long)((s.nx + 15) / 16) * s.ny * nzbr;
+        const unsigned gb = (unsigned)std::min<long long>((tasks + CONV_WAVES - 1) / CONV_WAVES, 8192);
+        hipLaunchKernelGGL(kern, dim3(gb), dim3(64 * CONV_WAVES), 0, st, X, W, bias, Z, Xn, dh, 1.f, sig, s.nx, s.ny,
+                           s.nz, zb0, nzbr);
+    };
+    if (nzb == 1) {
+        go(k_conv<EPI, true, true>, 0, 1);
+        return;
+    }
+    go(k_conv<EPI, true, false>, 0, 1);
+    if (nzb > 2) go(k_conv<EPI, false, false>, 1, nzb - 2);
+    go(k_conv<EPI, false, true>, nzb - 1, 1);
 }
 
 // forward of the whole stack on X[0] (already filled); last layer -> dh.
@@ -452,28 +523,23 @@ static unsigned conv_grid(long long N)
 // backward pass; inference skips them).
 static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool keep_z)
 {
-    const unsigned gb = conv_grid(s.N);
     for (int l = 0; l < NLAYER; ++l) {
         const __bf16 *W = s.wb + (long long)l * WSZ;
         const float *b = s.w + l * layer_stride() + WSZ;
         if (l < NLAYER - 1 && keep_z)
-            hipLaunchKernelGGL(k_conv<0>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, 1.f,
-                               s.nx, s.ny, s.nz);
+            launch_conv<0>(s, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, nullptr);
         else if (l < NLAYER - 1)
-            hipLaunchKernelGGL(k_conv<3>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, 1.f,
-                               s.nx, s.ny, s.nz);
-        else
-            hipLaunchKernelGGL(k_conv<1>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.X[l], W, b, s.Z[l], nullptr, dh, 1.f, s.nx,
-                               s.ny, s.nz);
+            launch_conv<3>(s, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, nullptr);
+        else  // dh = sigma * Net(...) with sigma from device memory when dev_scale
+            launch_conv<1>(s, st, s.X[l], W, b, s.Z[l], nullptr, dh, dev_scale ? s.sig : nullptr);
     }
-    if (dev_scale) hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(3 * s.N)), dim3(256), 0, st, dh, s.sig, 3 * s.N);
 }
 
 // sigma of dm (normalize) into s.sig, and X[0] = bf16(dm / sigma)
 static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st)
 {
     hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, dm, nullptr, s.dpart, 3 * s.N);
-    hipLaunchKernelGGL(k_sigma, dim3(1), dim3(64), 0, st, s.dpart, RED_B, (double)(3 * s.N), normalize, s.sig);
+    hipLaunchKernelGGL(k_sigma, dim3(1), dim3(256), 0, st, s.dpart, RED_B, (double)(3 * s.N), normalize, s.sig);
     hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.sig, s.N);
 }
 
@@ -488,7 +554,6 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
                        s.N);
     std::vector<double> hp(RED_B);
     MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * RED_B, hipMemcpyDeviceToHost, st));
-    const unsigned gb = conv_grid(s.N);
     for (int l = NLAYER - 1; l >= 0; --l) {
         hipLaunchKernelGGL(k_conv_dw, dim3(s.nchunk), dim3(256), 0, st, s.dZ, s.X[l], s.part, s.bpart, s.nx, s.ny, s.nz,
                            s.chunk);
@@ -496,8 +561,7 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
         hipLaunchKernelGGL(k_sum_chunks, dim3((WSZ + 255) / 256), dim3(256), 0, st, s.part, s.nchunk, WSZ, gl);
         hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, st, s.bpart, s.nchunk, SC, gl + WSZ);
         if (l > 0) {
-            hipLaunchKernelGGL(k_conv<2>, dim3(gb), dim3(64 * CONV_WAVES), 0, st, s.dZb, s.wt + (long long)l * WSZ, nullptr, s.dX,
-                               nullptr, nullptr, 1.f, s.nx, s.ny, s.nz);
+            launch_conv<2>(s, st, s.dZb, s.wt + (long long)l * WSZ, nullptr, s.dX, nullptr, nullptr, nullptr);
             hipLaunchKernelGGL(k_gelu_back, dim3(grid_for(s.N * SC)), dim3(256), 0, st, s.dX, s.Z[l - 1], s.dZ, s.dZb,
                                s.N * SC);
         }
@@ -582,7 +646,10 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
 {
     if (!out) return fail(MM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > (1LL << 28)) return fail(MM_EINVAL, "surrogate grid");
+    // the convolution addresses the bf16 activations ([cell][32], 64 bytes a
+    // cell) with 32-bit buffer offsets below 2^31: at most 2^25 cells
+    if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz > (1LL << 25))
+        return fail(MM_EINVAL, "surrogate grid: need 1 <= nx, ny, nz and nx*ny*nz <= 2^25");
     Sur *s = new Sur();
     s->nx = nx;
     s->ny = ny;
@@ -619,6 +686,9 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
         if (e == hipSuccess) e = hipMemset(s->m, 0, P * 4);
         if (e == hipSuccess) e = hipMemset(s->v, 0, P * 4);
         if (e == hipSuccess) e = hipMemset(s->g, 0, P * 4);
+        // channels 8..31 of the network input stay zero (the input
+        // conversion writes channels 0..7 only)
+        if (e == hipSuccess) e = hipMemset(s->X[0], 0, (size_t)s->N * SC * 2);
         if (e != hipSuccess) rc = fail(MM_EHIP, "surrogate init");
         refresh(*s, nullptr);
         if (hipDeviceSynchronize() != hipSuccess) rc = fail(MM_EHIP, "surrogate init sync");

@@ -58,6 +58,14 @@ def test_setup_rejects_bad_grid_before_device_work(L, args):
     assert L.mm_last_error(buf, 256) > 0 and buf.value
 
 
+@pytest.mark.parametrize("grid", [(0, 4, 4), (4, 0, 4), (4, 4, -1), (512, 256, 257)])
+def test_surrogate_rejects_bad_grid_before_device_work(L, grid):
+    from paper_1406_7459_amd import mm
+    h = C.c_void_p(123)
+    assert L.mm_sur_create(*grid, C.byref(h)) == mm.MM_EINVAL
+    assert h.value is None
+
+
 def test_null_arguments_are_rejected(L):
     from paper_1406_7459_amd import mm
     assert L.mm_demag_setup(4, 4, 4, 1e-9, 1e-9, 1e-9, None) == mm.MM_EINVAL

@@ -44,7 +44,7 @@ def ref_params(seed):
     return out
 
 
-@pytest.mark.parametrize("grid", [(16, 12, 4), (10, 6, 3), (33, 5, 2)])
+@pytest.mark.parametrize("grid", [(16, 12, 4), (10, 6, 3), (33, 5, 2), (20, 7, 9), (48, 3, 6)])
 def test_forward_matches_reference(grid):
     from paper_1406_7459_amd import mm
     nx, ny, nz = grid
