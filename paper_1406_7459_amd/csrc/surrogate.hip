@@ -51,7 +51,9 @@ __device__ __forceinline__ float gelu_d(float x)
 // EPI 0: hidden layer, Z = acc + b (FP32) and Xn = bf16(gelu(Z));
 // EPI 1: last layer, dh[co][cell] = s * (acc + b) for co < 3 (SoA FP32),
 //        s = sig[0] if sig is given (device sigma) else scale;
-// EPI 2: raw Z = acc (input gradient, no bias);
+// EPI 2: input gradient fused with the GELU derivative of the layer below:
+//        dZ_prev = acc * gelu'(Zp) with Zp = Z (read, the pre-activations of
+//        the layer below), written as bf16 cell-major Xn and channel-major Xt;
 // EPI 3: hidden layer for inference only, Xn = bf16(gelu(acc + b)) (no Z).
 //
 // A wave owns a 16-cell run along x at one y and TZ = 4 consecutive z levels
@@ -77,13 +79,38 @@ constexpr int WROW = NT * 4 + 1;  // 16-byte slots per output channel in LDS
 // is repacked element by element) and become bf16 at the MFMA
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
+// Channel-major, zero-padded copies of the layer inputs and of dZ, kept for
+// the weight gradient (training only).  Element (ch, x, y, z) sits at
+// ch * G + f + (z + 1) pl + y xp + x with xp = roundup(nx + 1, 8) (a zero
+// after every row), pl = (ny + 1) xp (a zero row after every level), a zero
+// level below and above the grid and at least xp + 8 zeros at both ends:
+// every neighbour of every cell and of every padding cell lies inside the
+// buffer, the ones outside the grid read zero, and rows start on 16 bytes.
+struct PadGeom {
+    int xp, pl, f;
+    long long G;  // elements per channel, a multiple of 8
+};
+static inline PadGeom pad_geom(int nx, int ny, int nz)
+{
+    PadGeom g;
+    g.xp = (nx + 1 + 7) & ~7;
+    g.pl = (ny + 1) * g.xp;
+    g.f = g.xp + 8;
+    g.G = ((long long)g.f + (long long)(nz + 2) * g.pl + g.xp + 80 + 7) & ~7LL;
+    return g;
+}
+__device__ __forceinline__ long long pad_at(const PadGeom &g, int x, int y, int z)
+{
+    return g.f + (long long)(z + 1) * g.pl + (long long)y * g.xp + x;
+}
+
 // One launch covers the z blocks zb0 .. zb0+nzbr-1 of one kind: ZLO (the
 // block starts at z = 0) and ZHI (it reaches the top level).
 template <int EPI, bool ZLO, bool ZHI>
 __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_conv(
     const __bf16 *__restrict__ X, const __bf16 *__restrict__ W, const float *__restrict__ bias, float *__restrict__ Z,
     __bf16 *__restrict__ Xn, float *__restrict__ dh, float scale, const float *__restrict__ sig, int nx, int ny,
-    int nz, int zb0, int nzbr)
+    int nz, int zb0, int nzbr, __bf16 *__restrict__ Xt, PadGeom pg)
 {
     constexpr bool HALF = EPI == 1;
     constexpr int NCO = HALF ? 16 : 32;
@@ -198,9 +225,15 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                     g0[r] = (__bf16)gelu_f(z0v[r]);
                     g1[r] = (__bf16)gelu_f(z1v[r]);
                 }
-                if constexpr (EPI == 0) {
+                if constexpr (EPI == 0) {  // training: pre-activations and the channel-major copy
                     *reinterpret_cast<f4 *>(Z + c * SC + 4 * kq) = z0v;
                     *reinterpret_cast<f4 *>(Z + c * SC + 16 + 4 * kq) = z1v;
+                    const long long pc = pad_at(pg, x, y, z0 + u);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        Xt[(long long)(4 * kq + r) * pg.G + pc] = g0[r];
+                        Xt[(long long)(16 + 4 * kq + r) * pg.G + pc] = g1[r];
+                    }
                 }
                 *reinterpret_cast<bf4 *>(Xn + c * SC + 4 * kq) = g0;
                 *reinterpret_cast<bf4 *>(Xn + c * SC + 16 + 4 * kq) = g1;
@@ -216,8 +249,22 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                     }
                 }
             } else {
-                *reinterpret_cast<f4 *>(Z + c * SC + 4 * kq) = acc0[u];
-                *reinterpret_cast<f4 *>(Z + c * SC + 16 + 4 * kq) = acc1[u];
+                const f4 z0v = *reinterpret_cast<const f4 *>(Z + c * SC + 4 * kq);
+                const f4 z1v = *reinterpret_cast<const f4 *>(Z + c * SC + 16 + 4 * kq);
+                bf4 g0, g1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    g0[r] = (__bf16)(acc0[u][r] * gelu_d(z0v[r]));
+                    g1[r] = (__bf16)(acc1[u][r] * gelu_d(z1v[r]));
+                }
+                *reinterpret_cast<bf4 *>(Xn + c * SC + 4 * kq) = g0;
+                *reinterpret_cast<bf4 *>(Xn + c * SC + 16 + 4 * kq) = g1;
+                const long long pc = pad_at(pg, x, y, z0 + u);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    Xt[(long long)(4 * kq + r) * pg.G + pc] = g0[r];
+                    Xt[(long long)(16 + 4 * kq + r) * pg.G + pc] = g1[r];
+                }
             }
         }
     }
@@ -227,8 +274,10 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
 // [N][32] (channels 3..7 zero; channels 8..31 are zeroed once at creation
 // and never written); sigma is read from device memory (the step driver
 // never synchronises for it)
+// (training: also channels 0..2 of the channel-major copy Xt)
 __global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm, __bf16 *__restrict__ X,
-                                                   const float *__restrict__ sig, long long N)
+                                                   const float *__restrict__ sig, long long N, __bf16 *__restrict__ Xt,
+                                                   PadGeom pg, int nx, int ny)
 {
     const float inv = sig[1];
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
@@ -237,14 +286,20 @@ __global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm,
         v[1] = (__bf16)(dm[N + c] * inv);
         v[2] = (__bf16)(dm[2 * N + c] * inv);
         *reinterpret_cast<bf8 *>(X + c * SC) = v;
+        if (Xt) {
+            const long long pc = pad_at(pg, (int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long long)nx * ny)));
+#pragma unroll
+            for (int r = 0; r < 3; ++r) Xt[r * pg.G + pc] = v[r];
+        }
     }
 }
 
-// last-layer gradient: dZ = 2 (z - target/scale) / (3N) on co < 3; squared
+// last-layer gradient: dZ = 2 (z - target/scale) / (3N) on co < 3 (zero on the
+// padded channels), as bf16 cell-major dZb and channel-major dZt; squared
 // error partials (FP64) per block
 __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const float *__restrict__ tgt, float inv,
-                                             float *__restrict__ dZ, __bf16 *__restrict__ dZb, double *__restrict__ part,
-                                             long long N)
+                                             __bf16 *__restrict__ dZb, __bf16 *__restrict__ dZt, PadGeom pg,
+                                             double *__restrict__ part, int nx, int ny, long long N)
 {
     double s = 0.0;
     const float w = 2.f / (3.f * (float)N);
@@ -258,10 +313,11 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const 
             s += (double)d * d;
             g[r] = w * d;
         }
+        const long long pc = pad_at(pg, (int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long long)nx * ny)));
 #pragma unroll
         for (int q = 0; q < SC; ++q) {
-            dZ[c * SC + q] = g[q];
             dZb[c * SC + q] = (__bf16)g[q];
+            dZt[q * pg.G + pc] = (__bf16)g[q];
         }
     }
 #pragma unroll
@@ -272,65 +328,122 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const 
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// dZ_prev = dX * gelu'(Z_prev), FP32 and bf16 copies
-__global__ __launch_bounds__(256) void k_gelu_back(const float *__restrict__ dX, const float *__restrict__ Zp,
-                                                   float *__restrict__ dZ, __bf16 *__restrict__ dZb, long long n)
+// Weight and bias gradient partials of one layer on the matrix cores:
+//   part[block][co][t][ci] = sum_cells dZ[cell][co] X[cell + off(t)][ci],
+//   part[block][WSZ + co] = sum_cells dZ[cell][co]
+// (each workgroup's row has the layout of one layer's parameters).
+// The reduction runs over cells, so the MFMA's K is 32 consecutive cells of
+// the channel-major padded copies (one 16-byte load per lane gives a
+// fragment): A = dZt rows (16 output channels), B = Xt rows (16 input
+// channels) at the source row of (dy, dz).  The dx = -1 and +1 fragments are
+// the dx = 0 one shifted by one cell, funnel-shifted from the 16-byte load and
+// its neighbouring dwords.  A wave owns one (co half, ci half) for all 27
+// taps (27 accumulators); four waves cover the 32 x 32 block, and the two
+// groups of four in a workgroup take alternate runs and meet in LDS.
+// Padding cells carry dZ = 0, so whole runs need no masks.
+constexpr int DW_BLOCKS = 256;
+__global__ __launch_bounds__(512) void k_conv_dw(const __bf16 *__restrict__ dZt, const __bf16 *__restrict__ Xt,
+                                                 float *__restrict__ part, PadGeom pg, int nruns)
 {
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        const float g = dX[e] * gelu_d(Zp[e]);
-        dZ[e] = g;
-        dZb[e] = (__bf16)g;
-    }
-}
-
-// Weight and bias gradient partials of one layer over a chunk of cells:
-// part[chunk][t][co][ci] = sum_cells dZ[cell][co] X[cell + off(t)][ci], and
-// bpart[chunk][co] = sum_cells dZ[cell][co].  Thread (co, ci group of 4).
-__global__ __launch_bounds__(256) void k_conv_dw(const float *__restrict__ dZ, const __bf16 *__restrict__ X,
-                                                 float *__restrict__ part, float *__restrict__ bpart, int nx, int ny,
-                                                 int nz, int chunk)
-{
-    const int co = threadIdx.x >> 3, cg = threadIdx.x & 7;
-    const long long N = (long long)nx * ny * nz;
-    const long long c0 = (long long)blockIdx.x * chunk;
-    const long long c1 = c0 + chunk < N ? c0 + chunk : N;
-    float acc[NT][4];
+    __shared__ f4 red[4][14][64];
+    __shared__ float bred[2][2][4][16];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = w & 1, gq = (w >> 1) & 1, grp = w >> 2;
+    const int m = lane & 15, kq = lane >> 4;
+    const __bf16 *A = dZt + (long long)(16 * h + m) * pg.G + 8 * kq;
+    const __bf16 *B = Xt + (long long)(16 * gq + m) * pg.G + 8 * kq;
+    f4 acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (int r = blockIdx.x * 2 + grp; r < nruns; r += gridDim.x * 2) {
+        const long long p = (long long)pg.f + pg.pl + 32LL * r;
+        const u4 a = *reinterpret_cast<const u4 *>(A + p);
+        if (gq == 0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
-    float bacc = 0.f;
-    for (long long c = c0; c < c1; ++c) {
-        const float d = dZ[c * SC + co];
-        bacc += d;
-        const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((long long)nx * ny));
+            for (int i = 0; i < 4; ++i)
+                bsum += __uint_as_float(a[i] << 16) + __uint_as_float(a[i] & 0xffff0000u);
+        }
+        const bf8 av = __builtin_bit_cast(bf8, a);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int ii = i + t % 3 - 1, jj = j + (t / 3) % 3 - 1, kk = k + t / 9 - 1;
-            if (ii >= 0 && ii < nx && jj >= 0 && jj < ny && kk >= 0 && kk < nz) {
-                const bf4 x = *reinterpret_cast<const bf4 *>(X + (((long long)kk * ny + jj) * nx + ii) * SC + 4 * cg);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[t][r] += d * (float)x[r];
-            }
+        for (int sr = 0; sr < 9; ++sr) {
+            const int dz = sr / 3 - 1, dy = sr % 3 - 1;
+            const __bf16 *s = B + p + (long long)dz * pg.pl + (long long)dy * pg.xp;
+            const u4 c = *reinterpret_cast<const u4 *>(s);
+            const unsigned lo = *reinterpret_cast<const unsigned *>(s - 2);  // cells -2, -1
+            const unsigned hi = *reinterpret_cast<const unsigned *>(s + 8);  // cells 8, 9
+            const u4 bm = {__builtin_amdgcn_alignbit(c[0], lo, 16), __builtin_amdgcn_alignbit(c[1], c[0], 16),
+                           __builtin_amdgcn_alignbit(c[2], c[1], 16), __builtin_amdgcn_alignbit(c[3], c[2], 16)};
+            const u4 bp = {__builtin_amdgcn_alignbit(c[1], c[0], 16), __builtin_amdgcn_alignbit(c[2], c[1], 16),
+                           __builtin_amdgcn_alignbit(c[3], c[2], 16), __builtin_amdgcn_alignbit(hi, c[3], 16)};
+            const int t0 = (dz + 1) * 9 + (dy + 1) * 3;
+            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, bm), acc[t0], 0, 0, 0);
+            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, c), acc[t0 + 1], 0, 0, 0);
+            acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, bp), acc[t0 + 2], 0, 0, 0);
         }
     }
-    float *o = part + (long long)blockIdx.x * WSZ;
+    // group 1 hands its accumulators to group 0 through LDS, in two halves
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int half = 0; half < 2; ++half) {
+        const int t0 = half * 14, nt = half ? NT - 14 : 14;
+        if (grp == 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) o[(co * NT + t) * SC + 4 * cg + r] = acc[t][r];
-    if (cg == 0) bpart[(long long)blockIdx.x * SC + co] = bacc;
+            for (int i = 0; i < 14; ++i)
+                if (i < nt) red[w & 3][i][lane] = acc[t0 + i];
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+            for (int i = 0; i < 14; ++i)
+                if (i < nt) acc[t0 + i] += red[w][i][lane];
+        }
+        __syncthreads();
+    }
+    if (gq == 0) bred[grp][h][kq][m] = bsum;
+    __syncthreads();
+    if (grp == 0) {
+        // lane holds D[co = 16 h + 4 kq + i][ci = 16 gq + m]
+        float *o = part + (long long)blockIdx.x * (WSZ + SC);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[((16 * h + 4 * kq + i) * NT + t) * SC + 16 * gq + m] = acc[t][i];
+    }
+    if (threadIdx.x < SC) {
+        const int co = threadIdx.x, hh = co >> 4, mm = co & 15;
+        float b = 0.f;
+#pragma unroll
+        for (int g2 = 0; g2 < 2; ++g2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b += bred[g2][hh][q][mm];
+        part[(long long)blockIdx.x * (WSZ + SC) + WSZ + co] = b;
+    }
 }
 
-// fixed-order sum over chunks: g[e] = sum_b part[b][e]
+// fixed-order sum over chunks: g[e] = sum_b part[b][e].  A workgroup takes 64
+// elements; its four waves sum a quarter of the chunks each (eight loads in
+// flight per lane) and the quarters are added in order.
 __global__ __launch_bounds__(256) void k_sum_chunks(const float *__restrict__ part, int nchunk, int n,
                                                     float *__restrict__ g)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+    __shared__ double q[4][64];
+    const int e = blockIdx.x * 64 + (threadIdx.x & 63), w = threadIdx.x >> 6;
+    const int per = (nchunk + 3) / 4, b0 = w * per, b1 = min(nchunk, b0 + per);
     double s = 0.0;
-    for (int b = 0; b < nchunk; ++b) s += part[(long long)b * n + e];
-    g[e] = (float)s;
+    if (e < n) {
+        int b = b0;
+        for (; b + 8 <= b1; b += 8) {
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = part[(long long)(b + i) * n + e];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) s += v[i];
+        }
+        for (; b < b1; ++b) s += part[(long long)b * n + e];
+    }
+    q[w][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (w == 0 && e < n) g[e] = (float)(((q[0][threadIdx.x] + q[1][threadIdx.x]) + q[2][threadIdx.x]) + q[3][threadIdx.x]);
 }
 
 // Adam on FP32 masters, then refresh the bf16 forward weights [co][t][ci]
@@ -453,10 +566,11 @@ struct Sur {
     __bf16 *wb = nullptr, *wt = nullptr;  // bf16 forward / mirrored-transposed copies
     __bf16 *X[NLAYER] = {};               // layer inputs, [N][32]
     float *Z[NLAYER] = {};                // pre-activations, [N][32]
-    float *dZ = nullptr, *dX = nullptr;   // [N][32]
-    __bf16 *dZb = nullptr;
-    float *part = nullptr, *bpart = nullptr;  // weight/bias gradient partials
-    int nchunk = 0, chunk = 0;
+    __bf16 *dZb[2] = {};                  // [N][32], this layer's dZ and the one below
+    PadGeom pg;                           // channel-major padded copies (training)
+    __bf16 *Xt[NLAYER] = {};              // layer inputs, [32][G]
+    __bf16 *dZt = nullptr;                // [32][G]
+    float *part = nullptr;                // weight/bias gradient partials, [workgroup][layer_stride]
     double *dpart = nullptr;              // FP64 reduction partials
     float *sig = nullptr;                 // device sigma, 1/sigma
     float *tmp = nullptr, *tmp2 = nullptr;  // [3][N] scratch
@@ -500,14 +614,14 @@ static unsigned grid_for(long long n) { return (unsigned)std::min<long long>((n 
 // block) task per wave and pass.
 template <int EPI>
 static void launch_conv(const Sur &s, hipStream_t st, const __bf16 *X, const __bf16 *W, const float *bias, float *Z,
-                        __bf16 *Xn, float *dh, const float *sig)
+                        __bf16 *Xn, float *dh, const float *sig, __bf16 *Xt = nullptr)
 {
     const int nzb = (s.nz + TZ - 1) / TZ;
     auto go = [&](auto kern, int zb0, int nzbr) {
         const long long tasks = (long long)((s.nx + 15) / 16) * s.ny * nzbr;
         const unsigned gb = (unsigned)std::min<long long>((tasks + CONV_WAVES - 1) / CONV_WAVES, 8192);
         hipLaunchKernelGGL(kern, dim3(gb), dim3(64 * CONV_WAVES), 0, st, X, W, bias, Z, Xn, dh, 1.f, sig, s.nx, s.ny,
-                           s.nz, zb0, nzbr);
+                           s.nz, zb0, nzbr, Xt, s.pg);
     };
     if (nzb == 1) {
         go(k_conv<EPI, true, true>, 0, 1);
@@ -527,7 +641,7 @@ static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool 
         const __bf16 *W = s.wb + (long long)l * WSZ;
         const float *b = s.w + l * layer_stride() + WSZ;
         if (l < NLAYER - 1 && keep_z)
-            launch_conv<0>(s, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, nullptr);
+            launch_conv<0>(s, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, nullptr, s.Xt[l + 1]);
         else if (l < NLAYER - 1)
             launch_conv<3>(s, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, nullptr);
         else  // dh = sigma * Net(...) with sigma from device memory when dev_scale
@@ -536,11 +650,13 @@ static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool 
 }
 
 // sigma of dm (normalize) into s.sig, and X[0] = bf16(dm / sigma)
-static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st)
+// (train: also the channel-major copy Xt[0] for the weight gradient)
+static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st, bool train = false)
 {
     hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, dm, nullptr, s.dpart, 3 * s.N);
     hipLaunchKernelGGL(k_sigma, dim3(1), dim3(256), 0, st, s.dpart, RED_B, (double)(3 * s.N), normalize, s.sig);
-    hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.sig, s.N);
+    hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.sig, s.N,
+                       train ? s.Xt[0] : nullptr, s.pg, s.nx, s.ny);
 }
 
 // loss and gradients into s.g (masters' layout); returns the loss on the host
@@ -550,20 +666,22 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
     float sg[2];
     MMK_HIP(hipMemcpyAsync(sg, s.sig, sizeof(sg), hipMemcpyDeviceToHost, st));
     MMK_HIP(hipStreamSynchronize(st));
-    hipLaunchKernelGGL(k_mse, dim3(RED_B), dim3(256), 0, st, s.Z[NLAYER - 1], dh_target, sg[1], s.dZ, s.dZb, s.dpart,
-                       s.N);
+    hipLaunchKernelGGL(k_mse, dim3(RED_B), dim3(256), 0, st, s.Z[NLAYER - 1], dh_target, sg[1], s.dZb[0], s.dZt, s.pg,
+                       s.dpart, s.nx, s.ny, s.N);
     std::vector<double> hp(RED_B);
     MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * RED_B, hipMemcpyDeviceToHost, st));
     for (int l = NLAYER - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(k_conv_dw, dim3(s.nchunk), dim3(256), 0, st, s.dZ, s.X[l], s.part, s.bpart, s.nx, s.ny, s.nz,
-                           s.chunk);
-        float *gl = s.g + l * layer_stride();
-        hipLaunchKernelGGL(k_sum_chunks, dim3((WSZ + 255) / 256), dim3(256), 0, st, s.part, s.nchunk, WSZ, gl);
-        hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, st, s.bpart, s.nchunk, SC, gl + WSZ);
+        const int nruns = (int)(((long long)s.nz * s.pg.pl + 31) / 32);
+        hipLaunchKernelGGL(k_conv_dw, dim3(DW_BLOCKS), dim3(512), 0, st, s.dZt, s.Xt[l], s.part, s.pg, nruns);
+        const int ls = (int)layer_stride();
+        hipLaunchKernelGGL(k_sum_chunks, dim3((ls + 63) / 64), dim3(256), 0, st, s.part, DW_BLOCKS, ls,
+                           s.g + l * layer_stride());
         if (l > 0) {
-            launch_conv<2>(s, st, s.dZb, s.wt + (long long)l * WSZ, nullptr, s.dX, nullptr, nullptr, nullptr);
-            hipLaunchKernelGGL(k_gelu_back, dim3(grid_for(s.N * SC)), dim3(256), 0, st, s.dX, s.Z[l - 1], s.dZ, s.dZb,
-                               s.N * SC);
+            // dZ of layer l-1 into the other dZb buffer (the convolution still
+            // reads this one) and into dZt, whose weight gradient has run
+            const int cur = (NLAYER - 1 - l) & 1;
+            launch_conv<2>(s, st, s.dZb[cur], s.wt + (long long)l * WSZ, nullptr, s.Z[l - 1], s.dZb[cur ^ 1], nullptr,
+                           nullptr, s.dZt);
         }
     }
     MMK_HIP(hipStreamSynchronize(st));
@@ -655,8 +773,7 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
     s->ny = ny;
     s->nz = nz;
     s->N = (long long)nx * ny * nz;
-    s->chunk = 256;
-    s->nchunk = (int)((s->N + s->chunk - 1) / s->chunk);
+    s->pg = pad_geom(nx, ny, nz);
     const size_t P = (size_t)NLAYER * layer_stride();
     int rc = MM_OK;
     rc = rc ? rc : sur_alloc(*s, (void **)&s->w, P * 4);
@@ -668,12 +785,12 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
     for (int l = 0; l < NLAYER && rc == MM_OK; ++l) {
         rc = sur_alloc(*s, (void **)&s->X[l], (size_t)s->N * SC * 2);
         if (rc == MM_OK) rc = sur_alloc(*s, (void **)&s->Z[l], (size_t)s->N * SC * 4);
+        if (rc == MM_OK) rc = sur_alloc(*s, (void **)&s->Xt[l], (size_t)s->pg.G * SC * 2);
     }
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZ, (size_t)s->N * SC * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dX, (size_t)s->N * SC * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb, (size_t)s->N * SC * 2);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->part, (size_t)s->nchunk * WSZ * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->bpart, (size_t)s->nchunk * SC * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZt, (size_t)s->pg.G * SC * 2);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[0], (size_t)s->N * SC * 2);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[1], (size_t)s->N * SC * 2);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->part, (size_t)DW_BLOCKS * layer_stride() * 4);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dpart, (size_t)2 * RED_B * 8);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->sig, 16);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->tmp, (size_t)3 * s->N * 4);
@@ -689,6 +806,9 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
         // channels 8..31 of the network input stay zero (the input
         // conversion writes channels 0..7 only)
         if (e == hipSuccess) e = hipMemset(s->X[0], 0, (size_t)s->N * SC * 2);
+        // the padded copies are zero outside the grid's cells and stay so
+        for (int l = 0; l < NLAYER && e == hipSuccess; ++l) e = hipMemset(s->Xt[l], 0, (size_t)s->pg.G * SC * 2);
+        if (e == hipSuccess) e = hipMemset(s->dZt, 0, (size_t)s->pg.G * SC * 2);
         if (e != hipSuccess) rc = fail(MM_EHIP, "surrogate init");
         refresh(*s, nullptr);
         if (hipDeviceSynchronize() != hipSuccess) rc = fail(MM_EHIP, "surrogate init sync");
@@ -777,7 +897,7 @@ int mm_sur_gradients(mm_sur sur, const float *dm, const float *dh, int normalize
     if (grads && n != oracle_param_count()) return fail(MM_EINVAL, "gradient count");
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
-    sur_input(s, dm, normalize, st);
+    sur_input(s, dm, normalize, st, true);
     sur_forward(s, s.tmp2, st, false, true);
     int rc = sur_backward(s, dh, loss, st);
     if (rc != MM_OK || !grads) return rc;
@@ -794,7 +914,7 @@ int mm_sur_train_step(mm_sur sur, const float *dm, const float *dh, float lr, in
     if (!(lr > 0.f)) return fail(MM_EINVAL, "learning rate must be > 0");
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
-    sur_input(s, dm, normalize, st);
+    sur_input(s, dm, normalize, st, true);
     sur_forward(s, s.tmp2, st, false, true);
     int rc = sur_backward(s, dh, loss, st);
     if (rc != MM_OK) return rc;
