@@ -46,9 +46,15 @@ def pass_bytes(nx, ny, nz):
     return b
 
 
+# the sources the demag passes and the stage kernel are built from (the
+# kernels whose counters the traffic summary holds)
+PROFILED_SOURCES = ("fft_engine.hpp", "demag_kernels.hpp", "demag.hip", "layout.hpp", "stage_body.hpp", "llg.hip",
+                    "mm_internal.hpp")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1406_7459_amd", "csrc"))):
+    for f in PROFILED_SOURCES:
         with open(os.path.join(ROOT, "paper_1406_7459_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -386,13 +392,75 @@ def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
     sur.close()
     plan.close()
     return {"workload": "film256 (256x256x4, 4 nm, alpha 0.1, in-plane |mu0 H| <= 50 mT); pairs from the solver",
-            "training": {"seconds": train_s, "pairs": pairs, "loss_first": float(np.mean(losses[:20])),
+            "training": {"seconds": train_s, "pairs": pairs, "pairs_per_s": pairs / train_s,
+                         "loss_first": float(np.mean(losses[:20])),
                          "loss_last": float(np.mean(losses[-20:]))},
             "gated_steps": steps, "tol": 1e-3, "stats": st,
             "exact_ms_per_step": te * 1e3, "surrogate_ms_per_step": ts * 1e3,
             "speedup_vs_plain_fp32": te / ts, "state_rel_l2_vs_exact": err,
             "inference_ms": inf * 1e3, "inference_tflops": 6.07e10 / inf / 1e12,
             "inference_mfma_frac": 6.07e10 / inf / 2.5e15}
+
+
+SURROGATE_PROFILE_CMD = (
+    "#   rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof_sur -o sur -- python3 $REPO/bench.py "
+    "--surrogate-profile",
+    "#   python3 bench.py --summarize-surrogate $REPO/gpurun_out/prof_sur/sur_results.db")
+
+
+def surrogate_profile(torch, mm):
+    """The launches profiles/surrogate_film256.txt is taken from: 20 network
+    evaluations (inference) and 10 training steps on the 256x256x4 film."""
+    from paper_1406_7459_amd.surrogate_train import init_params
+    nx, ny, nz = 256, 256, 4
+    sur = mm.Surrogate(nx, ny, nz)
+    sur.set_params(init_params(6, 5000))
+    x = torch.randn((3, nz, ny, nx), device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(20):
+        sur.forward(x, y, normalize=True)
+    dm, dh = x * 1e-3, torch.randn_like(x) * 1e-4
+    for _ in range(10):
+        sur.train_step(dm, dh, 1e-5)
+    torch.cuda.synchronize()
+    sur.close()
+
+
+def summarize_surrogate(db):
+    """Text of profiles/surrogate_film256.txt from a rocprofv3 --kernel-trace
+    database of bench.py --surrogate-profile: per kernel, the dispatch count
+    and durations; for the convolutions the rate of the 32 x 32-channel
+    3x3x3 product they compute (2*27*32*32 flop per cell, the last layer's 16
+    computed output rows: half of that)."""
+    import re
+    import sqlite3
+    import statistics
+    N = 256 * 256 * 4
+    con = sqlite3.connect(db)
+    groups = {}
+    for name, dur in con.execute("select name, duration from kernels"):
+        k = re.sub(r"\(.*", "", name).replace("void ", "")
+        groups.setdefault(k, []).append(dur / 1e3)
+    tot = sum(sum(v) for v in groups.values())
+    out = ["# kernel trace of the learned form, film256 (256x256x4 cells), rocprofv3 --kernel-trace",
+           "# command (from /tmp on the GPU, REPO = repository root):", *SURROGATE_PROFILE_CMD,
+           "# 20 network evaluations, then 10 training steps; durations in microseconds",
+           "# k_conv<E, lo, hi>: E = 3 inference hidden layer, 1 last layer, 0 training forward, 2 input",
+           "# gradient (GELU derivative fused); TFLOP/s of the computed 32x32-channel product (BF16 peak 2500)",
+           "%-44s %6s %9s %9s %7s %8s" % ("kernel", "calls", "median", "mean", "share", "TFLOP/s")]
+    for k in sorted(groups, key=lambda k: -sum(groups[k])):
+        v = groups[k]
+        med = statistics.median(v)
+        rate = ""
+        m = re.match(r"mmk::k_conv<(\d)", k)
+        if m:
+            fl = 2 * 27 * 32 * 32 * N * (0.5 if m.group(1) == "1" else 1.0)
+            rate = "%.0f" % (fl / (med * 1e-6) / 1e12)
+        elif k.startswith("mmk::k_conv_dw"):
+            rate = "%.0f" % (2 * 27 * 32 * 32 * N / (med * 1e-6) / 1e12)
+        out.append("%-44s %6d %9.2f %9.2f %6.1f%% %8s" % (k[:44], len(v), med, statistics.mean(v),
+                                                       100 * sum(v) / tot, rate))
+    return "\n".join(out) + "\n"
 
 
 def table1_euler(torch, mm, W):
@@ -474,6 +542,10 @@ def main():
                     help="print the traffic summary of rocprofv3 counter databases and exit")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("WORKLOAD", "DB"),
                     help="print the per-(pass, tile) summary of a rocprofv3 kernel-trace database and exit")
+    ap.add_argument("--surrogate-profile", action="store_true",
+                    help="run only the learned form's profiled launches (for rocprofv3)")
+    ap.add_argument("--summarize-surrogate", metavar="DB",
+                    help="print profiles/surrogate_film256.txt from a kernel-trace database")
     ap.add_argument("--sweep-tiles", action="store_true",
                     help="run only five demag evaluations with every valid tile of every pass "
                          "(for per-tile hardware counters)")
@@ -483,6 +555,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_traffic:
         sys.stdout.write(summarize_traffic(*args.summarize_traffic))
+        return
+    if args.summarize_surrogate:
+        sys.stdout.write(summarize_surrogate(args.summarize_surrogate))
         return
     if args.summarize_trace:
         sys.stdout.write(summarize_trace(*args.summarize_trace))
@@ -505,6 +580,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "elementwise copy", "bytes_read_per_launch": 4 * n,
                           "bytes_written_per_launch": 4 * n, "launches": 5}))
+        return
+    if args.surrogate_profile:
+        surrogate_profile(torch, mm)
+        print(json.dumps({"surrogate_profile": "film256", "evaluations": 20, "training_steps": 10}))
         return
 
     name = args.workload

@@ -183,11 +183,18 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                 s[j] = __builtin_amdgcn_raw_buffer_load_b128(src, ok ? row + xo[dx] : OUT_OF_RANGE, 0, 0);
             }
         };
-        u4 cur[TZ + 2], nxt_s[TZ + 2];
-        fetch(0, cur);
+        // loads run PF offsets ahead of the MFMAs, in a ring of PF + 1 row sets
+        // (two ahead in the inference forms when a block loads only four
+        // source rows, one otherwise: the registers of a deeper ring are not
+        // there)
+        constexpr int PF = (EPI == 1 || EPI == 3) && J1 - J0 <= 4 ? 2 : 1;
+        u4 ring[PF + 1][TZ + 2];
+#pragma unroll
+        for (int g = 0; g < PF; ++g) fetch(g, ring[g]);
 #pragma unroll
         for (int g = 0; g < 9; ++g) {
-            if (g < 8) fetch(g + 1, nxt_s);
+            if (g + PF < 9) fetch(g + PF, ring[(g + PF) % (PF + 1)]);
+            const u4 *cur = ring[g % (PF + 1)];
 #pragma unroll
             for (int dz = -1; dz <= 1; ++dz) {
                 const int t = (dz + 1) * 9 + g;
@@ -202,11 +209,8 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                     if (!HALF) acc1[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, bv, acc1[u], 0, 0, 0);
                 }
             }
-            if (g < 8) {
-#pragma unroll
-                for (int j = J0; j < J1; ++j) cur[j] = nxt_s[j];
-            }
-            // keep the prefetch one offset ahead (deeper would not fit the registers)
+            // keep the ring's distance (the scheduler would otherwise hoist
+            // further loads and run out of registers)
             __builtin_amdgcn_sched_barrier(0);
         }
         if (x >= nx) continue;
@@ -332,16 +336,25 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const 
 //   part[block][co][t][ci] = sum_cells dZ[cell][co] X[cell + off(t)][ci],
 //   part[block][WSZ + co] = sum_cells dZ[cell][co]
 // (each workgroup's row has the layout of one layer's parameters).
-// The reduction runs over cells, so the MFMA's K is 32 consecutive cells of
-// the channel-major padded copies (one 16-byte load per lane gives a
-// fragment): A = dZt rows (16 output channels), B = Xt rows (16 input
-// channels) at the source row of (dy, dz).  The dx = -1 and +1 fragments are
-// the dx = 0 one shifted by one cell, funnel-shifted from the 16-byte load and
-// its neighbouring dwords.  A wave owns one (co half, ci half) for all 27
-// taps (27 accumulators); four waves cover the 32 x 32 block, and the two
-// groups of four in a workgroup take alternate runs and meet in LDS.
-// Padding cells carry dZ = 0, so whole runs need no masks.
+// The reduction runs over cells, so the MFMA's K is a run of 32 consecutive
+// padded positions of the channel-major copies (one 16-byte chunk of 8 cells
+// per lane): A = dZ of 16 output channels, B = X of 16 input channels at the
+// source row of (dy, dz).  The dx = -1 and +1 fragments are the dx = 0 one
+// shifted by one cell, funnel-shifted from a window of cells -2 .. 9 around
+// the lane's chunk (one 16-byte and one 8-byte load).  A wave owns one (co
+// half, ci half) for all 27 taps (27 accumulators); four waves cover the
+// 32 x 32 block, and the two groups of four in a workgroup take alternate
+// runs of the workgroup's contiguous range (XCD-contiguous order) and meet
+// in LDS.  A run's loads are issued one run ahead.  Padding positions carry
+// dZ = 0, so whole runs need no masks.
 constexpr int DW_BLOCKS = 256;
+// a window of cells -2 .. 9 is 4-byte aligned
+typedef unsigned int u4w __attribute__((ext_vector_type(4), aligned(4)));
+typedef unsigned int u2w __attribute__((ext_vector_type(2), aligned(4)));
+struct DwWin {
+    u4w lo;  // cells -2 .. 5
+    u2w hi;  // cells 6 .. 9
+};
 __global__ __launch_bounds__(512) void k_conv_dw(const __bf16 *__restrict__ dZt, const __bf16 *__restrict__ Xt,
                                                  float *__restrict__ part, PadGeom pg, int nruns)
 {
@@ -352,13 +365,35 @@ __global__ __launch_bounds__(512) void k_conv_dw(const __bf16 *__restrict__ dZt,
     const int m = lane & 15, kq = lane >> 4;
     const __bf16 *A = dZt + (long long)(16 * h + m) * pg.G + 8 * kq;
     const __bf16 *B = Xt + (long long)(16 * gq + m) * pg.G + 8 * kq;
+    long long roff[9];  // source row offsets of (dz, dy)
+#pragma unroll
+    for (int sr = 0; sr < 9; ++sr) roff[sr] = (long long)(sr / 3 - 1) * pg.pl + (long long)(sr % 3 - 1) * pg.xp;
     f4 acc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    for (int r = blockIdx.x * 2 + grp; r < nruns; r += gridDim.x * 2) {
+    const int per = (nruns + gridDim.x - 1) / gridDim.x;
+    const int rb = (int)xcd_block(blockIdx.x, gridDim.x) * per, re = min(nruns, rb + per);
+    auto fetch = [&](int r, u4 &a, DwWin *win) {
         const long long p = (long long)pg.f + pg.pl + 32LL * r;
-        const u4 a = *reinterpret_cast<const u4 *>(A + p);
+        a = *reinterpret_cast<const u4 *>(A + p);
+#pragma unroll
+        for (int sr = 0; sr < 9; ++sr) {
+            win[sr].lo = *reinterpret_cast<const u4w *>(B + p + roff[sr] - 2);
+            win[sr].hi = *reinterpret_cast<const u2w *>(B + p + roff[sr] + 6);
+        }
+    };
+    // the next run's loads are made opaque at the end of the iteration (kept
+    // in flight across this run's MFMAs, not moved to the top of the next
+    // iteration); the last prefetch repeats a valid run
+    int r = rb + grp;
+    DwWin win[9];
+    u4 a = {0u, 0u, 0u, 0u};
+    if (r < re) fetch(r, a, win);
+    for (; r < re; r += 2) {
+        u4 an;
+        DwWin nw[9];
+        fetch(min(r + 2, re - 1), an, nw);
         if (gq == 0) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -367,20 +402,25 @@ __global__ __launch_bounds__(512) void k_conv_dw(const __bf16 *__restrict__ dZt,
         const bf8 av = __builtin_bit_cast(bf8, a);
 #pragma unroll
         for (int sr = 0; sr < 9; ++sr) {
-            const int dz = sr / 3 - 1, dy = sr % 3 - 1;
-            const __bf16 *s = B + p + (long long)dz * pg.pl + (long long)dy * pg.xp;
-            const u4 c = *reinterpret_cast<const u4 *>(s);
-            const unsigned lo = *reinterpret_cast<const unsigned *>(s - 2);  // cells -2, -1
-            const unsigned hi = *reinterpret_cast<const unsigned *>(s + 8);  // cells 8, 9
-            const u4 bm = {__builtin_amdgcn_alignbit(c[0], lo, 16), __builtin_amdgcn_alignbit(c[1], c[0], 16),
-                           __builtin_amdgcn_alignbit(c[2], c[1], 16), __builtin_amdgcn_alignbit(c[3], c[2], 16)};
-            const u4 bp = {__builtin_amdgcn_alignbit(c[1], c[0], 16), __builtin_amdgcn_alignbit(c[2], c[1], 16),
-                           __builtin_amdgcn_alignbit(c[3], c[2], 16), __builtin_amdgcn_alignbit(hi, c[3], 16)};
-            const int t0 = (dz + 1) * 9 + (dy + 1) * 3;
+            const unsigned d0 = win[sr].lo[0], d1 = win[sr].lo[1], d2 = win[sr].lo[2], d3 = win[sr].lo[3];
+            const unsigned d4 = win[sr].hi[0], d5 = win[sr].hi[1];
+            const u4 c = {d1, d2, d3, d4};
+            const u4 bm = {__builtin_amdgcn_alignbit(d1, d0, 16), __builtin_amdgcn_alignbit(d2, d1, 16),
+                           __builtin_amdgcn_alignbit(d3, d2, 16), __builtin_amdgcn_alignbit(d4, d3, 16)};
+            const u4 bp = {__builtin_amdgcn_alignbit(d2, d1, 16), __builtin_amdgcn_alignbit(d3, d2, 16),
+                           __builtin_amdgcn_alignbit(d4, d3, 16), __builtin_amdgcn_alignbit(d5, d4, 16)};
+            const int t0 = sr * 3;  // (dz + 1) * 9 + (dy + 1) * 3
             acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, bm), acc[t0], 0, 0, 0);
             acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, c), acc[t0 + 1], 0, 0, 0);
             acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, bp), acc[t0 + 2], 0, 0, 0);
         }
+        asm volatile("" : "+v"(an));
+#pragma unroll
+        for (int sr = 0; sr < 9; ++sr) {
+            asm volatile("" : "+v"(nw[sr].lo), "+v"(nw[sr].hi));
+            win[sr] = nw[sr];
+        }
+        a = an;
     }
     // group 1 hands its accumulators to group 0 through LDS, in two halves
 #pragma unroll
