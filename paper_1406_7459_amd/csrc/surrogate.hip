@@ -35,17 +35,28 @@ constexpr int NLAYER = 6;
 constexpr int WSZ = SC * NT * SC;  // weights per padded layer
 static const int CH[NLAYER + 1] = {3, 32, 32, 32, 32, 32, 3};
 
-__device__ __forceinline__ float gelu_f(float x)
+// GELU, tanh form: 0.5 x (1 + tanh(u)) with u = sqrt(2/pi) (x + 0.044715 x^3),
+// evaluated as x * s with s = 1 / (1 + e^(-2u)) (the same function; one
+// exponential and one reciprocal instead of a tanh), and its derivative
+// s + 2 x s (1 - s) u'.
+__device__ __forceinline__ float gelu_s(float x, float &du)
 {
     const float c = 0.7978845608028654f;  // sqrt(2/pi)
-    return 0.5f * x * (1.f + tanhf(c * (x + 0.044715f * x * x * x)));
+    const float x2 = x * x;
+    du = c * (1.f + 3.f * 0.044715f * x2);
+    const float u = c * x * (1.f + 0.044715f * x2);
+    return __builtin_amdgcn_rcpf(1.f + __expf(-2.f * u));
+}
+__device__ __forceinline__ float gelu_f(float x)
+{
+    float du;
+    return x * gelu_s(x, du);
 }
 __device__ __forceinline__ float gelu_d(float x)
 {
-    const float c = 0.7978845608028654f;
-    const float u = c * (x + 0.044715f * x * x * x);
-    const float t = tanhf(u);
-    return 0.5f * (1.f + t) + 0.5f * x * (1.f - t * t) * c * (1.f + 3.f * 0.044715f * x * x);
+    float du;
+    const float s = gelu_s(x, du);
+    return s + 2.f * x * s * (1.f - s) * du;
 }
 
 // EPI 0: hidden layer, Z = acc + b (FP32) and Xn = bf16(gelu(Z));
