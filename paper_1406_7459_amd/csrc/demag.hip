@@ -157,7 +157,8 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
         if (var == 0) {
             threads = P * (L / k.E0);
             maxt = k.conv_max;
-            lds = (tws + (k.nstage > 1 ? (size_t)lds_rows(L) * P : 0)) * sizeof(float2);
+            // two exchange buffers (ping-pong transforms)
+            lds = (tws + (k.nstage > 1 ? 2 * (size_t)lds_rows(L) * P : 0)) * sizeof(float2);
         } else if (var == 1 || var == 2) {
             const int E = var == 1 ? k.E0 : k.E1;
             if (var == 2 && k.E1 == k.E0) return false;

@@ -202,7 +202,9 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
     const int xp = x_pitch(nxc);
+    // two exchange buffers (ping-pong transforms: one barrier per exchange)
     const LdsView s{lds + tw_slots<L>(), P, p};
+    const LdsView s1{lds + tw_slots<L>() + lds_rows(L) * P, P, p};
     const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;  // stride along the transform
     const size_t cs = (size_t)NH * rs;                            // component stride
     float2 *base = X + (size_t)ky * xp + kx + (size_t)q * rs;  // this thread's row q
@@ -223,9 +225,9 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             vb[b * R0 + r] = ld ? float2(base[cs + o]) : make_float2(0.f, 0.f);
             vc[b * R0 + r] = ld ? float2(base[2 * cs + o]) : make_float2(0.f, 0.f);
         }
-    fft<L, -1, false>(va, s, q, twl);
-    fft<L, -1, false>(vb, s, q, twl);
-    fft<L, -1, false>(vc, s, q, twl);
+    fft_pp<L, -1, false>(va, s, s1, q, twl);
+    fft_pp<L, -1, false>(vb, s, s1, q, twl);
+    fft_pp<L, -1, false>(vc, s, s1, q, twl);
 
     constexpr int RL = last_radix<L, false>();
     const int nyk = ny + 1;
@@ -255,9 +257,9 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     // mixing them lifts the register peak from ~106 to ~134 VGPRs at L = 256
     // (three waves per SIMD instead of four).
     __builtin_amdgcn_sched_barrier(0);
-    fft<L, +1, true>(va, s, q, twl);
-    fft<L, +1, true>(vb, s, q, twl);
-    fft<L, +1, true>(vc, s, q, twl);
+    fft_pp<L, +1, true>(va, s, s1, q, twl);
+    fft_pp<L, +1, true>(vb, s, s1, q, twl);
+    fft_pp<L, +1, true>(vc, s, s1, q, twl);
     // the reversed order ends with radix R0: outputs sit where the inputs did
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)

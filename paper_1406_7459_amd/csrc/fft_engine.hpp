@@ -189,13 +189,14 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[E], int q, const float
 }
 
 // Write the outputs of a stage (radix R, NS) to LDS, then read the inputs
-// of the next stage (radix R2).  Two barriers: the second keeps the next
-// exchange's writes from overtaking this exchange's reads.
+// of the next stage (radix R2).  TRAIL: a second barrier keeps the next
+// exchange's writes from overtaking this exchange's reads (not needed when
+// the next exchange writes another buffer).
 // Where a thread's rows are base + c with c a compile-time offset that never
 // carries base into the next group of 8 (c a multiple of 8, or base a
 // multiple of R with c < R | 8), slot(base + c) = slot(base) + slot(c) and
 // the per-access offsets fold into the LDS instructions.
-template <int L, int E, int R, int NS, int R2>
+template <int L, int E, int R, int NS, int R2, bool TRAIL = true>
 __device__ __forceinline__ void exchange(float2 (&v)[E], const LdsView &s, int q)
 {
     constexpr int Q = L / E;
@@ -226,7 +227,7 @@ __device__ __forceinline__ void exchange(float2 (&v)[E], const LdsView &s, int q
             for (int r = 0; r < R2; ++r) v[b * R2 + r] = s.at(lds_slot(row + r * ST));
         }
     }
-    __syncthreads();
+    if constexpr (TRAIL) __syncthreads();
 }
 
 template <int L, int E, int DIR, bool REV, int S>
@@ -241,6 +242,36 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], const LdsView &s, int
         exchange<L, E, R, NS, R2>(v, s, q);
         run_stages<L, E, DIR, REV, S + 1>(v, s, q, tw);
     }
+}
+
+// Ping-pong form: exchange S uses buffer S mod 2, so only one barrier per
+// exchange is needed; exchange k + 2 rewrites a buffer only after every
+// thread has passed exchange k + 1's barrier, which follows its reads of
+// exchange k.  The last exchange keeps its trailing barrier when it uses
+// buffer 0 (an odd number of exchanges), since the next transform's first
+// exchange writes buffer 0 again.  The caller must not write either buffer
+// between transforms without a barrier.
+template <int L, int E, int DIR, bool REV, int S>
+__device__ __forceinline__ void run_stages_pp(float2 (&v)[E], const LdsView &s0, const LdsView &s1, int q,
+                                              const float2 *__restrict__ tw)
+{
+    constexpr int R = radix_at<L, REV>(S);
+    constexpr int NS = ns_before<L, REV>(S);
+    constexpr int N = Factors<L>::N;
+    stage_compute<L, E, R, NS, DIR>(v, q, tw);
+    if constexpr (S + 1 < N) {
+        constexpr int R2 = radix_at<L, REV>(S + 1);
+        constexpr bool TRAIL = S == N - 2 && S % 2 == 0;
+        exchange<L, E, R, NS, R2, TRAIL>(v, S % 2 ? s1 : s0, q);
+        run_stages_pp<L, E, DIR, REV, S + 1>(v, s0, s1, q, tw);
+    }
+}
+
+template <int L, int DIR, bool REV>
+__device__ __forceinline__ void fft_pp(float2 (&v)[Factors<L>::E], const LdsView &s0, const LdsView &s1, int q,
+                                       const float2 *__restrict__ tw)
+{
+    run_stages_pp<L, Factors<L>::E, DIR, REV, 0>(v, s0, s1, q, tw);
 }
 
 // Full transform with E values per thread (E a multiple of every radix of
