@@ -127,10 +127,23 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
     constexpr int NCO = HALF ? 16 : 32;
     constexpr int J0 = ZLO ? 1 : 0, J1 = ZHI ? TZ + 1 : TZ + 2;  // source rows that exist
     __shared__ u4 wl[NCO * WROW];
-    const u4 *Wv = reinterpret_cast<const u4 *>(W);
-    for (int i = threadIdx.x; i < NCO * NT * 4; i += blockDim.x) {
-        const int co = i / (NT * 4);
-        wl[co * WROW + (i - co * NT * 4)] = Wv[i];
+    {
+        // every load of the staging is issued before the first LDS write (a
+        // load-wait-write loop would pay the load latency once per round)
+        constexpr int NW = NCO * NT * 4, ROUNDS = (NW + 64 * CONV_WAVES - 1) / (64 * CONV_WAVES);
+        const u4 *Wv = reinterpret_cast<const u4 *>(W);
+        u4 tmp[ROUNDS];
+#pragma unroll
+        for (int k = 0; k < ROUNDS; ++k) {
+            const int i = threadIdx.x + k * 64 * CONV_WAVES;
+            if (i < NW) tmp[k] = Wv[i];
+        }
+#pragma unroll
+        for (int k = 0; k < ROUNDS; ++k) {
+            const int i = threadIdx.x + k * 64 * CONV_WAVES;
+            const int co = i / (NT * 4);
+            if (i < NW) wl[co * WROW + (i - co * NT * 4)] = tmp[k];
+        }
     }
     __syncthreads();
     // the wave index is uniform: read it into a scalar so that the task
@@ -146,6 +159,14 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
     const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<__bf16 *>(X), 0, (int)((long long)nx * ny * nz * SC * 2), 0x00020000);
     const unsigned OUT_OF_RANGE = 0x80000000u;
+    // inference forms: the lane's biases are loaded once, ahead of the tasks
+    f4 bia0 = {0.f, 0.f, 0.f, 0.f}, bia1 = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (EPI == 3) {
+        bia0 = *reinterpret_cast<const f4 *>(bias + 4 * kq);
+        bia1 = *reinterpret_cast<const f4 *>(bias + 16 + 4 * kq);
+    } else if constexpr (EPI == 1) {
+        bia0 = *reinterpret_cast<const f4 *>(bias);
+    }
     // XCD-contiguous workgroup order: the rows y-1..y+1 and levels z0-1..z0+4
     // a task reads were read by its neighbours in the same L2
     for (long long task = (long long)xcd_block(blockIdx.x, gridDim.x) * CONV_WAVES + wv; task < ntask;
@@ -235,8 +256,8 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                 bf4 g0, g1;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    z0v[r] = acc0[u][r] + bias[4 * kq + r];
-                    z1v[r] = acc1[u][r] + bias[16 + 4 * kq + r];
+                    z0v[r] = acc0[u][r] + (EPI == 3 ? bia0[r] : bias[4 * kq + r]);
+                    z1v[r] = acc1[u][r] + (EPI == 3 ? bia1[r] : bias[16 + 4 * kq + r]);
                     g0[r] = (__bf16)gelu_f(z0v[r]);
                     g1[r] = (__bf16)gelu_f(z1v[r]);
                 }
@@ -258,7 +279,7 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                     const float s = sig ? sig[0] : scale;
 #pragma unroll
                     for (int r = 0; r < 3; ++r) {
-                        const float z = acc0[u][r] + bias[r];
+                        const float z = acc0[u][r] + bia0[r];
                         Z[c * SC + r] = z;
                         dh[r * N + c] = s * z;
                     }
