@@ -373,13 +373,17 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const 
 // per lane): A = dZ of 16 output channels, B = X of 16 input channels at the
 // source row of (dy, dz).  The dx = -1 and +1 fragments are the dx = 0 one
 // shifted by one cell, funnel-shifted from a window of cells -2 .. 9 around
-// the lane's chunk (one 16-byte and one 8-byte load).  A wave owns one (co
-// half, ci half) for all 27 taps (27 accumulators); four waves cover the
-// 32 x 32 block, and the two groups of four in a workgroup take alternate
-// runs of the workgroup's contiguous range (XCD-contiguous order) and meet
-// in LDS.  A run's loads are issued one run ahead.  Padding positions carry
-// dZ = 0, so whole runs need no masks.
+// the lane's chunk (one 16-byte and one 8-byte load).  A wave owns one input
+// half and one part of the taps (source rows 0-4 or 5-8, i.e. 15 or 12 taps)
+// for both output halves, so each source window is loaded by two waves of a
+// group and reused for two output halves (the loads, each touching 16
+// channel rows, bound this kernel).  Four waves cover the 32 x 32 x 27
+// block; the two groups of four in a workgroup take alternate runs of the
+// workgroup's contiguous range (XCD-contiguous order) and meet in LDS.  A
+// run's loads are issued one run ahead.  Padding positions carry dZ = 0, so
+// whole runs need no masks.
 constexpr int DW_BLOCKS = 256;
+constexpr int DW_ROUND = 10;  // accumulator tiles handed over through LDS per round
 // a window of cells -2 .. 9 is 4-byte aligned
 typedef unsigned int u4w __attribute__((ext_vector_type(4), aligned(4)));
 typedef unsigned int u2w __attribute__((ext_vector_type(2), aligned(4)));
@@ -387,100 +391,138 @@ struct DwWin {
     u4w lo;  // cells -2 .. 5
     u2w hi;  // cells 6 .. 9
 };
-__global__ __launch_bounds__(512) void k_conv_dw(const __bf16 *__restrict__ dZt, const __bf16 *__restrict__ Xt,
-                                                 float *__restrict__ part, PadGeom pg, int nruns)
+
+template <int TH>
+__device__ __forceinline__ void dw_wave(const __bf16 *__restrict__ dZt, const __bf16 *__restrict__ Xt,
+                                        float *__restrict__ part, const PadGeom &pg, int nruns, int gq, int grp,
+                                        int w, f4 (*red)[DW_ROUND][64], float (*bred)[2][4][16])
 {
-    __shared__ f4 red[4][14][64];
-    __shared__ float bred[2][2][4][16];
-    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int h = w & 1, gq = (w >> 1) & 1, grp = w >> 2;
-    const int m = lane & 15, kq = lane >> 4;
-    const __bf16 *A = dZt + (long long)(16 * h + m) * pg.G + 8 * kq;
+    constexpr int SR0 = TH ? 5 : 0, NR = TH ? 4 : 5, NTT = 3 * NR;  // source rows, taps
+    const int lane = threadIdx.x & 63, m = lane & 15, kq = lane >> 4;
+    const __bf16 *A0 = dZt + (long long)m * pg.G + 8 * kq;  // output channels m and 16 + m
+    const __bf16 *A1 = A0 + 16 * pg.G;
     const __bf16 *B = Xt + (long long)(16 * gq + m) * pg.G + 8 * kq;
-    long long roff[9];  // source row offsets of (dz, dy)
+    long long roff[NR];  // source row offsets of (dz, dy)
 #pragma unroll
-    for (int sr = 0; sr < 9; ++sr) roff[sr] = (long long)(sr / 3 - 1) * pg.pl + (long long)(sr % 3 - 1) * pg.xp;
-    f4 acc[NT];
+    for (int i = 0; i < NR; ++i) {
+        const int sr = SR0 + i;
+        roff[i] = (long long)(sr / 3 - 1) * pg.pl + (long long)(sr % 3 - 1) * pg.xp;
+    }
+    f4 acc[2][NTT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f;
+    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+        for (int t = 0; t < NTT; ++t) acc[hh][t] = f4{0.f, 0.f, 0.f, 0.f};
+    float bs0 = 0.f, bs1 = 0.f;
     const int per = (nruns + gridDim.x - 1) / gridDim.x;
     const int rb = (int)xcd_block(blockIdx.x, gridDim.x) * per, re = min(nruns, rb + per);
-    auto fetch = [&](int r, u4 &a, DwWin *win) {
+    auto fetch = [&](int r, u4 &a0, u4 &a1, DwWin *win) {
         const long long p = (long long)pg.f + pg.pl + 32LL * r;
-        a = *reinterpret_cast<const u4 *>(A + p);
+        a0 = *reinterpret_cast<const u4 *>(A0 + p);
+        a1 = *reinterpret_cast<const u4 *>(A1 + p);
 #pragma unroll
-        for (int sr = 0; sr < 9; ++sr) {
-            win[sr].lo = *reinterpret_cast<const u4w *>(B + p + roff[sr] - 2);
-            win[sr].hi = *reinterpret_cast<const u2w *>(B + p + roff[sr] + 6);
+        for (int i = 0; i < NR; ++i) {
+            win[i].lo = *reinterpret_cast<const u4w *>(B + p + roff[i] - 2);
+            win[i].hi = *reinterpret_cast<const u2w *>(B + p + roff[i] + 6);
         }
     };
     // the next run's loads are made opaque at the end of the iteration (kept
     // in flight across this run's MFMAs, not moved to the top of the next
     // iteration); the last prefetch repeats a valid run
     int r = rb + grp;
-    DwWin win[9];
-    u4 a = {0u, 0u, 0u, 0u};
-    if (r < re) fetch(r, a, win);
+    DwWin win[NR];
+    u4 a0 = {0u, 0u, 0u, 0u}, a1 = {0u, 0u, 0u, 0u};
+    if (r < re) fetch(r, a0, a1, win);
     for (; r < re; r += 2) {
-        u4 an;
-        DwWin nw[9];
-        fetch(min(r + 2, re - 1), an, nw);
-        if (gq == 0) {
+        u4 an0, an1;
+        DwWin nw[NR];
+        fetch(min(r + 2, re - 1), an0, an1, nw);
+        if (TH == 0 && gq == 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                bsum += __uint_as_float(a[i] << 16) + __uint_as_float(a[i] & 0xffff0000u);
+            for (int i = 0; i < 4; ++i) {
+                bs0 += __uint_as_float(a0[i] << 16) + __uint_as_float(a0[i] & 0xffff0000u);
+                bs1 += __uint_as_float(a1[i] << 16) + __uint_as_float(a1[i] & 0xffff0000u);
+            }
         }
-        const bf8 av = __builtin_bit_cast(bf8, a);
+        const bf8 av0 = __builtin_bit_cast(bf8, a0), av1 = __builtin_bit_cast(bf8, a1);
 #pragma unroll
-        for (int sr = 0; sr < 9; ++sr) {
-            const unsigned d0 = win[sr].lo[0], d1 = win[sr].lo[1], d2 = win[sr].lo[2], d3 = win[sr].lo[3];
-            const unsigned d4 = win[sr].hi[0], d5 = win[sr].hi[1];
-            const u4 c = {d1, d2, d3, d4};
-            const u4 bm = {__builtin_amdgcn_alignbit(d1, d0, 16), __builtin_amdgcn_alignbit(d2, d1, 16),
-                           __builtin_amdgcn_alignbit(d3, d2, 16), __builtin_amdgcn_alignbit(d4, d3, 16)};
-            const u4 bp = {__builtin_amdgcn_alignbit(d2, d1, 16), __builtin_amdgcn_alignbit(d3, d2, 16),
-                           __builtin_amdgcn_alignbit(d4, d3, 16), __builtin_amdgcn_alignbit(d5, d4, 16)};
-            const int t0 = sr * 3;  // (dz + 1) * 9 + (dy + 1) * 3
-            acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, bm), acc[t0], 0, 0, 0);
-            acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, c), acc[t0 + 1], 0, 0, 0);
-            acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, bp), acc[t0 + 2], 0, 0, 0);
+        for (int i = 0; i < NR; ++i) {
+            const unsigned d0 = win[i].lo[0], d1 = win[i].lo[1], d2 = win[i].lo[2], d3 = win[i].lo[3];
+            const unsigned d4 = win[i].hi[0], d5 = win[i].hi[1];
+            const bf8 bc = __builtin_bit_cast(bf8, u4{d1, d2, d3, d4});
+            const bf8 bm = __builtin_bit_cast(
+                bf8, u4{__builtin_amdgcn_alignbit(d1, d0, 16), __builtin_amdgcn_alignbit(d2, d1, 16),
+                        __builtin_amdgcn_alignbit(d3, d2, 16), __builtin_amdgcn_alignbit(d4, d3, 16)});
+            const bf8 bp = __builtin_bit_cast(
+                bf8, u4{__builtin_amdgcn_alignbit(d2, d1, 16), __builtin_amdgcn_alignbit(d3, d2, 16),
+                        __builtin_amdgcn_alignbit(d4, d3, 16), __builtin_amdgcn_alignbit(d5, d4, 16)});
+            const int t0 = 3 * i;  // local tap (dx = -1, 0, +1)
+            acc[0][t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bm, acc[0][t0], 0, 0, 0);
+            acc[1][t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bm, acc[1][t0], 0, 0, 0);
+            acc[0][t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bc, acc[0][t0 + 1], 0, 0, 0);
+            acc[1][t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bc, acc[1][t0 + 1], 0, 0, 0);
+            acc[0][t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av0, bp, acc[0][t0 + 2], 0, 0, 0);
+            acc[1][t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av1, bp, acc[1][t0 + 2], 0, 0, 0);
         }
-        asm volatile("" : "+v"(an));
+        asm volatile("" : "+v"(an0), "+v"(an1));
 #pragma unroll
-        for (int sr = 0; sr < 9; ++sr) {
-            asm volatile("" : "+v"(nw[sr].lo), "+v"(nw[sr].hi));
-            win[sr] = nw[sr];
+        for (int i = 0; i < NR; ++i) {
+            asm volatile("" : "+v"(nw[i].lo), "+v"(nw[i].hi));
+            win[i] = nw[i];
         }
-        a = an;
+        a0 = an0;
+        a1 = an1;
     }
-    // group 1 hands its accumulators to group 0 through LDS, in two halves
+    // group 1 hands its 2 NTT tiles to group 0 through LDS, DW_ROUND at a time
+    // (three rounds for either part of the taps: the barriers match)
 #pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        const int t0 = half * 14, nt = half ? NT - 14 : 14;
+    for (int rd = 0; rd < 3; ++rd) {
         if (grp == 1) {
 #pragma unroll
-            for (int i = 0; i < 14; ++i)
-                if (i < nt) red[w & 3][i][lane] = acc[t0 + i];
+            for (int i = 0; i < DW_ROUND; ++i) {
+                const int k = rd * DW_ROUND + i;
+                if (k < 2 * NTT) red[w & 3][i][lane] = acc[k / NTT][k % NTT];
+            }
         }
         __syncthreads();
         if (grp == 0) {
 #pragma unroll
-            for (int i = 0; i < 14; ++i)
-                if (i < nt) acc[t0 + i] += red[w][i][lane];
+            for (int i = 0; i < DW_ROUND; ++i) {
+                const int k = rd * DW_ROUND + i;
+                if (k < 2 * NTT) acc[k / NTT][k % NTT] += red[w][i][lane];
+            }
         }
         __syncthreads();
     }
-    if (gq == 0) bred[grp][h][kq][m] = bsum;
+    if (TH == 0 && gq == 0) {
+        bred[grp][0][kq][m] = bs0;
+        bred[grp][1][kq][m] = bs1;
+    }
     __syncthreads();
     if (grp == 0) {
-        // lane holds D[co = 16 h + 4 kq + i][ci = 16 gq + m]
+        // lane holds D[co = 16 hh + 4 kq + i][ci = 16 gq + m] of tap 3 SR0 + t
         float *o = part + (long long)blockIdx.x * (WSZ + SC);
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) o[((16 * h + 4 * kq + i) * NT + t) * SC + 16 * gq + m] = acc[t][i];
+            for (int t = 0; t < NTT; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    o[((16 * hh + 4 * kq + i) * NT + 3 * SR0 + t) * SC + 16 * gq + m] = acc[hh][t][i];
     }
+}
+
+__global__ __launch_bounds__(512) void k_conv_dw(const __bf16 *__restrict__ dZt, const __bf16 *__restrict__ Xt,
+                                                 float *__restrict__ part, PadGeom pg, int nruns)
+{
+    __shared__ f4 red[4][DW_ROUND][64];
+    __shared__ float bred[2][2][4][16];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gq = w & 1, th = (w >> 1) & 1, grp = w >> 2;
+    if (th == 0)
+        dw_wave<0>(dZt, Xt, part, pg, nruns, gq, grp, w, red, bred);
+    else
+        dw_wave<1>(dZt, Xt, part, pg, nruns, gq, grp, w, red, bred);
     if (threadIdx.x < SC) {
         const int co = threadIdx.x, hh = co >> 4, mm = co & 15;
         float b = 0.f;
