@@ -35,6 +35,25 @@ static hipEvent_t take_event(Plan &p)
     return e;
 }
 
+void timing_arm(Plan &p)
+{
+    p.tev[0] = p.tev[1] = nullptr;
+    if (!p.timing) return;
+    hipEvent_t e0 = take_event(p), e1 = e0 ? take_event(p) : nullptr;
+    if (!e1) {
+        if (e0) p.event_pool.push_back(e0);
+        return;
+    }
+    p.tev[0] = e0;
+    p.tev[1] = e1;
+}
+
+void timing_file(Plan &p, int pass)
+{
+    if (p.tev[0]) p.pending.push_back({pass, {p.tev[0], p.tev[1]}});
+    p.tev[0] = p.tev[1] = nullptr;
+}
+
 void timing_begin(Plan &p, int pass, hipStream_t s, hipEvent_t *ev0)
 {
     (void)pass;

@@ -307,20 +307,20 @@ static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, 
     switch (pass) {
     case MM_PASS_XFWD: {
         const int pairs = (nrows + 1) / 2;
-        hipLaunchKernelGGL((k_xfwd<L, V>), dim3((pairs + P - 1) / P), block, lds, s, M, p.X1, nrows, lp2, p.tw[0]);
+        MMK_LAUNCH(p, (k_xfwd<L, V>), dim3((pairs + P - 1) / P), block, lds, s, M, p.X1, nrows, lp2, p.tw[0]);
         break;
     }
     case MM_PASS_YFWD:
-        hipLaunchKernelGGL((k_yfwd<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X1, p.X2, nxc, lp2,
+        MMK_LAUNCH(p, (k_yfwd<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X1, p.X2, nxc, lp2,
                            p.tw[1]);
         break;
     case MM_PASS_YINV:
-        hipLaunchKernelGGL((k_yinv<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X2, p.X1, nxc, lp2,
+        MMK_LAUNCH(p, (k_yinv<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X2, p.X1, nxc, lp2,
                            p.tw[1]);
         break;
     case MM_PASS_XINV: {
         const int pairs = (nrows + 1) / 2;
-        hipLaunchKernelGGL((k_xinv<L, V>), dim3((pairs + P - 1) / P), block, lds, s, p.X1, H, nrows, lp2, p.tw[0]);
+        MMK_LAUNCH(p, (k_xinv<L, V>), dim3((pairs + P - 1) / P), block, lds, s, p.X1, H, nrows, lp2, p.tw[0]);
         break;
     }
     default: break;
@@ -338,16 +338,16 @@ static void launch_conv(Plan &p, int pass, int P, int var, size_t lds, hipStream
     const dim3 grid((nxc + P - 1) / P, z ? 2 * p.ny : 1);
     if (var == 0) {
         const dim3 block(P * (L / Factors<L>::E));
-        if (z) hipLaunchKernelGGL((k_conv_reg3<L, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
-        else hipLaunchKernelGGL((k_conv_reg3<L, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_reg3<L, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        else MMK_LAUNCH(p, (k_conv_reg3<L, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
     } else if (var == 1) {
         const dim3 block(3 * P * (L / ept<L, 0>()));
-        if (z) hipLaunchKernelGGL((k_conv_split<L, 0, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
-        else hipLaunchKernelGGL((k_conv_split<L, 0, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_split<L, 0, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        else MMK_LAUNCH(p, (k_conv_split<L, 0, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
     } else {
         const dim3 block(3 * P * (L / ept<L, 1>()));
-        if (z) hipLaunchKernelGGL((k_conv_split<L, 1, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
-        else hipLaunchKernelGGL((k_conv_split<L, 1, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_split<L, 1, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        else MMK_LAUNCH(p, (k_conv_split<L, 1, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
     }
 }
 
@@ -368,15 +368,14 @@ int launch_pass(Plan &p, int pass, const float *M, float *H, hipStream_t s)
     int threads, maxt;
     size_t lds;
     shape_for(pass, L, tile, threads, lds, maxt);
-    hipEvent_t ev0 = nullptr;
-    timing_begin(p, pass, s, &ev0);
+    timing_arm(p);
     switch (L) {
 #define MMK_CASE(LEN) case LEN: launch_len<LEN>(p, pass, tile, lds, M, H, s); break;
         MMK_ALL_LENGTHS(MMK_CASE)
 #undef MMK_CASE
-    default: return fail(MM_EINVAL, "unsupported FFT length");
+    default: timing_file(p, pass); return fail(MM_EINVAL, "unsupported FFT length");
     }
-    timing_end(p, pass, s, ev0);
+    timing_file(p, pass);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MM_EHIP, std::string("demag launch: ") + hipGetErrorString(e));
     return MM_OK;

@@ -68,15 +68,14 @@ static int launch_stage(Plan &p, const float *S, const float *Mn, float *out, co
         W /= 2;
     const size_t threads = (n + W - 1) / W;
     const dim3 grid((unsigned)((threads + bs - 1) / bs));
-    hipEvent_t ev0 = nullptr;
-    timing_begin(p, MM_PASS_STAGE, s, &ev0);
+    timing_arm(p);
     if (W == 4)
-        hipLaunchKernelGGL((k_stage_vec<STAGE, 4>), grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
+        MMK_LAUNCH(p, (k_stage_vec<STAGE, 4>), grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
     else if (W == 2)
-        hipLaunchKernelGGL((k_stage_vec<STAGE, 2>), grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
+        MMK_LAUNCH(p, (k_stage_vec<STAGE, 2>), grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
     else
-        hipLaunchKernelGGL(k_stage<STAGE>, grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
-    timing_end(p, MM_PASS_STAGE, s, ev0);
+        MMK_LAUNCH(p, k_stage<STAGE>, grid, dim3(bs), 0, s, S, Hd, Mn, p.kacc, out, p.nx, p.ny, p.nz, c);
+    timing_file(p, MM_PASS_STAGE);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MM_EHIP, std::string("k_stage: ") + hipGetErrorString(e));
     return MM_OK;

@@ -1,6 +1,7 @@
 // mm_internal.hpp -- host-side plan state and helpers shared by the library's
 // translation units (not part of the public ABI; see include/mm.h).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -83,6 +84,7 @@ struct Plan {
     int tile[MM_PASS_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
 
     bool timing = false;
+    hipEvent_t tev[2] = {nullptr, nullptr};  // armed start/stop pair for the next launch
     TimingAcc acc[MM_PASS_COUNT];
     std::vector<TimedPair> pending;       // recorded, not yet read
     std::vector<hipEvent_t> event_pool;
@@ -109,9 +111,24 @@ int prepare_kernels(Plan &p);  // raise LDS limits where needed
 int demag_enqueue(Plan &p, const float *M, float *H, hipStream_t s);
 int launch_pass(Plan &p, int pass, const float *M, float *H, hipStream_t s);
 
-// Timing hooks used around every launch of the plan.
+// Timing hooks.  A pass of one kernel arms an event pair before its launch
+// and files it after; MMK_LAUNCH hands an armed pair to the dispatch itself
+// (hipExtLaunchKernelGGL), so the events time the kernel's execution and not
+// the command processor's handling of separate event records.  Passes of
+// several kernels bracket them with recorded events instead.
+void timing_arm(Plan &p);
+void timing_file(Plan &p, int pass);
 void timing_begin(Plan &p, int pass, hipStream_t s, hipEvent_t *ev0);
 void timing_end(Plan &p, int pass, hipStream_t s, hipEvent_t ev0);
+
+#define MMK_LAUNCH(p, kern, grid, block, lds, s, ...)                                                         \
+    do {                                                                                                      \
+        if ((p).tev[0])                                                                                       \
+            hipExtLaunchKernelGGL(kern, grid, block, (std::uint32_t)(lds), s, (p).tev[0], (p).tev[1], 0u,    \
+                                  __VA_ARGS__);                                                               \
+        else                                                                                                  \
+            hipLaunchKernelGGL(kern, grid, block, lds, s, __VA_ARGS__);                                        \
+    } while (0)
 
 // Tensor set-up (tensor.hip).
 int newell_octant_device(int nx, int ny, int nz, double dx, double dy, double dz, double *N,
