@@ -12,9 +12,11 @@
 // cells, K = 32 input channels per tap, 27 taps) on v_mfma_f32_16x16x32_bf16
 // with FP32 accumulation.  Layers with 3 channels are zero-padded to 32.
 // The input gradient reuses the same kernel with the weights transposed and
-// the taps mirrored; the weight gradient is an FP32 reduction over cells.
-// Training keeps FP32 master weights and Adam moments; the bfloat16 copies
-// are refreshed after every update.
+// the taps mirrored (its epilogue applies the GELU derivative of the layer
+// below); the weight gradient is an MFMA reduction over cells of
+// channel-major copies of dZ and of the layer input.  Training keeps FP32
+// master weights and Adam moments; the bfloat16 copies are refreshed after
+// every update, and every reduction runs in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
