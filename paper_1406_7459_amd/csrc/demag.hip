@@ -208,13 +208,13 @@ std::vector<int> tile_candidates_for(int pass, int L, size_t lds_limit)
 }
 
 // rows: the largest P with <= 256 threads; columns: the largest P <= 16 whose
-// LDS fits in 64 KiB (split schedule for the product passes when the
-// transform has several stages, reg3 otherwise)
+// LDS fits in 64 KiB (the product passes in the three-component register
+// schedule, which the autotuner picks at every measured size)
 int default_tile_for(int pass, int L, size_t lds_limit)
 {
     KInfo k{};
     if (!kinfo_for(L, k)) return 0;
-    const int var = (is_conv(pass) && k.nstage > 1) ? 1 : 0;
+    const int var = 0;  // product passes: three components in registers (faster than the split)
     int best = 0;
     for (int P = 1; P <= 128; P *= 2) {
         const int tile = P + 256 * var;

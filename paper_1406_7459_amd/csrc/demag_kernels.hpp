@@ -313,9 +313,37 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
             v[b * R0 + r] = (!upper && ok && k < NH) ? float2(base[(size_t)(Q * b + r * (L / R0)) * rs])
                                                      : make_float2(0.f, 0.f);
         }
-    fft_e<L, E, -1, false>(v, s, q, twl);
-
+    // this group's row of the symmetric tensor: (xx,xy,xz), (xy,yy,yz), (xz,yz,zz);
+    // its K~ values do not depend on the transform: with E = 8 values per
+    // thread they are loaded first and their latency passes under the
+    // forward transform (with more values the registers are not there)
     constexpr int RL = last_radix<L, false>();
+    constexpr bool PRE = E <= 8;
+    const int c0 = g == 0 ? 0 : (g == 1 ? 3 : 4);
+    const int c1 = g == 0 ? 3 : (g == 1 ? 1 : 5);
+    const int c2 = g == 0 ? 4 : (g == 1 ? 5 : 2);
+    const int nyk = ny + 1;
+    const int kyf = ky <= ny ? ky : 2 * ny - ky;
+    const float sy0 = ky <= ny ? 1.f : -1.f;
+    const float *Kb = Kt + 6 * ((ZAXIS ? (size_t)kyf * xp : 0) + (size_t)(ok ? kx : 0));
+    float kr[E][3];
+    auto load_k = [&]() {
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int k = q + Q * b + r * (L / RL);
+                const int kf = k <= NH ? k : L - k;
+                const float *K = Kb + 6u * __umul24((unsigned)kf, ZAXIS ? (unsigned)(nyk * xp) : (unsigned)xp);
+                kr[b * RL + r][0] = K[c0];
+                kr[b * RL + r][1] = K[c1];
+                kr[b * RL + r][2] = K[c2];
+            }
+    };
+    if constexpr (PRE) load_k();
+    fft_e<L, E, -1, false>(v, s, q, twl);
+    if constexpr (!PRE) load_k();
+
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -324,28 +352,19 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
             buf[((size_t)g * GS + lds_slot(k)) * P + p] = v[b * RL + r];
         }
     __syncthreads();
-    // this group's row of the symmetric tensor: (xx,xy,xz), (xy,yy,yz), (xz,yz,zz)
-    const int c0 = g == 0 ? 0 : (g == 1 ? 3 : 4);
-    const int c1 = g == 0 ? 3 : (g == 1 ? 1 : 5);
-    const int c2 = g == 0 ? 4 : (g == 1 ? 5 : 2);
-    const int nyk = ny + 1;
-    const int kyf = ky <= ny ? ky : 2 * ny - ky;
-    const float sy0 = ky <= ny ? 1.f : -1.f;
-    const float *Kb = Kt + 6 * ((ZAXIS ? (size_t)kyf * xp : 0) + (size_t)(ok ? kx : 0));
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int k = q + Q * b + r * (L / RL);
-            const int kf = k <= NH ? k : L - k;
             const float sk = k <= NH ? 1.f : -1.f;
             // parity signs: ZAXIS: sy on xy, sk on xz, sy*sk on yz; y only: sk on xy
             const float sxy = ZAXIS ? sy0 : sk, sxz = ZAXIS ? sk : 0.f, syz = ZAXIS ? sy0 * sk : 0.f;
             const float w0 = g == 0 ? 1.f : (g == 1 ? sxy : sxz);
             const float w1 = g == 0 ? sxy : (g == 1 ? 1.f : syz);
             const float w2 = g == 0 ? sxz : (g == 1 ? syz : 1.f);
-            const float *K = Kb + 6u * __umul24((unsigned)kf, ZAXIS ? (unsigned)(nyk * xp) : (unsigned)xp);
-            const float k0 = w0 * K[c0], k1 = w1 * K[c1], k2 = w2 * K[c2];
+            const float *kk = kr[b * RL + r];
+            const float k0 = w0 * kk[0], k1 = w1 * kk[1], k2 = w2 * kk[2];
             const int ks = lds_slot(k) * P + p;
             const float2 m0 = buf[ks];
             const float2 m1 = buf[(size_t)GS * P + ks];
