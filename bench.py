@@ -144,11 +144,11 @@ def summarize_trace(workload, db):
             other.setdefault(name.split("(")[0].replace("void ", ""), []).append(dur / 1e3)
     alg = pass_bytes(*shape)
     out = ["# kernel trace, %s (%dx%dx%d cells), rocprofv3 --kernel-trace" % ((workload,) + tuple(shape)),
-           "# command (from /tmp on the GPU, REPO = repository root):",
-           "#   rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof_%s -o %s -- python3 $REPO/bench.py "
+           "# command (from /tmp on the GPU, REPO = repository root, OUT = an output folder):",
+           "#   rocprofv3 --kernel-trace --stats -d $OUT/prof_%s -o %s -- python3 $REPO/bench.py "
            "--workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs --no-surrogate"
            % (workload, workload, workload),
-           "#   python3 bench.py --summarize-trace %s $REPO/gpurun_out/prof_%s/%s_results.db" % (workload, workload, workload),
+           "#   python3 bench.py --summarize-trace %s $OUT/prof_%s/%s_results.db" % (workload, workload, workload),
            "# durations in microseconds; tile = P + 256 * variant, for the stage kernel its vector width, with",
            "# the RK4 stage (1-4, 0 = Euler) in column s; GB/s from the algorithmic bytes per launch",
            "# (bench.pass_bytes; stage: 48N, 72N, 72N, 60N bytes, Euler 60N) over the median duration",
@@ -205,12 +205,12 @@ def summarize_traffic(workload, pmc_dir):
                 acc.setdefault(key, {}).setdefault(c, []).append(v * 1024.0 * scale[c])
     alg = pass_bytes(nx, ny, nz)
     out = ["# HBM traffic per launch, %s (%dx%dx%d cells), rocprofv3 hardware counters" % (workload, nx, ny, nz),
-           "# commands (from /tmp on the GPU, REPO = repository root):",
-           "#   rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/pmc/sweep_FETCH_SIZE -o sweep -- python3 $REPO/bench.py --sweep-tiles",
-           "#   rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/pmc/sweep_WRITE_SIZE -o sweep -- python3 $REPO/bench.py --sweep-tiles",
-           "#   rocprofv3 --pmc FETCH_SIZE -d $REPO/gpurun_out/pmc/copy_FETCH_SIZE -o copy -- python3 $REPO/bench.py --calibrate-copy",
-           "#   rocprofv3 --pmc WRITE_SIZE -d $REPO/gpurun_out/pmc/copy_WRITE_SIZE -o copy -- python3 $REPO/bench.py --calibrate-copy",
-           "#   python3 bench.py --summarize-traffic %s $REPO/gpurun_out/pmc" % workload,
+           "# commands (from /tmp on the GPU, REPO = repository root, OUT = an output folder):",
+           "#   rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc/sweep_FETCH_SIZE -o sweep -- python3 $REPO/bench.py --sweep-tiles",
+           "#   rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc/sweep_WRITE_SIZE -o sweep -- python3 $REPO/bench.py --sweep-tiles",
+           "#   rocprofv3 --pmc FETCH_SIZE -d $OUT/pmc/copy_FETCH_SIZE -o copy -- python3 $REPO/bench.py --calibrate-copy",
+           "#   rocprofv3 --pmc WRITE_SIZE -d $OUT/pmc/copy_WRITE_SIZE -o copy -- python3 $REPO/bench.py --calibrate-copy",
+           "#   python3 bench.py --summarize-traffic %s $OUT/pmc" % workload,
            "# scale: a 512 MiB copy (512 MiB read + 512 MiB written) reads back FETCH_SIZE x%.4f, WRITE_SIZE x%.4f"
            % (scale["FETCH_SIZE"], scale["WRITE_SIZE"]),
            "# per pass and tile (P + 256 * variant): median fetch / write bytes per launch; stage: mean of RK4 stages 1-4",
@@ -403,9 +403,9 @@ def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
 
 
 SURROGATE_PROFILE_CMD = (
-    "#   rocprofv3 --kernel-trace --stats -d $REPO/gpurun_out/prof_sur -o sur -- python3 $REPO/bench.py "
+    "#   rocprofv3 --kernel-trace --stats -d $OUT/prof_sur -o sur -- python3 $REPO/bench.py "
     "--surrogate-profile",
-    "#   python3 bench.py --summarize-surrogate $REPO/gpurun_out/prof_sur/sur_results.db")
+    "#   python3 bench.py --summarize-surrogate $OUT/prof_sur/sur_results.db")
 
 
 def surrogate_profile(torch, mm):
@@ -443,7 +443,7 @@ def summarize_surrogate(db):
         groups.setdefault(k, []).append(dur / 1e3)
     tot = sum(sum(v) for v in groups.values())
     out = ["# kernel trace of the learned form, film256 (256x256x4 cells), rocprofv3 --kernel-trace",
-           "# command (from /tmp on the GPU, REPO = repository root):", *SURROGATE_PROFILE_CMD,
+           "# command (from /tmp on the GPU, REPO = repository root, OUT = an output folder):", *SURROGATE_PROFILE_CMD,
            "# 20 network evaluations, then 10 training steps; durations in microseconds",
            "# k_conv<E, lo, hi>: E = 3 inference hidden layer, 1 last layer, 0 training forward, 2 input",
            "# gradient (GELU derivative fused); TFLOP/s of the computed 32x32-channel product (BF16 peak 2500)",

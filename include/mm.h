@@ -43,7 +43,7 @@ enum {
     MM_EHIP = -4,         /* a HIP runtime call failed (detail in mm_last_error) */
     MM_ENONFINITE = -5,   /* a reduction found NaN/Inf in the state */
     MM_ETUNE = -6,        /* the autotuner found no valid candidate */
-    MM_EUNSUPPORTED = -7  /* valid request outside what this build implements */
+    MM_EUNSUPPORTED = -7  /* valid request outside what the library implements */
 };
 
 enum { MM_RK4 = 0, MM_EULER = 1 };
