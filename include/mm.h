@@ -183,8 +183,12 @@ int mm_plan_set_tile(mm_plan plan, int pass, int tile);
  * mm_plan_query.  Synchronises.  Errors: MM_ETUNE if no candidate ran.       */
 int mm_plan_autotune(mm_plan plan, int reps, void *stream);
 
-/* Per-kernel timing: when enabled, every launch of the plan is bracketed
- * by HIP events on its stream and its duration accumulated per pass kind.
+/* Per-kernel timing: when enabled, every launch of the plan is timed with a
+ * pair of HIP events and its duration accumulated per pass kind.  For the
+ * passes of one kernel (the FFT passes and the stage kernel) the events
+ * travel with the dispatch (hipExtLaunchKernelGGL) and time the kernel's
+ * execution; the reduction's two kernels are bracketed by recorded events.
+ * Steps run as direct launches while timing is on (no graph replay).
  * mm_plan_timing synchronises and returns total milliseconds and launch
  * counts per MM_PASS_* kind (arrays of MM_PASS_COUNT), then resets them.   */
 int mm_plan_set_timing(mm_plan plan, int enable);
