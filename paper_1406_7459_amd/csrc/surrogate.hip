@@ -61,12 +61,12 @@ __device__ __forceinline__ float gelu_d(float x)
     return s + 2.f * x * s * (1.f - s) * du;
 }
 
-// EPI 0: hidden layer, Z = acc + b (FP32) and Xn = bf16(gelu(Z));
+// EPI 0: hidden layer, Zh = bf16(acc + b) and Xn = bf16(gelu(acc + b));
 // EPI 1: last layer, dh[co][cell] = s * (acc + b) for co < 3 (SoA FP32),
 //        s = sig[0] if sig is given (device sigma) else scale;
 // EPI 2: input gradient fused with the GELU derivative of the layer below:
-//        dZ_prev = acc * gelu'(Zp) with Zp = Z (read, the pre-activations of
-//        the layer below), written as bf16 cell-major Xn and channel-major Xt;
+//        dZ_prev = acc * gelu'(Zp) with Zp = Zh (read, the bf16 pre-activations
+//        of the layer below), written as bf16 cell-major Xn and channel-major Xt;
 // EPI 3: hidden layer for inference only, Xn = bf16(gelu(acc + b)) (no Z).
 //
 // A wave owns a 16-cell run along x at one y and TZ = 4 consecutive z levels
@@ -122,8 +122,8 @@ __device__ __forceinline__ long long pad_at(const PadGeom &g, int x, int y, int 
 template <int EPI, bool ZLO, bool ZHI>
 __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_conv(
     const __bf16 *__restrict__ X, const __bf16 *__restrict__ W, const float *__restrict__ bias, float *__restrict__ Z,
-    __bf16 *__restrict__ Xn, float *__restrict__ dh, float scale, const float *__restrict__ sig, int nx, int ny,
-    int nz, int zb0, int nzbr, __bf16 *__restrict__ Xt, PadGeom pg)
+    __bf16 *__restrict__ Zh, __bf16 *__restrict__ Xn, float *__restrict__ dh, float scale,
+    const float *__restrict__ sig, int nx, int ny, int nz, int zb0, int nzbr, __bf16 *__restrict__ Xt, PadGeom pg)
 {
     constexpr bool HALF = EPI == 1;
     constexpr int NCO = HALF ? 16 : 32;
@@ -264,8 +264,14 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                     g1[r] = (__bf16)gelu_f(z1v[r]);
                 }
                 if constexpr (EPI == 0) {  // training: pre-activations and the channel-major copy
-                    *reinterpret_cast<f4 *>(Z + c * SC + 4 * kq) = z0v;
-                    *reinterpret_cast<f4 *>(Z + c * SC + 16 + 4 * kq) = z1v;
+                    bf4 h0, h1;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        h0[r] = (__bf16)z0v[r];
+                        h1[r] = (__bf16)z1v[r];
+                    }
+                    *reinterpret_cast<bf4 *>(Zh + c * SC + 4 * kq) = h0;
+                    *reinterpret_cast<bf4 *>(Zh + c * SC + 16 + 4 * kq) = h1;
                     const long long pc = pad_at(pg, x, y, z0 + u);
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
@@ -287,13 +293,13 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
                     }
                 }
             } else {
-                const f4 z0v = *reinterpret_cast<const f4 *>(Z + c * SC + 4 * kq);
-                const f4 z1v = *reinterpret_cast<const f4 *>(Z + c * SC + 16 + 4 * kq);
+                const bf4 z0v = *reinterpret_cast<const bf4 *>(Zh + c * SC + 4 * kq);
+                const bf4 z1v = *reinterpret_cast<const bf4 *>(Zh + c * SC + 16 + 4 * kq);
                 bf4 g0, g1;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    g0[r] = (__bf16)(acc0[u][r] * gelu_d(z0v[r]));
-                    g1[r] = (__bf16)(acc1[u][r] * gelu_d(z1v[r]));
+                    g0[r] = (__bf16)(acc0[u][r] * gelu_d((float)z0v[r]));
+                    g1[r] = (__bf16)(acc1[u][r] * gelu_d((float)z1v[r]));
                 }
                 *reinterpret_cast<bf4 *>(Xn + c * SC + 4 * kq) = g0;
                 *reinterpret_cast<bf4 *>(Xn + c * SC + 16 + 4 * kq) = g1;
@@ -681,7 +687,8 @@ struct Sur {
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     __bf16 *wb = nullptr, *wt = nullptr;  // bf16 forward / mirrored-transposed copies
     __bf16 *X[NLAYER] = {};               // layer inputs, [N][32]
-    float *Z[NLAYER] = {};                // pre-activations, [N][32]
+    __bf16 *Zh[NLAYER - 1] = {};          // hidden pre-activations (training), [N][32]
+    float *Zout = nullptr;                // last layer's output before the scale, [N][32] (channels 0-2)
     __bf16 *dZb[2] = {};                  // [N][32], this layer's dZ and the one below
     PadGeom pg;                           // channel-major padded copies (training)
     __bf16 *Xt[NLAYER] = {};              // layer inputs, [32][G]
@@ -730,14 +737,14 @@ static unsigned grid_for(long long n) { return (unsigned)std::min<long long>((n 
 // block) task per wave and pass.
 template <int EPI>
 static void launch_conv(const Sur &s, hipStream_t st, const __bf16 *X, const __bf16 *W, const float *bias, float *Z,
-                        __bf16 *Xn, float *dh, const float *sig, __bf16 *Xt = nullptr)
+                        __bf16 *Zh, __bf16 *Xn, float *dh, const float *sig, __bf16 *Xt = nullptr)
 {
     const int nzb = (s.nz + TZ - 1) / TZ;
     auto go = [&](auto kern, int zb0, int nzbr) {
         const long long tasks = (long long)((s.nx + 15) / 16) * s.ny * nzbr;
         const unsigned gb = (unsigned)std::min<long long>((tasks + CONV_WAVES - 1) / CONV_WAVES, 8192);
-        hipLaunchKernelGGL(kern, dim3(gb), dim3(64 * CONV_WAVES), 0, st, X, W, bias, Z, Xn, dh, 1.f, sig, s.nx, s.ny,
-                           s.nz, zb0, nzbr, Xt, s.pg);
+        hipLaunchKernelGGL(kern, dim3(gb), dim3(64 * CONV_WAVES), 0, st, X, W, bias, Z, Zh, Xn, dh, 1.f, sig, s.nx,
+                           s.ny, s.nz, zb0, nzbr, Xt, s.pg);
     };
     if (nzb == 1) {
         go(k_conv<EPI, true, true>, 0, 1);
@@ -757,11 +764,11 @@ static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool 
         const __bf16 *W = s.wb + (long long)l * WSZ;
         const float *b = s.w + l * layer_stride() + WSZ;
         if (l < NLAYER - 1 && keep_z)
-            launch_conv<0>(s, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, nullptr, s.Xt[l + 1]);
+            launch_conv<0>(s, st, s.X[l], W, b, nullptr, s.Zh[l], s.X[l + 1], nullptr, nullptr, s.Xt[l + 1]);
         else if (l < NLAYER - 1)
-            launch_conv<3>(s, st, s.X[l], W, b, s.Z[l], s.X[l + 1], nullptr, nullptr);
+            launch_conv<3>(s, st, s.X[l], W, b, nullptr, nullptr, s.X[l + 1], nullptr, nullptr);
         else  // dh = sigma * Net(...) with sigma from device memory when dev_scale
-            launch_conv<1>(s, st, s.X[l], W, b, s.Z[l], nullptr, dh, dev_scale ? s.sig : nullptr);
+            launch_conv<1>(s, st, s.X[l], W, b, s.Zout, nullptr, nullptr, dh, dev_scale ? s.sig : nullptr);
     }
 }
 
@@ -782,7 +789,7 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
     float sg[2];
     MMK_HIP(hipMemcpyAsync(sg, s.sig, sizeof(sg), hipMemcpyDeviceToHost, st));
     MMK_HIP(hipStreamSynchronize(st));
-    hipLaunchKernelGGL(k_mse, dim3(RED_B), dim3(256), 0, st, s.Z[NLAYER - 1], dh_target, sg[1], s.dZb[0], s.dZt, s.pg,
+    hipLaunchKernelGGL(k_mse, dim3(RED_B), dim3(256), 0, st, s.Zout, dh_target, sg[1], s.dZb[0], s.dZt, s.pg,
                        s.dpart, s.nx, s.ny, s.N);
     std::vector<double> hp(RED_B);
     MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * RED_B, hipMemcpyDeviceToHost, st));
@@ -796,8 +803,8 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
             // dZ of layer l-1 into the other dZb buffer (the convolution still
             // reads this one) and into dZt, whose weight gradient has run
             const int cur = (NLAYER - 1 - l) & 1;
-            launch_conv<2>(s, st, s.dZb[cur], s.wt + (long long)l * WSZ, nullptr, s.Z[l - 1], s.dZb[cur ^ 1], nullptr,
-                           nullptr, s.dZt);
+            launch_conv<2>(s, st, s.dZb[cur], s.wt + (long long)l * WSZ, nullptr, nullptr, s.Zh[l - 1],
+                           s.dZb[cur ^ 1], nullptr, nullptr, s.dZt);
         }
     }
     MMK_HIP(hipStreamSynchronize(st));
@@ -900,9 +907,10 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
     rc = rc ? rc : sur_alloc(*s, (void **)&s->wt, (size_t)NLAYER * WSZ * 2);
     for (int l = 0; l < NLAYER && rc == MM_OK; ++l) {
         rc = sur_alloc(*s, (void **)&s->X[l], (size_t)s->N * SC * 2);
-        if (rc == MM_OK) rc = sur_alloc(*s, (void **)&s->Z[l], (size_t)s->N * SC * 4);
+        if (rc == MM_OK && l < NLAYER - 1) rc = sur_alloc(*s, (void **)&s->Zh[l], (size_t)s->N * SC * 2);
         if (rc == MM_OK) rc = sur_alloc(*s, (void **)&s->Xt[l], (size_t)s->pg.G * SC * 2);
     }
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->Zout, (size_t)s->N * SC * 4);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZt, (size_t)s->pg.G * SC * 2);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[0], (size_t)s->N * SC * 2);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[1], (size_t)s->N * SC * 2);
