@@ -338,8 +338,9 @@ __global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm,
     }
 }
 
-// last-layer gradient: dZ = 2 (z - target/scale) / (3N) on co < 3 (zero on the
-// padded channels), as bf16 cell-major dZb and channel-major dZt; squared
+// last-layer gradient: dZ = 2 (z - target/scale) / (3N) on co < 3, as bf16
+// cell-major dZb and channel-major dZt (buffers of the last layer only, whose
+// padded channels are zeroed once at creation and never written); squared
 // error partials (FP64) per block
 __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const float *__restrict__ tgt, float inv,
                                              __bf16 *__restrict__ dZb, __bf16 *__restrict__ dZt, PadGeom pg,
@@ -348,20 +349,14 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const 
     double s = 0.0;
     const float w = 2.f / (3.f * (float)N);
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
-        float g[SC];
-#pragma unroll
-        for (int q = 0; q < SC; ++q) g[q] = 0.f;
+        const long long pc = pad_at(pg, (int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long long)nx * ny)));
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const float d = Z[c * SC + r] - tgt[r * N + c] * inv;
             s += (double)d * d;
-            g[r] = w * d;
-        }
-        const long long pc = pad_at(pg, (int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long long)nx * ny)));
-#pragma unroll
-        for (int q = 0; q < SC; ++q) {
-            dZb[c * SC + q] = (__bf16)g[q];
-            dZt[q * pg.G + pc] = (__bf16)g[q];
+            const __bf16 g = (__bf16)(w * d);
+            dZb[c * SC + r] = g;
+            dZt[r * pg.G + pc] = g;
         }
     }
 #pragma unroll
@@ -690,6 +685,7 @@ struct Sur {
     __bf16 *Zh[NLAYER - 1] = {};          // hidden pre-activations (training), [N][32]
     float *Zout = nullptr;                // last layer's output before the scale, [N][32] (channels 0-2)
     __bf16 *dZb[2] = {};                  // [N][32], this layer's dZ and the one below
+    __bf16 *dZbL = nullptr, *dZtL = nullptr;  // the last layer's dZ, cell- and channel-major
     PadGeom pg;                           // channel-major padded copies (training)
     __bf16 *Xt[NLAYER] = {};              // layer inputs, [32][G]
     __bf16 *dZt = nullptr;                // [32][G]
@@ -789,22 +785,26 @@ static int sur_backward(Sur &s, const float *dh_target, double *loss, hipStream_
     float sg[2];
     MMK_HIP(hipMemcpyAsync(sg, s.sig, sizeof(sg), hipMemcpyDeviceToHost, st));
     MMK_HIP(hipStreamSynchronize(st));
-    hipLaunchKernelGGL(k_mse, dim3(RED_B), dim3(256), 0, st, s.Zout, dh_target, sg[1], s.dZb[0], s.dZt, s.pg,
+    hipLaunchKernelGGL(k_mse, dim3(RED_B), dim3(256), 0, st, s.Zout, dh_target, sg[1], s.dZbL, s.dZtL, s.pg,
                        s.dpart, s.nx, s.ny, s.N);
     std::vector<double> hp(RED_B);
     MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * RED_B, hipMemcpyDeviceToHost, st));
     for (int l = NLAYER - 1; l >= 0; --l) {
         const int nruns = (int)(((long long)s.nz * s.pg.pl + 31) / 32);
-        hipLaunchKernelGGL(k_conv_dw, dim3(DW_BLOCKS), dim3(512), 0, st, s.dZt, s.Xt[l], s.part, s.pg, nruns);
+        const bool last = l == NLAYER - 1;
+        hipLaunchKernelGGL(k_conv_dw, dim3(DW_BLOCKS), dim3(512), 0, st, last ? s.dZtL : s.dZt, s.Xt[l], s.part, s.pg,
+                           nruns);
         const int ls = (int)layer_stride();
         hipLaunchKernelGGL(k_sum_chunks, dim3((ls + 63) / 64), dim3(256), 0, st, s.part, DW_BLOCKS, ls,
                            s.g + l * layer_stride());
         if (l > 0) {
             // dZ of layer l-1 into the other dZb buffer (the convolution still
-            // reads this one) and into dZt, whose weight gradient has run
-            const int cur = (NLAYER - 1 - l) & 1;
-            launch_conv<2>(s, st, s.dZb[cur], s.wt + (long long)l * WSZ, nullptr, nullptr, s.Zh[l - 1],
-                           s.dZb[cur ^ 1], nullptr, nullptr, s.dZt);
+            // reads this one; layer l's is dZbL for the last layer, else
+            // dZb[(NLAYER - 2 - l) & 1]) and into dZt, whose weight gradient has run
+            const __bf16 *in = last ? s.dZbL : s.dZb[(NLAYER - 2 - l) & 1];
+            __bf16 *out = s.dZb[(NLAYER - 1 - l) & 1];
+            launch_conv<2>(s, st, in, s.wt + (long long)l * WSZ, nullptr, nullptr, s.Zh[l - 1], out, nullptr, nullptr,
+                           s.dZt);
         }
     }
     MMK_HIP(hipStreamSynchronize(st));
@@ -914,6 +914,8 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZt, (size_t)s->pg.G * SC * 2);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[0], (size_t)s->N * SC * 2);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[1], (size_t)s->N * SC * 2);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZbL, (size_t)s->N * SC * 2);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZtL, (size_t)s->pg.G * SC * 2);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->part, (size_t)DW_BLOCKS * layer_stride() * 4);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dpart, (size_t)2 * RED_B * 8);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->sig, 16);
@@ -933,6 +935,8 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
         // the padded copies are zero outside the grid's cells and stay so
         for (int l = 0; l < NLAYER && e == hipSuccess; ++l) e = hipMemset(s->Xt[l], 0, (size_t)s->pg.G * SC * 2);
         if (e == hipSuccess) e = hipMemset(s->dZt, 0, (size_t)s->pg.G * SC * 2);
+        if (e == hipSuccess) e = hipMemset(s->dZtL, 0, (size_t)s->pg.G * SC * 2);
+        if (e == hipSuccess) e = hipMemset(s->dZbL, 0, (size_t)s->N * SC * 2);
         if (e != hipSuccess) rc = fail(MM_EHIP, "surrogate init");
         refresh(*s, nullptr);
         if (hipDeviceSynchronize() != hipSuccess) rc = fail(MM_EHIP, "surrogate init sync");
