@@ -63,7 +63,8 @@ __device__ __forceinline__ float gelu_d(float x)
 
 // EPI 0: hidden layer, Zh = bf16(acc + b) and Xn = bf16(gelu(acc + b));
 // EPI 1: last layer, dh[co][cell] = s * (acc + b) for co < 3 (SoA FP32),
-//        s = sig[0] if sig is given (device sigma) else scale;
+//        s = sig[0] if sig is given (device sigma) else scale, and (training,
+//        Z given) Z[cell][co] = acc + b in [N][4];
 // EPI 2: input gradient fused with the GELU derivative of the layer below:
 //        dZ_prev = acc * gelu'(Zp) with Zp = Zh (read, the bf16 pre-activations
 //        of the layer below), written as bf16 cell-major Xn and channel-major Xt;
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
 #pragma unroll
                     for (int r = 0; r < 3; ++r) {
                         const float z = acc0[u][r] + bia0[r];
-                        Z[c * SC + r] = z;
+                        if (Z) Z[c * 4 + r] = z;  // training only
                         dh[r * N + c] = s * z;
                     }
                 }
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ Z, const 
         const long long pc = pad_at(pg, (int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long long)nx * ny)));
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            const float d = Z[c * SC + r] - tgt[r * N + c] * inv;
+            const float d = Z[c * 4 + r] - tgt[r * N + c] * inv;
             s += (double)d * d;
             const __bf16 g = (__bf16)(w * d);
             dZb[c * SC + r] = g;
@@ -683,7 +684,7 @@ struct Sur {
     __bf16 *wb = nullptr, *wt = nullptr;  // bf16 forward / mirrored-transposed copies
     __bf16 *X[NLAYER] = {};               // layer inputs, [N][32]
     __bf16 *Zh[NLAYER - 1] = {};          // hidden pre-activations (training), [N][32]
-    float *Zout = nullptr;                // last layer's output before the scale, [N][32] (channels 0-2)
+    float *Zout = nullptr;                // last layer's output before the scale, [N][4] (channels 0-2)
     __bf16 *dZb[2] = {};                  // [N][32], this layer's dZ and the one below
     __bf16 *dZbL = nullptr, *dZtL = nullptr;  // the last layer's dZ, cell- and channel-major
     PadGeom pg;                           // channel-major padded copies (training)
@@ -764,7 +765,8 @@ static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool 
         else if (l < NLAYER - 1)
             launch_conv<3>(s, st, s.X[l], W, b, nullptr, nullptr, s.X[l + 1], nullptr, nullptr);
         else  // dh = sigma * Net(...) with sigma from device memory when dev_scale
-            launch_conv<1>(s, st, s.X[l], W, b, s.Zout, nullptr, nullptr, dh, dev_scale ? s.sig : nullptr);
+            launch_conv<1>(s, st, s.X[l], W, b, keep_z ? s.Zout : nullptr, nullptr, nullptr, dh,
+                           dev_scale ? s.sig : nullptr);
     }
 }
 
@@ -910,7 +912,7 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
         if (rc == MM_OK && l < NLAYER - 1) rc = sur_alloc(*s, (void **)&s->Zh[l], (size_t)s->N * SC * 2);
         if (rc == MM_OK) rc = sur_alloc(*s, (void **)&s->Xt[l], (size_t)s->pg.G * SC * 2);
     }
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->Zout, (size_t)s->N * SC * 4);
+    rc = rc ? rc : sur_alloc(*s, (void **)&s->Zout, (size_t)s->N * 4 * 4);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZt, (size_t)s->pg.G * SC * 2);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[0], (size_t)s->N * SC * 2);
     rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[1], (size_t)s->N * SC * 2);
