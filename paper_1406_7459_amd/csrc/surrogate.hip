@@ -315,16 +315,42 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
     }
 }
 
-// dm [3][N] FP32 (SoA) * (1/sigma) -> channels 0..7 of bf16 channel-last
-// [N][32] (channels 3..7 zero; channels 8..31 are zeroed once at creation
-// and never written); sigma is read from device memory (the step driver
-// never synchronises for it)
+// sigma = sqrt(sum / count) from the nb FP64 partials of the sum of squares
+// (1 if the sum is 0 or normalisation is off), in a fixed order (a strided
+// sum per thread, then a tree; 256 threads), then dm [3][N] FP32 (SoA) *
+// (1/sigma) -> channels 0..7 of bf16 channel-last [N][32] (channels 3..7
+// zero; channels 8..31 are zeroed once at creation and never written).
+// Every workgroup forms sigma itself (4 KB of partials from L2, no extra
+// launch); workgroup 0 stores sig = {sigma, 1/sigma} for the later kernels
+// (the step driver never synchronises for it).
 // (training: also channels 0..2 of the channel-major copy Xt)
 __global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm, __bf16 *__restrict__ X,
-                                                   const float *__restrict__ sig, long long N, __bf16 *__restrict__ Xt,
-                                                   PadGeom pg, int nx, int ny)
+                                                   const double *__restrict__ part, int nb, double count,
+                                                   int normalize, float *__restrict__ sig, long long N,
+                                                   __bf16 *__restrict__ Xt, PadGeom pg, int nx, int ny)
 {
-    const float inv = sig[1];
+    __shared__ double red[256];
+    __shared__ float s_inv;
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) t += part[b];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double sg = normalize ? sqrt(red[0] / count) : 1.0;
+        if (!(sg > 0.0) || !isfinite(sg)) sg = 1.0;
+        const float inv_sg = (float)(1.0 / sg);
+        if (blockIdx.x == 0) {
+            sig[0] = (float)sg;
+            sig[1] = inv_sg;
+        }
+        s_inv = inv_sg;
+    }
+    __syncthreads();
+    const float inv = s_inv;
     for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += (long long)gridDim.x * blockDim.x) {
         bf8 v = {0, 0, 0, 0, 0, 0, 0, 0};
         v[0] = (__bf16)(dm[c] * inv);
@@ -654,28 +680,6 @@ __global__ __launch_bounds__(256) void k_anchor(const float *__restrict__ h0, co
 
 namespace mmk {
 
-// sigma = sqrt(sum / count) (1 if the sum is 0 or normalisation is off);
-// out[0] = sigma, out[1] = 1 / sigma
-__global__ __launch_bounds__(256) void k_sigma(const double *__restrict__ part, int nb, double count, int normalize,
-                                               float *__restrict__ out)
-{
-    // fixed-order tree over the partials (deterministic)
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 256) s += part[b];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    double sg = normalize ? sqrt(red[0] / count) : 1.0;
-    if (!(sg > 0.0) || !isfinite(sg)) sg = 1.0;
-    out[0] = (float)sg;
-    out[1] = (float)(1.0 / sg);
-}
-
 struct Sur {
     int nx, ny, nz;
     long long N;
@@ -775,9 +779,8 @@ static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool 
 static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st, bool train = false)
 {
     hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, dm, nullptr, s.dpart, 3 * s.N);
-    hipLaunchKernelGGL(k_sigma, dim3(1), dim3(256), 0, st, s.dpart, RED_B, (double)(3 * s.N), normalize, s.sig);
-    hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.sig, s.N,
-                       train ? s.Xt[0] : nullptr, s.pg, s.nx, s.ny);
+    hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.dpart, RED_B,
+                       (double)(3 * s.N), normalize, s.sig, s.N, train ? s.Xt[0] : nullptr, s.pg, s.nx, s.ny);
 }
 
 // loss and gradients into s.g (masters' layout); returns the loss on the host
