@@ -644,19 +644,22 @@ __global__ __launch_bounds__(256) void k_resid(const float *__restrict__ a, cons
     }
 }
 
-// sum of squares of a field (FP64 partials), for the increment scale
-__global__ __launch_bounds__(256) void k_sumsq_diff(const float *__restrict__ a, const float *__restrict__ b,
-                                                    double *__restrict__ part, long long n)
+// Sum of squares (FP64 partials per workgroup) of d = (a - b) * s (b may be
+// NULL: d = a * s), and d itself into dout when given: the increment of the
+// state and its scale in one pass.
+__global__ __launch_bounds__(256) void k_sumsq_diff(const float *__restrict__ a, const float *__restrict__ b, float s,
+                                                    float *__restrict__ dout, double *__restrict__ part, long long n)
 {
-    double s = 0.0;
+    double acc = 0.0;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
-        const double d = (double)a[e] - (b ? (double)b[e] : 0.0);
-        s += d * d;
+        const float d = (b ? a[e] - b[e] : a[e]) * s;
+        if (dout) dout[e] = d;
+        acc += (double)d * d;
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     __shared__ double sh[4];
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
@@ -776,9 +779,12 @@ static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool 
 
 // sigma of dm (normalize) into s.sig, and X[0] = bf16(dm / sigma)
 // (train: also the channel-major copy Xt[0] for the weight gradient)
-static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st, bool train = false)
+// (have_partials: the sum-of-squares partials of dm are already in s.dpart)
+static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st, bool train = false,
+                      bool have_partials = false)
 {
-    hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, dm, nullptr, s.dpart, 3 * s.N);
+    if (!have_partials)
+        hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, dm, nullptr, 1.f, nullptr, s.dpart, 3 * s.N);
     hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.dpart, RED_B,
                        (double)(3 * s.N), normalize, s.sig, s.N, train ? s.Xt[0] : nullptr, s.pg, s.nx, s.ny);
 }
@@ -872,8 +878,9 @@ static int resid(Sur &s, const float *a, const float *b, double *r, hipStream_t 
 // H = H0 + Ms * sigma * Net((Mstage - Mn) / (Ms sigma)) on stream st (no sync)
 static void sur_field(Sur &s, const float *Mstage, const float *Mn, const float *H0, float Ms, float *H, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_axpby, dim3(grid_for(3 * s.N)), dim3(256), 0, st, Mstage, Mn, 1.f / Ms, s.tmp, 3 * s.N);
-    sur_input(s, s.tmp, 1, st);
+    // the increment and its sum of squares in one pass
+    hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, Mstage, Mn, 1.f / Ms, s.tmp, s.dpart, 3 * s.N);
+    sur_input(s, s.tmp, 1, st, false, true);
     sur_forward(s, s.tmp2, st, true, false);
     hipLaunchKernelGGL(k_anchor, dim3(grid_for(3 * s.N)), dim3(256), 0, st, H0, s.tmp2, Ms, H, 3 * s.N);
 }
