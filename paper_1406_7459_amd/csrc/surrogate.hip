@@ -607,10 +607,14 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__re
 }
 
 __global__ __launch_bounds__(256) void k_refresh(const float *__restrict__ w, __bf16 *__restrict__ wb,
-                                                 __bf16 *__restrict__ wt)
+                                                 __bf16 *__restrict__ wt, long long wstride)
 {
+    // layer blockIdx.y: masters at w + layer * wstride, copies at layer * WSZ
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= WSZ) return;
+    w += blockIdx.y * wstride;
+    wb += (long long)blockIdx.y * WSZ;
+    wt += (long long)blockIdx.y * WSZ;
     const int co = e / (NT * SC), t = (e / SC) % NT, ci = e % SC;
     const __bf16 b = (__bf16)w[e];
     wb[e] = b;
@@ -728,9 +732,8 @@ static long long oracle_param_count()
 
 static void refresh(Sur &s, hipStream_t st)
 {
-    for (int l = 0; l < NLAYER; ++l)
-        hipLaunchKernelGGL(k_refresh, dim3((WSZ + 255) / 256), dim3(256), 0, st, s.w + l * layer_stride(),
-                           s.wb + (long long)l * WSZ, s.wt + (long long)l * WSZ);
+    hipLaunchKernelGGL(k_refresh, dim3((WSZ + 255) / 256, NLAYER), dim3(256), 0, st, s.w, s.wb, s.wt,
+                       layer_stride());
 }
 
 static unsigned grid_for(long long n) { return (unsigned)std::min<long long>((n + 255) / 256, 4096); }
