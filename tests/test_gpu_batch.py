@@ -88,3 +88,53 @@ def test_batch_rejects_bad_input():
     with pytest.raises(mm.MMError):
         mm.Batch([(7, 8, 2)], [(1e-9, 1e-9, 1e-9)])
     b.close()
+
+
+# ------------------------------------------------------------------------
+# The batched form against the oracle itself (not only against the
+# per-instance plans): nine uneven instances with nz in {1, 2, 3, 4, 8},
+# padded lengths with a factor 3 (6, 12, 24, 48, 96) and a single cell.
+def _oracle_params(i, integrator="rk4"):
+    import oracle
+    return oracle.Params(Ms=8e5, A=1.3e-11, Ku=1e4 * (i % 3), alpha=0.3 + 0.05 * i,
+                         Hext=(1e4 * (i - 4), 2e3 * i, -5e3), dt=1e-14, integrator=integrator)
+
+
+def test_batched_demag_matches_oracle():
+    """mm_batch_demag of every instance against the oracle's zero-padded FFT
+    convolution (paper Sec. 2 steps (1)-(5)); bar: relative L2 <= 1e-5."""
+    import oracle
+    from gpucommon import rel_l2
+    from paper_1406_7459_amd import mm
+    b = mm.Batch([s for s, _ in SMALL], [d for _, d in SMALL])
+    M0 = [8e5 * W.random_unit(*s, seed=200 + i) for i, (s, _) in enumerate(SMALL)]
+    Hb = [to_host(h) for h in b.demag([to_dev(m) for m in M0])]
+    for i, (s, d) in enumerate(SMALL):
+        Mq = to_host(to_dev(M0[i]))  # the FP32 input the GPU saw
+        Ho = oracle.Demag(*s, *d).apply(Mq)
+        err = rel_l2(Hb[i], Ho)
+        say("batch demag vs oracle", s, err)
+        assert err <= 1e-5, s
+    b.close()
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "euler"])
+def test_batched_steps_match_oracle(integrator):
+    """1 + 4 batched steps of every instance against the oracle's RK4 / Euler
+    (eq. (6)), element by element through the relative L2 of the state."""
+    import oracle
+    from gpucommon import rel_l2
+    from paper_1406_7459_amd import mm
+    b = mm.Batch([s for s, _ in SMALL], [d for _, d in SMALL])
+    M0 = [to_host(to_dev(8e5 * W.random_unit(*s, seed=300 + i))) for i, (s, _) in enumerate(SMALL)]
+    Mb = [to_dev(m) for m in M0]
+    params = [_params(mm, i, integrator) for i in range(len(SMALL))]
+    Mo = list(M0)
+    for nsteps in (1, 4):
+        b.step(params, Mb, nsteps)
+        for i, (s, d) in enumerate(SMALL):
+            Mo[i], _ = oracle.Demag(*s, *d).run(_oracle_params(i, integrator), Mo[i], nsteps)
+            err = rel_l2(to_host(Mb[i]), Mo[i])
+            say("batch", integrator, s, nsteps, err)
+            assert err < 2e-6, (s, nsteps)
+    b.close()

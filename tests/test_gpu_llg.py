@@ -223,3 +223,39 @@ def test_stage_vector_widths_are_bitwise_identical(grid, integrator):
     assert len(ws) >= 2 or nx % 2
     for w in ws[1:]:
         assert np.array_equal(out[w], out[ws[0]])
+
+
+def test_relax_matches_oracle_trajectory():
+    """mm_llg_relax on an 8^3 cube with uniaxial anisotropy (the structure of
+    the paper's cube benchmark, Sec. 4: relax to the minimum-energy state)
+    against the oracle run for the same number of steps from the same FP32
+    start: the state, E_tot and <m> agree, and the oracle's torque at that
+    state is below the tolerance the GPU stopped at."""
+    from paper_1406_7459_amd import mm
+    n = 8
+    d = (2e-9, 2e-9, 2e-9)
+    mat = W.Material(Ms=1e6, A=1.5e-11, Ku=5e4, axis=(1, 0, 0), alpha=1.0, Hext=(0.0, 0.0, 0.0))
+    pg, po = _params(mm, mat, dt=5e-14)
+    plan = mm.Plan(n, n, n, *d)
+    M0 = to_host(to_dev(mat.Ms * W.random_unit(n, n, n, seed=41)))
+    M = to_dev(M0)
+    tol = 1e5
+    st = plan.relax(pg, M, torque_tol=tol, max_steps=5000, check_every=50)
+    steps = st["steps"]
+    say("relax 8^3", steps, "steps, torque", st["torque_max"], "E", st["E_tot"])
+    assert 0 < steps < 5000 and steps % 50 == 0
+    dm = oracle.Demag(n, n, n, *d)
+    # one check interval before the stop the oracle's torque is still above
+    # the tolerance; at the stop it is below it (up to FP32 rounding)
+    Mp, _ = dm.run(po, M0, steps - 50)
+    assert dm.observables(po, Mp)["torque_max"] > 0.95 * tol
+    Mo, _ = dm.run(po, Mp, 50)
+    g = to_host(M)
+    err = rel_l2(g, Mo)
+    ob = dm.observables(po, Mo)
+    say("  state rel L2", err, "oracle E", ob["E_tot"], "oracle torque", ob["torque_max"])
+    assert err < 1e-4
+    assert st["E_tot"] == pytest.approx(ob["E_tot"], rel=1e-5)
+    assert np.allclose(st["m_avg"], ob["m_avg"], atol=1e-5)
+    assert st["torque_max"] <= tol
+    assert ob["torque_max"] <= 1.05 * tol
