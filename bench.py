@@ -3,9 +3,11 @@
 Workload ``cube128``: a 128^3 cube of 2 nm cells (padded FFT grid 256^3),
 Ms 1e6 A/m, A 1.5e-11 J/m, Ku 5e4 J/m^3 along x, alpha 0.1, gamma0 2.211e5,
 dt 1e-14 s, isotropic random initial M (seed 3128); synthetic data.  A step
-is one classical RK4 step: four demag evaluations (five FFT passes each) and
-four fused field + LLG stage kernels, all on the GPU with the state resident
-in HBM.  Prints one JSON line.
+is one classical RK4 step: four demag evaluations and four field + LLG
+stages, all on the GPU with the state resident in HBM.  With the fused
+schedule (the default) a step is XFWD(M) once, then per stage YFWD, ZCONV,
+YINV and one fused launch (x inverse of the field, the stage, x forward of
+the stage's result).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cube128]
 """
@@ -43,13 +45,31 @@ def pass_bytes(nx, ny, nz):
         b["yconv"] = 8 * nc * 2 + 4 * (4 * (ny + 1) * (nx + 1))
     # RK4 stages read/write 48N, 72N, 72N, 60N bytes: mean per launch
     b["stage"] = (48 + 72 + 72 + 60) * N / 4.0
+    # fused x-inverse / stage / x-forward: the half spectrum in (8 nc), the
+    # stage without its field (36N, 60N, 60N, 48N) and the new state's half
+    # spectrum out (8 nc; not after stage 4): mean per launch
+    b["xstage"] = ((36 + 60 + 60 + 48) * N + (16 + 16 + 16 + 8) * nc) / 4.0
     return b
+
+
+XSTAGE_BYTES = {1: (36, 16), 2: (60, 16), 3: (60, 16), 4: (48, 8)}  # (x N, x nc) per RK4 stage
+
+
+def step_bytes(nx, ny, nz, fused=True):
+    """Algorithmic bytes of one RK4 step: the unfused schedule runs four
+    complete demag evaluations and four stage kernels; the fused one runs
+    XFWD once, the middle passes four times and four fused launches."""
+    b = pass_bytes(nx, ny, nz)
+    mid = sum(v for k, v in b.items() if k in ("yfwd", "zconv", "yinv", "yconv"))
+    if not fused:
+        return 4 * (b["xfwd"] + mid + b["xinv"] + b["stage"])
+    return b["xfwd"] + 4 * mid + 4 * b["xstage"]
 
 
 # the sources the demag passes and the stage kernel are built from (the
 # kernels whose counters the traffic summary holds)
 PROFILED_SOURCES = ("fft_engine.hpp", "demag_kernels.hpp", "demag.hip", "layout.hpp", "stage_body.hpp", "llg.hip",
-                    "mm_internal.hpp")
+                    "mm_internal.hpp", "xstage_body.hpp", "xstage.hip")
 
 
 def kernel_source_hash():
@@ -118,6 +138,11 @@ def pass_tile_of(kname, blocks, threads, shape):
         if int(m.group(1)) != lens[pname]:
             return None
         return pname, p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2))), 0
+    m = re.search(r"mmk::k_xstage<(\d+), ([0-4]), (true|false)>", kname)
+    if m:
+        if int(m.group(1)) != lens["xfwd"]:
+            return None
+        return "xstage", p2(-(-(nz * ny) // (2 * blocks))), int(m.group(2))
     m = re.search(r"mmk::k_stage(_vec)?<([0-4])(?:, (\d))?>", kname)
     w = int(m.group(3)) if m and m.group(3) else 1
     if m and threads * w >= nx * ny * nz:
@@ -149,17 +174,21 @@ def summarize_trace(workload, db):
            "--workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs --no-surrogate"
            % (workload, workload, workload),
            "#   python3 bench.py --summarize-trace %s $OUT/prof_%s/%s_results.db" % (workload, workload, workload),
-           "# durations in microseconds; tile = P + 256 * variant, for the stage kernel its vector width, with",
-           "# the RK4 stage (1-4, 0 = Euler) in column s; GB/s from the algorithmic bytes per launch",
-           "# (bench.pass_bytes; stage: 48N, 72N, 72N, 60N bytes, Euler 60N) over the median duration",
+           "# durations in microseconds; tile = P + 256 * variant, for the stage kernel its vector width, for",
+           "# the fused xstage pass its row pairs per workgroup, with the RK4 stage (1-4, 0 = Euler) in column s;",
+           "# GB/s from the algorithmic bytes per launch (bench.pass_bytes; stage: 48N, 72N, 72N, 60N bytes,",
+           "# Euler 60N; xstage: 36N, 60N, 60N, 48N plus 16, 16, 16, 8 bytes per half-spectrum element)",
+           "# over the median duration",
            "%-7s %6s %2s %6s %9s %9s %9s %9s %8s" % ("pass", "tile", "s", "calls", "median", "mean", "min", "max", "GB/s")]
     N = shape[0] * shape[1] * shape[2]
+    nc = 3 * shape[2] * shape[1] * (shape[0] + 1)
     stage_bytes = {0: 60 * N, 1: 48 * N, 2: 72 * N, 3: 72 * N, 4: 60 * N}
+    xs_bytes = {k: a * N + b * nc for k, (a, b) in XSTAGE_BYTES.items()}
     for key in sorted(groups):
         pname, tile, sub = key
         d = groups[key]
         med = statistics.median(d)
-        a = stage_bytes[sub] if pname == "stage" else alg.get(pname)
+        a = stage_bytes[sub] if pname == "stage" else (xs_bytes.get(sub) if pname == "xstage" else alg.get(pname))
         out.append("%-7s %6d %2d %6d %9.2f %9.2f %9.2f %9.2f %8s" % (
             pname, tile, sub, len(d), med, statistics.mean(d), min(d), max(d), ("%.0f" % (a / med / 1e3)) if a else "-"))
     out.append("# other kernels")
@@ -201,7 +230,7 @@ def summarize_traffic(workload, pmc_dir):
     for c in ("FETCH_SIZE", "WRITE_SIZE"):
         for kname, gx, wx, v in load("sweep", c).values():
             key = pass_tile_of(kname, gx, wx, shape)
-            if key and not (key[0] == "stage" and key[2] == 0):
+            if key and not (key[0] in ("stage", "xstage") and key[2] == 0):
                 acc.setdefault(key, {}).setdefault(c, []).append(v * 1024.0 * scale[c])
     alg = pass_bytes(nx, ny, nz)
     out = ["# HBM traffic per launch, %s (%dx%dx%d cells), rocprofv3 hardware counters" % (workload, nx, ny, nz),
@@ -222,45 +251,62 @@ def summarize_traffic(workload, pmc_dir):
         if "FETCH_SIZE" not in d or "WRITE_SIZE" not in d:
             continue
         f, w = statistics.median(d["FETCH_SIZE"]), statistics.median(d["WRITE_SIZE"])
-        if pname == "stage":
-            stage.setdefault(tile, []).append(f + w)
+        if pname in ("stage", "xstage"):
+            stage.setdefault((pname, tile), []).append(f + w)
             continue
         a = alg.get(pname)
         out.append("# %-6s tile %4d: fetch %11.0f write %11.0f  (x%.2f of algorithmic %d)"
                    % (pname, tile, f, w, (f + w) / a if a else 0.0, a or 0))
         out.append("hbm_bytes_per_launch.%s.%d: %.0f" % (pname, tile, f + w))
-    for tile in sorted(stage):
-        v = sum(stage[tile]) / len(stage[tile])
-        out.append("# stage  tile %4d: RK4 stages 1-4 mean %.0f (x%.2f of algorithmic %d)"
-                   % (tile, v, v / alg["stage"], alg["stage"]))
-        out.append("hbm_bytes_per_launch.stage.%d: %.0f" % (tile, v))
+    for pname, tile in sorted(stage):
+        v = sum(stage[(pname, tile)]) / len(stage[(pname, tile)])
+        out.append("# %-6s tile %4d: RK4 stages 1-4 mean %.0f (x%.2f of algorithmic %d)"
+                   % (pname, tile, v, v / alg[pname], alg[pname]))
+        out.append("hbm_bytes_per_launch.%s.%d: %.0f" % (pname, tile, v))
     return "\n".join(out) + "\n"
 
 
-def cpu_baseline(budget_s=30.0):
-    """The CPU oracle (single-threaded FP64 C), timed on a bounded sample of
-    the cube workload: the same material and cells on a 32^3 cube, set-up
-    excluded, RK4 steps until ~10 s have elapsed."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline():
+    """The CPU oracle (single-threaded FP64 C) timed on the host: one RK4 step
+    of the cube workload's material on a 64^3 cube (its own set-up excluded,
+    timed separately), and the 128^3 headline grid extrapolated from it by
+    the FFT route's N log N cost (labelled as extrapolated)."""
+    import math
     import oracle
     from paper_1406_7459_amd import workloads as W
-    wl = W.cube(32)
+    wl = W.cube(64)
     nx, ny, nz = wl.shape
+    t0 = time.perf_counter()
     dm = oracle.Demag(nx, ny, nz, *wl.cell)
+    setup = time.perf_counter() - t0
     m = wl.mat
     p = oracle.Params(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha, gamma0=m.gamma0,
                       Hext=m.Hext, dt=m.dt)
     M = m.Ms * wl.initial_unit()
-    steps = 0
     t0 = time.perf_counter()
-    while True:
-        M, _ = dm.run(p, M, 1)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > 10.0 or el > budget_s:
-            break
-    return dict(value=wl.cells * steps / el, unit="cell-updates/s", cores=1, kind="oracle",
-                sample="cube32 (32^3 cells, same material and 2 nm cells), %d RK4 steps in %.1f s, "
-                       "oracle set-up excluded" % (steps, el))
+    M, _ = dm.run(p, M, 1)
+    step = time.perf_counter() - t0
+    rate = wl.cells / step
+    n64, n128 = 8 * 64 ** 3, 8 * 128 ** 3  # padded FFT points
+    step128 = step * (n128 * math.log2(n128)) / (n64 * math.log2(n64))
+    return dict(value=rate, unit="cell-updates/s", cores=1, kind="oracle",
+                host_cpus=os.cpu_count(), cpu_model=cpu_model(),
+                sample="cube64 (64^3 cells, the cube workload's material, 2 nm cells): 1 RK4 step "
+                       "(4 demag evaluations by the padded FFT route) in %.1f s, oracle set-up "
+                       "(Newell tensor and its transform) %.1f s excluded" % (step, setup),
+                cube128_extrapolated={"s_per_step": step128, "cell_updates_per_s": 128 ** 3 / step128,
+                                      "how": "extrapolated from the cube64 step by N log N of the "
+                                             "padded FFT grid (not run)"})
 
 
 def oracle_error_sample(plan, wl, torch):
@@ -516,11 +562,11 @@ def other_configs(torch, mm, W):
         torch.cuda.synchronize()
         dm = (time.perf_counter() - t0) / 50
         b = pass_bytes(nx, ny, nz)
-        step_bytes = sum(4 * v for v in b.values())
-        demag_bytes = sum(v for k, v in b.items() if k != "stage")
+        sbytes = step_bytes(nx, ny, nz, fused=tiles.get("xstage", 0) > 0)
+        demag_bytes = sum(v for k, v in b.items() if k not in ("stage", "xstage"))
         out[wl.name] = {"grid": [nx, ny, nz], "ms_per_step": st * 1e3,
                         "cell_updates_per_s": nx * ny * nz / st,
-                        "step_roofline_frac": step_bytes / st / 1e9 / HBM_PEAK_GBS,
+                        "step_roofline_frac": sbytes / st / 1e9 / HBM_PEAK_GBS,
                         "demag_ms": dm * 1e3, "demag_roofline_frac": demag_bytes / dm / 1e9 / HBM_PEAK_GBS,
                         "tiles": tiles}
         plan.close()
@@ -620,8 +666,18 @@ def main():
             plan.set_tile(pname, dflt[pname])
         pw = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=m.alpha,
                                gamma0=m.gamma0, Hext=m.Hext, dt=m.dt)
+        plan.set_tile("xstage", 0)
         for _ in range(3):
             plan.step(pw, Mw, 1)  # the four RK4 stage kernels, launched directly
+        for P in (1, 2, 4, 8, 16, 32, 64):
+            try:
+                plan.set_tile("xstage", P)
+            except mm.MMError:
+                continue
+            for _ in range(3):
+                plan.step(pw, Mw, 1)  # the four fused launches of a step
+            done.append("xstage.%d" % P)
+        plan.set_tile("xstage", dflt["xstage"])
         torch.cuda.synchronize()
         print(json.dumps({"sweep": name, "tiles": done}))
         return
@@ -676,6 +732,8 @@ def main():
     euler_ms = (time.perf_counter() - t1) / args.steps * 1e3
 
     bytes_per = pass_bytes(nx, ny, nz)
+    fused = tiles.get("xstage", 0) > 0
+    sbytes = step_bytes(nx, ny, nz, fused)
     kern = {}
     for k, (ms, n) in per_kernel.items():
         if n > 0:
@@ -706,6 +764,8 @@ def main():
                    "demag_evals_per_step": 4},
         "demag_evals_per_s": 1e3 / demag_ms,
         "demag_ms": demag_ms,
+        "demag_roofline_frac": sum(v for k, v in bytes_per.items() if k not in ("stage", "xstage"))
+                               / (demag_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "euler_ms_per_step": euler_ms,
         "euler_cell_updates_per_s": cells / (euler_ms * 1e-3),
         "oracle_err": {"H_demag_rel_l2": err, "bar": 1e-5,
@@ -719,8 +779,10 @@ def main():
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": bytes_per[dom]},
         "step_roofline": {
-            "algorithmic_bytes_per_step": sum(4 * v for k, v in bytes_per.items()),
-            "achieved_GBs": sum(4 * v for k, v in bytes_per.items()) / (el / args.steps) / 1e9,
+            "schedule": "fused" if fused else "unfused",
+            "algorithmic_bytes_per_step": sbytes,
+            "achieved_GBs": sbytes / (el / args.steps) / 1e9,
+            "unfused_schedule_bytes_per_step": step_bytes(nx, ny, nz, fused=False),
         },
         "paper_context": {"table1_128cube_euler_ms_HD7970_fp32": 26.34,
                           "note": "paper Table 1, Euler, AMD HD 7970, other hardware: context only"},

@@ -17,6 +17,12 @@
  *     fastest, cells zero-indexed; SI units (A/m), lengths in metres.
  *   - Pointers named *_dev are device (HBM) pointers owned by the caller;
  *     the library never frees them.  Host pointers are named plainly.
+ *   - Device memory: the library allocates none.  Every object (plan, batch,
+ *     surrogate) reports the bytes it needs (mm_*_workspace_bytes) and works
+ *     in a caller-allocated workspace bound to it (mm_*_bind_workspace; 256-
+ *     byte aligned, owned by the caller, kept alive and untouched by the
+ *     caller until the object is destroyed or re-bound).  The library owns
+ *     only host-side metadata, a capture stream and HIP graphs.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     All device work is enqueued asynchronously on it unless the entry point
  *     says it synchronises.
@@ -47,6 +53,7 @@ enum {
 };
 
 enum { MM_RK4 = 0, MM_EULER = 1 };
+enum { MM_EXACT = 0, MM_SURROGATE = 1 };
 
 /* Opaque plan: grid, Newell spectrum, FFT launch configuration, workspace. */
 typedef struct mm_plan_s *mm_plan;
@@ -61,7 +68,12 @@ typedef struct mm_plan_s *mm_plan;
  *  Hext    applied field [A/m]
  *  dt      time step [s]
  *  integrator MM_RK4 (classical, 4 field evaluations per step) or MM_EULER
- *  renorm  1: M <- Ms M/|M| after every step, 0: leave |M| free          */
+ *  renorm  1: M <- Ms M/|M| after every step, 0: leave |M| free
+ *  demag_mode MM_EXACT (FFT demag at every stage) or MM_SURROGATE (the
+ *          learned increment attached with mm_sur_attach in RK stages 2-4)
+ *  log_every  with a stats array, observables after every log_every steps
+ *          (<= 0: only after the last step)
+ *  sur_tol relative residual above which a surrogate step is redone exactly */
 typedef struct {
     double Ms, A, Ku;
     double axis[3];
@@ -70,16 +82,22 @@ typedef struct {
     double dt;
     int integrator;
     int renorm;
+    int demag_mode;
+    int log_every;
+    double sur_tol;
 } mm_llg_params;
 
 /* Observables of a state (Sec. 2, eq. (1) with V = dx dy dz per cell):
  * energies in J, torque_max = max_i |M_i x H_eff,i| / Ms in A/m,
- * m_avg = (1/N) sum M/Ms, nonfinite = number of cells holding NaN/Inf.    */
+ * m_avg = (1/N) sum M/Ms, nonfinite = number of cells holding NaN/Inf;
+ * steps = steps taken before the state was observed (in the call), and
+ * fallbacks = surrogate steps redone exactly by then.                      */
 typedef struct {
     double E_ex, E_an, E_d, E_z, E_tot;
     double torque_max;
     double m_avg[3];
     long long nonfinite;
+    long long steps, fallbacks;
 } mm_stats;
 
 /* Plan description filled by mm_plan_query. */
@@ -87,8 +105,8 @@ typedef struct {
     int nx, ny, nz;
     int Lx, Ly, Lz;            /* padded FFT lengths 2nx, 2ny, 2nz (Lz = 1 when nz = 1: collapsed) */
     long long spectrum_count;  /* floats in the stored K~ octant: 6 * (nx+1)(ny+1)(nz+1), nz=1: 6(nx+1)(ny+1) */
-    long long workspace_bytes; /* device bytes held by the plan */
-    int cfg[8];                /* launch tile per pass kind (see MM_PASS_*) */
+    long long workspace_bytes; /* device bytes the plan works in (mm_plan_workspace_bytes) */
+    int cfg[9];                /* launch tile per pass kind (see MM_PASS_*) */
 } mm_plan_info;
 
 /* Pass kinds of one demag evaluation, for tiles and per-kernel timing. */
@@ -101,32 +119,57 @@ enum {
     MM_PASS_YCONV = 5,  /* nz = 1: y forward, K~ . M~, y inverse in one pass                 */
     MM_PASS_STAGE = 6,  /* fused H_eff + LLG stage update                                    */
     MM_PASS_REDUCE = 7, /* observables reduction                                             */
-    MM_PASS_COUNT = 8
+    MM_PASS_XSTAGE = 8, /* fused: x inverse of the field, LLG stage, x forward of the result  */
+    MM_PASS_COUNT = 9
 };
 
-/* Build a plan for an nx x ny x nz grid of dx x dy x dz cells (Sec. 2,
- * eq. (7)-(12), set-up of K~ per the remark after eq. (16)).  Computes the
- * Newell tensor in FP64 on the current device, its transform in FP64 by
- * separable cosine/sine sums, and stores the real, parity-folded octant of
- * K~ = FFT(-N)/(2nx 2ny 2nz) in FP32, one six-float record per frequency.  Allocates the plan's workspace with
- * hipMalloc and synchronises the device before returning.
+/* Describe a plan for an nx x ny x nz grid of dx x dy x dz cells (Sec. 2,
+ * cell labelling and eq. (7)-(12)): sizes, padded transform lengths, launch
+ * configuration and the workspace it needs.  Allocates no device memory;
+ * the plan computes nothing until a workspace is bound.
  * Supported n per axis: 2^a or 3*2^a, 1 <= n <= 512 (padded lengths 2n of
  * 2, 4, 6, 8, 12, 16, 24, ..., 512, 768, 1024: radices 2, 3, 4, 8).
- * Errors: MM_EINVAL (bad sizes), MM_ENODEV, MM_ENOMEM, MM_EHIP.            */
+ * Errors: MM_EINVAL (bad sizes), MM_ENODEV, MM_EHIP.                        */
 int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_plan *out);
+
+/* Device bytes the plan works in: K~, twiddles, reduction records and the
+ * run-time buffers (half spectra X1 [3][nz][ny][xp] and X2 [3][nz][2ny][xp]
+ * c64 with xp = nx+1 rounded up to 16, demag field and RK4 states 4 x
+ * [3][nz][ny][nx] f32).                                                     */
+int mm_plan_workspace_bytes(mm_plan plan, size_t *bytes);
+
+/* Bind a caller-allocated device workspace of `bytes` >= the size above
+ * (256-byte aligned) and compute K~ into it (set-up of the transform of the
+ * demag kernel, remark after eq. (16)): the Newell tensor in FP64 on the
+ * current device, its transform in FP64 by separable cosine/sine sums, and
+ * the real, parity-folded octant of K~ = FFT(-N)/(2nx 2ny 2nz) stored in
+ * FP32, one six-float record per frequency.  Synchronises the device.  A
+ * second bind moves the plan to the new workspace (K~ is recomputed).
+ * Errors: MM_EINVAL (NULL, misaligned), MM_ENOMEM (too small), MM_EHIP.   */
+int mm_plan_bind_workspace(mm_plan plan, void *ws_dev, size_t bytes);
 
 /* H_dev = demagnetising field of M_dev (eq. (11)-(16)).  M_dev, H_dev:
  * [3][nz][ny][nx] float32 device arrays, not aliased.  Asynchronous.
- * Errors: MM_EINVAL (NULL plan/pointer, M == H), MM_EHIP.                  */
+ * Errors: MM_EINVAL (NULL plan/pointer, M == H, no workspace bound), MM_EHIP. */
 int mm_demag_apply(mm_plan plan, const float *M_dev, float *H_dev, void *stream);
 
 /* Advance M_dev (in place) by nsteps time steps of eq. (6) under H_eff of
  * eq. (2), with classical RK4 (four demag evaluations per step) or explicit
- * Euler (one).  nsteps = 0 is a no-op.  Asynchronous; the steps are
+ * Euler (one); params->demag_mode MM_SURROGATE takes the attached learned
+ * increment in RK stages 2-4 (see mm_llg_step_surrogate).  The steps are
  * replayed from a captured HIP graph after the first call with the same
- * (M_dev, params).  Errors: MM_EINVAL (NULL, nsteps < 0, Ms <= 0, dt not
- * finite), MM_EHIP.                                                         */
-int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M_dev, int nsteps,
+ * (M_dev, params).
+ * stats (host, nullable): NULL -> asynchronous.  Else the call fills
+ * ceil(nsteps / e) records, e = log_every if 0 < log_every < nsteps, else
+ * nsteps (one record; nsteps = 0 gives one record of the current state):
+ * record k holds the observables (as mm_reduce) of the state after
+ * min((k+1) e, nsteps) steps, each taken with one extra demag evaluation
+ * and an FP64 reduction into device records, read back when RED_LOG (256)
+ * are pending and at the end; the call then synchronises `stream` and
+ * returns MM_ENONFINITE if a record holds a non-finite cell.
+ * Errors: MM_EINVAL (NULL, nsteps < 0, Ms <= 0, dt not finite, no workspace,
+ * MM_SURROGATE without an attached surrogate), MM_ENONFINITE, MM_EHIP.      */
+int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M_dev, int nsteps, mm_stats *stats,
                 void *stream);
 
 /* Observables of state M_dev (energies per eq. (1), max torque, <m>, NaN
@@ -139,8 +182,9 @@ int mm_reduce(mm_plan plan, const mm_llg_params *params, const float *M_dev, mm_
 /* Relax toward the minimum-energy state (the paper's benchmark runs, Sec. 4,
  * relax a cube under demag, exchange and anisotropy): step with `params`
  * until max_i |M_i x H_eff,i| / Ms <= torque_tol, checking every
- * `check_every` steps, or until max_steps.  Fills *out with the final
- * observables and *steps_taken.  Synchronises at every check.              */
+ * `check_every` steps (mm_llg_step with a stats record), or until
+ * max_steps.  Fills *out with the final observables (out->steps = steps
+ * taken) and *steps_taken.  Synchronises at every check.                    */
 int mm_llg_relax(mm_plan plan, const mm_llg_params *params, float *M_dev, double torque_tol, long long max_steps,
                  int check_every, mm_stats *out, long long *steps_taken, void *stream);
 
@@ -171,7 +215,11 @@ int mm_plan_query(mm_plan plan, mm_plan_info *info);
  * For MM_PASS_STAGE the tile is the vector width W in {1, 2, 4}: W
  * consecutive cells of an x row per thread (nx % W == 0; default 4 when
  * nx % 4 == 0; a launch whose arrays are not aligned to 4W bytes falls back
- * to a narrower width).  Every configuration computes bitwise the same
+ * to a narrower width).  For MM_PASS_XSTAGE the tile is P = 2^k pairs of
+ * cell rows per workgroup of the fused pass that runs, per RK stage, the x
+ * inverse of the field, the stage and the x forward of its result (the
+ * field is never stored; the default), or 0 for the unfused path (XINV,
+ * stage kernel, XFWD).  Every configuration computes bitwise the same
  * result.  Returns MM_EINVAL for a configuration the pass cannot launch.    */
 int mm_plan_set_tile(mm_plan plan, int pass, int tile);
 
@@ -204,11 +252,21 @@ int mm_plan_timing(mm_plan plan, double *total_ms, long long *launches);
  * ------------------------------------------------------------------------ */
 typedef struct mm_batch_s *mm_batch;
 
-/* Build `count` plans (arrays of per-instance sizes and cells, host memory;
- * each instance as in mm_demag_setup) and their task tables.  Synchronises.
+/* Describe `count` plans (arrays of per-instance sizes and cells, host
+ * memory; each instance as in mm_demag_setup) and their task tables.
+ * Allocates no device memory.
  * Errors: those of mm_demag_setup, MM_EINVAL (count < 1, NULL array).      */
 int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const double *dx, const double *dy,
                    const double *dz, mm_batch *out);
+
+/* Device bytes of the batch: every instance's plan workspace, the task
+ * tables (sized for the largest candidate tile) and the instance tables.   */
+int mm_batch_workspace_bytes(mm_batch batch, size_t *bytes);
+
+/* Bind a caller-allocated device workspace (>= the size above, 256-byte
+ * aligned): binds every instance's plan (computing its K~) and uploads the
+ * tables.  Synchronises.  Errors: MM_EINVAL, MM_ENOMEM (too small), MM_EHIP. */
+int mm_batch_bind_workspace(mm_batch batch, void *ws_dev, size_t bytes);
 
 /* Demag field of every instance: M_dev[i] -> H_dev[i] (host arrays of
  * `count` device pointers, layout as mm_demag_apply, not aliased).  Waits
@@ -257,9 +315,25 @@ typedef struct {
     double last_residual, max_residual, sum_residual;  /* |H_s - H_d| / |H_d| */
 } mm_sur_stats;
 
-/* Network and training buffers for an nx x ny x nz grid of at most 2^25
- * cells (MM_EINVAL otherwise, before any device work); weights zero. */
+/* Describe a network for an nx x ny x nz grid of at most 2^25 cells
+ * (MM_EINVAL otherwise, before any device work).  Allocates no device
+ * memory: bind a workspace before any other call.                          */
 int mm_sur_create(int nx, int ny, int nz, mm_sur *out);
+
+/* Device bytes of the network's weights, Adam state, activations and
+ * training buffers (BF16 activations [N][32] per layer, padded
+ * channel-major copies for the weight gradient, FP32 scratch fields).      */
+int mm_sur_workspace_bytes(mm_sur sur, size_t *bytes);
+
+/* Bind a caller-allocated device workspace (>= the size above, 256-byte
+ * aligned); zeroes the weights and Adam state.  Synchronises.
+ * Errors: MM_EINVAL (NULL, misaligned), MM_ENOMEM (too small), MM_EHIP.   */
+int mm_sur_bind_workspace(mm_sur sur, void *ws_dev, size_t bytes);
+
+/* Attach a bound network to a plan of the same grid (NULL detaches), so
+ * that mm_llg_step with params->demag_mode = MM_SURROGATE uses it in RK
+ * stages 2-4 with params->sur_tol as the residual gate.                    */
+int mm_sur_attach(mm_plan plan, mm_sur sur);
 long long mm_sur_param_count(void);
 int mm_sur_set_params(mm_sur sur, const float *params, long long n);  /* host; resets Adam state */
 int mm_sur_get_params(mm_sur sur, float *params, long long n);

@@ -94,24 +94,19 @@ static void drop_plan_graph(Plan &p)
 }
 
 // ------------------------------------------------------------------- plan ---
-static int upload_twiddles(int L, float2 **dst, std::vector<void *> &owned)
+// Twiddle table exp(-2 pi i m / L), m < L, built in FP64 and rounded once.
+static std::vector<float2> twiddle_table(int L)
 {
     std::vector<float2> h((size_t)L);
     for (int m = 0; m < L; ++m) {
         const double a = -2.0 * M_PI * (double)m / (double)L;
         h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
     }
-    float2 *d = nullptr;
-    MMK_HIP(hipMalloc(&d, sizeof(float2) * (size_t)L));
-    owned.push_back(d);
-    MMK_HIP(hipMemcpy(d, h.data(), sizeof(float2) * (size_t)L, hipMemcpyHostToDevice));
-    *dst = d;
-    return MM_OK;
+    return h;
 }
 
 struct PlanOwner {
     Plan p;
-    std::vector<void *> owned;
 };
 
 static void free_plan(PlanOwner *o)
@@ -125,7 +120,6 @@ static void free_plan(PlanOwner *o)
         (void)hipEventDestroy(t.second.second);
     }
     for (auto e : p.event_pool) (void)hipEventDestroy(e);
-    for (void *ptr : o->owned) (void)hipFree(ptr);
     delete o;
 }
 
@@ -138,6 +132,56 @@ static int check_grid(int nx, int ny, int nz, double dx, double dy, double dz)
     if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dx) || !std::isfinite(dy) ||
         !std::isfinite(dz))
         return fail(MM_EINVAL, "cell sizes must be finite and > 0");
+    return MM_OK;
+}
+
+// Carve the plan's workspace (base == nullptr: only measure it) and return
+// its size.  Order: K~, twiddles, reduction partials and records, then the
+// run-time buffers X1, X2, H, Sa, Sb, kacc.  The spectrum set-up borrows the
+// run-time region for its FP64 scratch before any step runs, so the region
+// is at least that large.
+size_t plan_layout(Plan &p, char *base)
+{
+    const size_t N = (size_t)p.nx * p.ny * p.nz;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const size_t szK = sizeof(float) * 6 * (size_t)p.nzK * (ny + 1) * p.xp;
+    const size_t szX1 = sizeof(float2) * 3 * (size_t)nz * ny * p.xp;
+    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * 2 * ny * p.xp : 0;
+    const size_t szF = sizeof(float) * 3 * N;
+    const size_t szPart = sizeof(double) * 9 * (size_t)p.red_blocks;
+    const size_t szRed = sizeof(double) * 16 * (size_t)RED_LOG;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t tw = 0;
+    const int Ls[3] = {p.Lx, p.Ly, nz > 1 ? p.Lz : 0};
+    for (int a = 0; a < 3; ++a) tw += Ls[a] ? al(sizeof(float2) * (size_t)Ls[a]) : 0;
+    const size_t run = al(szX1) + al(szX2) + 4 * al(szF);
+    const size_t scratch = al(spectrum_scratch_bytes(nx, ny, nz));
+    const size_t total = al(szK) + tw + al(szPart) + al(szRed) + (run > scratch ? run : scratch);
+    if (!base) return total;
+    char *cur = base;
+    p.Kt = (float *)cur; cur += al(szK);
+    for (int a = 0; a < 3; ++a) {
+        p.tw[a] = nullptr;
+        if (!Ls[a]) continue;
+        p.tw[a] = (float2 *)cur;
+        cur += al(sizeof(float2) * (size_t)Ls[a]);
+    }
+    p.part = (double *)cur; cur += al(szPart);
+    p.red = (double *)cur; cur += al(szRed);
+    p.run = cur;
+    p.X1 = (float2 *)cur; cur += al(szX1);
+    p.X2 = szX2 ? (float2 *)cur : nullptr; cur += al(szX2);
+    p.H = (float *)cur; cur += al(szF);
+    p.Sa = (float *)cur; cur += al(szF);
+    p.Sb = (float *)cur; cur += al(szF);
+    p.kacc = (float *)cur;
+    return total;
+}
+
+int plan_ready(const Plan *p)
+{
+    if (!p) return fail(MM_EINVAL, "NULL plan");
+    if (!p->ws) return fail(MM_EINVAL, "plan has no workspace: call mm_plan_bind_workspace first");
     return MM_OK;
 }
 
@@ -214,42 +258,12 @@ int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_p
         if (p.lds_limit > 160 * 1024) p.lds_limit = 160 * 1024;
         if (p.lds_limit < 32768) p.lds_limit = 32768;
     }
-    const size_t N = (size_t)nx * ny * nz;
     p.nK = 6LL * p.nzK * (ny + 1) * (nx + 1);
     p.red_blocks = 1024;
-    const size_t szK = sizeof(float) * 6 * (size_t)p.nzK * (ny + 1) * p.xp;
-    const size_t szX1 = sizeof(float2) * 3 * (size_t)nz * ny * p.xp;
-    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * 2 * ny * p.xp : 0;
-    const size_t szF = sizeof(float) * 3 * N;
-    const size_t szPart = sizeof(double) * 9 * (size_t)p.red_blocks;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t total = al(szK) + al(szX1) + al(szX2) + 4 * al(szF) + al(szPart) + al(16 * sizeof(double));
-    char *base = nullptr;
-    if (hipMalloc(&base, total) != hipSuccess) {
-        (void)hipGetLastError();
-        free_plan(o);
-        return fail(MM_ENOMEM, "plan workspace (" + std::to_string(total) + " bytes)");
-    }
-    o->owned.push_back(base);
-    p.bytes = total;
-    char *cur = base;
-    p.Kt = (float *)cur; cur += al(szK);
-    p.X1 = (float2 *)cur; cur += al(szX1);
-    p.X2 = szX2 ? (float2 *)cur : nullptr; cur += al(szX2);
-    p.H = (float *)cur; cur += al(szF);
-    p.Sa = (float *)cur; cur += al(szF);
-    p.Sb = (float *)cur; cur += al(szF);
-    p.kacc = (float *)cur; cur += al(szF);
-    p.part = (double *)cur; cur += al(szPart);
-    p.red = (double *)cur;
+    p.bytes = plan_layout(p, nullptr);
     const int Ls[3] = {p.Lx, p.Ly, nz > 1 ? p.Lz : 0};
-    for (int a = 0; a < 3; ++a) {
-        if (!Ls[a]) continue;
-        if ((rc = upload_twiddles(Ls[a], &p.tw[a], o->owned)) != MM_OK) {
-            free_plan(o);
-            return rc;
-        }
-    }
+    for (int a = 0; a < 3; ++a)
+        if (Ls[a]) p.tw_host[a] = twiddle_table(Ls[a]);
     if ((rc = prepare_kernels(p)) != MM_OK) {
         free_plan(o);
         return rc;
@@ -259,16 +273,38 @@ int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_p
         free_plan(o);
         return fail(MM_EHIP, "stream create");
     }
-    if ((rc = build_spectrum(p, nullptr)) != MM_OK) {
-        free_plan(o);
-        return rc;
-    }
-    if (hipDeviceSynchronize() != hipSuccess) {
-        free_plan(o);
-        return fail(MM_EHIP, "set-up sync");
-    }
     mm_plan h = new mm_plan_s{o};
     *out = h;
+    return MM_OK;
+}
+
+int mm_plan_workspace_bytes(mm_plan plan, size_t *bytes)
+{
+    Plan *p = P(plan);
+    if (!p || !bytes) return fail(MM_EINVAL, "NULL plan or bytes");
+    *bytes = p->bytes;
+    return MM_OK;
+}
+
+int mm_plan_bind_workspace(mm_plan plan, void *ws, size_t bytes)
+{
+    Plan *p = P(plan);
+    if (!p || !ws) return fail(MM_EINVAL, "NULL plan or workspace");
+    if ((uintptr_t)ws % 256 != 0) return fail(MM_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < p->bytes)
+        return fail(MM_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes; the plan needs " +
+                                   std::to_string(p->bytes));
+    drop_plan_graph(*p);
+    p->ws = nullptr;
+    plan_layout(*p, (char *)ws);
+    for (int a = 0; a < 3; ++a)
+        if (!p->tw_host[a].empty())
+            MMK_HIP(hipMemcpy(p->tw[a], p->tw_host[a].data(), sizeof(float2) * p->tw_host[a].size(),
+                              hipMemcpyHostToDevice));
+    int rc = build_spectrum(*p, nullptr);
+    if (rc != MM_OK) return rc;
+    MMK_HIP(hipDeviceSynchronize());
+    p->ws = (char *)ws;
     return MM_OK;
 }
 
@@ -282,7 +318,9 @@ void mm_destroy(mm_plan plan)
 int mm_demag_apply(mm_plan plan, const float *M, float *H, void *stream)
 {
     Plan *p = P(plan);
-    if (!p || !M || !H) return fail(MM_EINVAL, "NULL plan or pointer");
+    int rc = plan_ready(p);
+    if (rc != MM_OK) return rc;
+    if (!M || !H) return fail(MM_EINVAL, "NULL pointer");
     if ((const void *)M == (const void *)H) return fail(MM_EINVAL, "M and H alias");
     return demag_enqueue(*p, M, H, (hipStream_t)stream);
 }
@@ -295,37 +333,39 @@ static int check_params(const mm_llg_params *q)
         !std::isfinite(q->Ku))
         return fail(MM_EINVAL, "non-finite parameter");
     if (q->integrator != MM_RK4 && q->integrator != MM_EULER) return fail(MM_EINVAL, "unknown integrator");
+    if (q->demag_mode != MM_EXACT && q->demag_mode != MM_SURROGATE) return fail(MM_EINVAL, "unknown demag mode");
     const double u2 = q->axis[0] * q->axis[0] + q->axis[1] * q->axis[1] + q->axis[2] * q->axis[2];
     if (q->Ku != 0.0 && !(std::fabs(u2 - 1.0) < 1e-6)) return fail(MM_EINVAL, "anisotropy axis must be a unit vector");
     return MM_OK;
 }
 
-int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M, int nsteps, void *stream)
+// n exact steps: direct launches (timing mode, or a single step), else
+// replays of a captured graph: one RK4 step, or a pair of Euler steps (M ->
+// Sa -> M, no copy) with a single copying step for an odd count.
+static int exact_steps(Plan &p, const mm_llg_params &q, const StageCoef &c, float *M, int n, hipStream_t s)
 {
-    Plan *p = P(plan);
-    if (!p || !M) return fail(MM_EINVAL, "NULL plan or M");
-    int rc = check_params(params);
-    if (rc != MM_OK) return rc;
-    if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
-    if (nsteps == 0) return MM_OK;
-    hipStream_t s = (hipStream_t)stream;
-    const StageCoef c = stage_coef(*p, *params);
+    int rc;
     static const bool no_graph = std::getenv("MM_NO_GRAPH") != nullptr;
-    if (p->timing || no_graph || nsteps < 2) {
+    const bool euler = q.integrator == MM_EULER;
+    const int unit = euler ? 2 : 1;  // steps per graph replay
+    if (p.timing || no_graph || n < 2) {
         // direct launches (timing mode brackets every one with HIP events)
-        for (int i = 0; i < nsteps; ++i)
-            if ((rc = llg_enqueue_step(*p, c, params->integrator, M, s)) != MM_OK) return rc;
+        int i = 0;
+        for (; euler && i + 2 <= n; i += 2)
+            if ((rc = llg_enqueue_euler_pair(p, c, M, s)) != MM_OK) return rc;
+        for (; i < n; ++i)
+            if ((rc = llg_enqueue_step(p, c, q.integrator, M, s)) != MM_OK) return rc;
         return MM_OK;
     }
     std::string key((const char *)&c, sizeof(c));
-    key += std::string((const char *)&params->integrator, sizeof(int));
-    key += std::string((const char *)p->tile, sizeof(p->tile));
-    if (!p->graph.exec || p->graph.M != M || p->graph.key != key) {
-        drop_plan_graph(*p);
-        MMK_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-        rc = llg_enqueue_step(*p, c, params->integrator, M, p->cap_stream);
+    key += std::string((const char *)&q.integrator, sizeof(int));
+    key += std::string((const char *)p.tile, sizeof(p.tile));
+    if (!p.graph.exec || p.graph.M != M || p.graph.key != key) {
+        drop_plan_graph(p);
+        MMK_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+        rc = euler ? llg_enqueue_euler_pair(p, c, M, p.cap_stream) : llg_enqueue_step(p, c, q.integrator, M, p.cap_stream);
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        hipError_t e = hipStreamEndCapture(p.cap_stream, &g);
         if (rc != MM_OK || e != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
             return rc != MM_OK ? rc : fail(MM_EHIP, std::string("capture: ") + hipGetErrorString(e));
@@ -336,40 +376,100 @@ int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M, int nsteps,
             (void)hipGraphDestroy(g);
             return fail(MM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
         }
-        p->graph.graph = g;
-        p->graph.exec = x;
-        p->graph.M = M;
-        p->graph.key = key;
+        p.graph.graph = g;
+        p.graph.exec = x;
+        p.graph.M = M;
+        p.graph.key = key;
     }
-    for (int i = 0; i < nsteps; ++i) MMK_HIP(hipGraphLaunch(p->graph.exec, s));
+    for (int i = 0; i + unit <= n; i += unit) MMK_HIP(hipGraphLaunch(p.graph.exec, s));
+    if (n % unit) return llg_enqueue_step(p, c, q.integrator, M, s);
+    return MM_OK;
+}
+
+int mm_llg_step(mm_plan plan, const mm_llg_params *params, float *M, int nsteps, mm_stats *stats, void *stream)
+{
+    Plan *p = P(plan);
+    int rc = plan_ready(p);
+    if (rc != MM_OK) return rc;
+    if (!M) return fail(MM_EINVAL, "NULL M");
+    if ((rc = check_params(params)) != MM_OK) return rc;
+    if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
+    const bool sur = params->demag_mode == MM_SURROGATE;
+    if (sur && !p->sur) return fail(MM_EINVAL, "MM_SURROGATE needs a surrogate attached with mm_sur_attach");
+    if (sur && params->integrator != MM_RK4) return fail(MM_EINVAL, "surrogate stepping needs RK4");
+    hipStream_t s = (hipStream_t)stream;
+    const StageCoef c = stage_coef(*p, *params);
+    // chunks of `every` steps; after each one (when stats are asked for) the
+    // observables of the state are reduced into a device record
+    const int every = (stats && params->log_every > 0 && params->log_every < nsteps) ? params->log_every
+                                                                                      : (nsteps > 0 ? nsteps : 1);
+    long long done = 0, fallbacks = 0;
+    int rec = 0, out = 0;
+    std::vector<long long> rec_steps, rec_fb;
+    auto flush = [&]() -> int {
+        if (rec == 0) return MM_OK;
+        std::vector<double> h((size_t)16 * rec);
+        MMK_HIP(hipMemcpyAsync(h.data(), p->red, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        MMK_HIP(hipStreamSynchronize(s));
+        for (int k = 0; k < rec; ++k) {
+            mm_stats &o = stats[out + k];
+            stats_from_record(*p, *params, &h[(size_t)16 * k], &o);
+            o.steps = rec_steps[k];
+            o.fallbacks = rec_fb[k];
+        }
+        out += rec;
+        rec = 0;
+        rec_steps.clear();
+        rec_fb.clear();
+        return MM_OK;
+    };
+    do {
+        const int k = (int)std::min<long long>(every, nsteps - done);
+        if (k > 0) {
+            if (sur) {
+                mm_sur_stats st{};
+                rc = mm_llg_step_surrogate(plan, (mm_sur)p->sur, params, M, k, params->sur_tol, &st, stream);
+                fallbacks += st.fallbacks;
+            } else {
+                rc = exact_steps(*p, *params, c, M, k, s);
+            }
+            if (rc != MM_OK) return rc;
+            done += k;
+        }
+        if (stats) {
+            if ((rc = demag_enqueue(*p, M, p->H, s)) != MM_OK) return rc;
+            if ((rc = reduce_enqueue(*p, *params, M, p->H, s, rec)) != MM_OK) return rc;
+            rec_steps.push_back(done);
+            rec_fb.push_back(fallbacks);
+            if (++rec == RED_LOG && (rc = flush()) != MM_OK) return rc;
+        }
+    } while (done < nsteps);
+    if (stats) {
+        if ((rc = flush()) != MM_OK) return rc;
+        for (int k = 0; k < out; ++k)
+            if (stats[k].nonfinite > 0)
+                return fail(MM_ENONFINITE, std::to_string(stats[k].nonfinite) + " non-finite cells after " +
+                                               std::to_string(stats[k].steps) + " steps");
+    }
     return MM_OK;
 }
 
 int mm_reduce(mm_plan plan, const mm_llg_params *params, const float *M, mm_stats *out, void *stream)
 {
     Plan *p = P(plan);
-    if (!p || !M || !out) return fail(MM_EINVAL, "NULL plan, M or out");
-    int rc = check_params(params);
+    int rc = plan_ready(p);
     if (rc != MM_OK) return rc;
+    if (!M || !out) return fail(MM_EINVAL, "NULL M or out");
+    if ((rc = check_params(params)) != MM_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     if ((rc = demag_enqueue(*p, M, p->H, s)) != MM_OK) return rc;
-    if ((rc = reduce_enqueue(*p, *params, M, p->H, s)) != MM_OK) return rc;
-    double r[9];
+    if ((rc = reduce_enqueue(*p, *params, M, p->H, s, 0)) != MM_OK) return rc;
+    double r[16];
     MMK_HIP(hipMemcpyAsync(r, p->red, sizeof(r), hipMemcpyDeviceToHost, s));
     MMK_HIP(hipStreamSynchronize(s));
-    const double mu0 = 4e-7 * M_PI;
-    const double V = p->dx * p->dy * p->dz;
-    const double N = (double)p->cells();
-    out->E_ex = params->A * V * r[0];
-    out->E_an = V * r[1];
-    out->E_d = -0.5 * mu0 * V * r[2];
-    out->E_z = -mu0 * V * r[3];
-    out->E_tot = out->E_ex + out->E_an + out->E_d + out->E_z;
-    out->m_avg[0] = r[4] / N;
-    out->m_avg[1] = r[5] / N;
-    out->m_avg[2] = r[6] / N;
-    out->nonfinite = (long long)r[7];
-    out->torque_max = r[8];
+    stats_from_record(*p, *params, r, out);
+    out->steps = 0;
+    out->fallbacks = 0;
     if (out->nonfinite > 0) return fail(MM_ENONFINITE, std::to_string(out->nonfinite) + " non-finite cells");
     return MM_OK;
 }
@@ -378,20 +478,24 @@ int mm_llg_relax(mm_plan plan, const mm_llg_params *params, float *M, double tor
                  int check_every, mm_stats *out, long long *steps_taken, void *stream)
 {
     Plan *p = P(plan);
-    if (!p || !M || !out || !steps_taken) return fail(MM_EINVAL, "NULL plan, M, out or steps_taken");
-    if (!(torque_tol > 0.0) || max_steps < 0 || check_every < 1) return fail(MM_EINVAL, "bad relax controls");
-    int rc = check_params(params);
+    int rc = plan_ready(p);
     if (rc != MM_OK) return rc;
+    if (!M || !out || !steps_taken) return fail(MM_EINVAL, "NULL M, out or steps_taken");
+    if (!(torque_tol > 0.0) || max_steps < 0 || check_every < 1) return fail(MM_EINVAL, "bad relax controls");
+    if ((rc = check_params(params)) != MM_OK) return rc;
     long long done = 0;
     *steps_taken = 0;
+    // each check takes the observables of the state the chunk ended on
     if ((rc = mm_reduce(plan, params, M, out, stream)) != MM_OK) return rc;
     while (out->torque_max > torque_tol && done < max_steps) {
-        const long long k = std::min<long long>(check_every, max_steps - done);
-        if ((rc = mm_llg_step(plan, params, M, (int)k, stream)) != MM_OK) return rc;
+        const int k = (int)std::min<long long>(check_every, max_steps - done);
+        mm_llg_params q = *params;
+        q.log_every = 0;
+        if ((rc = mm_llg_step(plan, &q, M, k, out, stream)) != MM_OK) return rc;
         done += k;
         *steps_taken = done;
-        if ((rc = mm_reduce(plan, params, M, out, stream)) != MM_OK) return rc;
     }
+    out->steps = done;
     return MM_OK;
 }
 
@@ -412,7 +516,9 @@ int mm_newell_tensor(int nx, int ny, int nz, double dx, double dy, double dz, do
 int mm_plan_spectrum(mm_plan plan, float *Kt, long long count, void *stream)
 {
     Plan *p = P(plan);
-    if (!p || !Kt) return fail(MM_EINVAL, "NULL plan or Kt");
+    int rc = plan_ready(p);
+    if (rc != MM_OK) return rc;
+    if (!Kt) return fail(MM_EINVAL, "NULL Kt");
     if (count < p->nK) return fail(MM_EINVAL, "Kt too small");
     const size_t rec = 6 * sizeof(float);
     MMK_HIP(hipMemcpy2DAsync(Kt, rec * p->nxc, p->Kt, rec * p->xp, rec * p->nxc, (size_t)p->nzK * (p->ny + 1),
@@ -428,7 +534,7 @@ int mm_plan_query(mm_plan plan, mm_plan_info *info)
     info->Lx = p->Lx; info->Ly = p->Ly; info->Lz = p->Lz;
     info->spectrum_count = p->nK;
     info->workspace_bytes = (long long)p->bytes;
-    for (int k = 0; k < 8; ++k) info->cfg[k] = p->tile[k];
+    for (int k = 0; k < MM_PASS_COUNT; ++k) info->cfg[k] = p->tile[k];
     return MM_OK;
 }
 
@@ -466,7 +572,7 @@ int mm_plan_timing(mm_plan plan, double *total_ms, long long *launches)
 int mm_plan_autotune(mm_plan plan, int reps, void *stream)
 {
     Plan *p = P(plan);
-    if (!p) return fail(MM_EINVAL, "NULL plan");
+    if (plan_ready(p) != MM_OK) return MM_EINVAL;
     if (reps < 1) reps = 1;
     hipStream_t s = (hipStream_t)stream;
     // Each candidate is timed as the duration of `reps` complete demag
@@ -509,9 +615,48 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
             p->tile[pass] = best_tile;
         }
     }
+    // the fused pass (when in use): each candidate timed as `reps` RK4
+    // steps by direct launches on a zero state held in H, which the fused
+    // step never touches
+    if (rc == MM_OK && p->tile[MM_PASS_XSTAGE] > 0) {
+        std::vector<int> cand = xstage_candidates(*p);
+        mm_llg_params q{};
+        q.Ms = 1.0;
+        q.alpha = 0.1;
+        q.gamma0 = 2.211e5;
+        q.dt = 1e-14;
+        q.axis[0] = 1.0;
+        q.integrator = MM_RK4;
+        q.renorm = 1;
+        const StageCoef c = stage_coef(*p, q);
+        MMK_HIP(hipMemsetAsync(p->H, 0, sizeof(float) * 3 * (size_t)p->cells(), s));
+        float best = 1e30f;
+        int best_tile = p->tile[MM_PASS_XSTAGE];
+        for (int t : cand) {
+            if (cand.size() < 2) break;
+            p->tile[MM_PASS_XSTAGE] = t;
+            if ((rc = llg_enqueue_step(*p, c, MM_RK4, p->H, s)) != MM_OK) break;  // warm-up
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MM_EHIP, "event"); break; }
+            for (int r = 0; r < reps && rc == MM_OK; ++r) rc = llg_enqueue_step(*p, c, MM_RK4, p->H, s);
+            if (rc != MM_OK) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(MM_EHIP, "event");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                best_tile = t;
+            }
+            ++tuned;
+        }
+        p->tile[MM_PASS_XSTAGE] = best_tile;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->timing = was;
+    drop_plan_graph(*p);
     if (rc != MM_OK) return rc;
     if (tuned == 0) return fail(MM_ETUNE, "no candidate ran");
     return MM_OK;

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(1024) void kb_xfwd(const BInst *__restrict__ B, con
 {
     const int4 t = T[blockIdx.x];
     const BInst &I = B[t.x];
-    xfwd_body<L, V>(bsel(I, sel), I.X1, 3 * I.nz * I.ny, lp2, I.tw0, t.y);
+    xfwd_body<L, V>(bsel(I, sel), I.X1, I.nz * I.ny, lp2, I.tw0, t.y);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void kb_yfwd(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(1024) void kb_xinv(const BInst *__restrict__ B, con
 {
     const int4 t = T[blockIdx.x];
     const BInst &I = B[t.x];
-    xinv_body<L, V>(I.X1, I.Hout, 3 * I.nz * I.ny, lp2, I.tw0, t.y);
+    xinv_body<L, V>(I.X1, I.Hout, I.nz * I.ny, lp2, I.tw0, t.y);
 }
 template <int STAGE>
 __global__ __launch_bounds__(256) void kb_stage(const BInst *__restrict__ B, const int2 *__restrict__ T, int ssel,
@@ -105,7 +105,7 @@ struct BGroup {
     size_t lds = 0;
     std::vector<int4> tasks;
     int4 *d = nullptr;
-    size_t cap = 0;
+    size_t cap = 0;  // device table capacity: the most tasks any candidate tile makes
 };
 
 struct BatchImpl {
@@ -123,6 +123,9 @@ struct BatchImpl {
     std::string key;
     std::vector<float *> bound_M;
     std::string bound_params;
+    size_t bytes = 0;                // workspace bytes
+    std::vector<size_t> plan_bytes;  // per-instance plan workspace
+    char *ws = nullptr;              // bound workspace (nullptr: unbound)
 };
 
 static int pass_len_of(const BInst &I, int pass)
@@ -140,43 +143,45 @@ static int pass_len_of(const BInst &I, int pass)
 
 static int launch_group(const BGroup &g, const BInst *table, int sel, hipStream_t s, bool raise_only);
 
-static int build_tasks(BatchImpl &b, BGroup &g)
+static void make_tasks(const BatchImpl &b, const BGroup &g, int tile, std::vector<int4> &tasks)
 {
-    const int P = g.tile & 255;
-    g.tasks.clear();
+    const int P = tile & 255;
+    tasks.clear();
     for (int i = 0; i < b.count; ++i) {
         const BInst &I = b.inst[i];
         if (pass_len_of(I, g.pass) != g.L) continue;
-        const int nxc = I.nx + 1, nrows = 3 * I.nz * I.ny;
+        const int nxc = I.nx + 1, ncr = I.nz * I.ny;
         switch (g.pass) {
         case MM_PASS_XFWD:
         case MM_PASS_XINV: {
-            const int pairs = (nrows + 1) / 2;
-            for (int bx = 0; bx < (pairs + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));
+            const int pairs = 3 * ((ncr + 1) / 2);
+            for (int bx = 0; bx < (pairs + P - 1) / P; ++bx) tasks.push_back(make_int4(i, bx, 0, 0));
             break;
         }
         case MM_PASS_YFWD:
         case MM_PASS_YINV:
             for (int pl = 0; pl < 3 * I.nz; ++pl)
-                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, pl, 0));
+                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) tasks.push_back(make_int4(i, bx, pl, 0));
             break;
         case MM_PASS_ZCONV:  // the two rows of a mirror pair next to each other, then the tile
             for (int m = 0; m < I.ny; ++m)
                 for (int bx = 0; bx < (nxc + P - 1) / P; ++bx)
-                    for (int h = 0; h < 2; ++h) g.tasks.push_back(make_int4(i, bx, ky_of_slot(2 * m + h, I.ny), 0));
+                    for (int h = 0; h < 2; ++h) tasks.push_back(make_int4(i, bx, ky_of_slot(2 * m + h, I.ny), 0));
             break;
         case MM_PASS_YCONV:
-            for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, 0));
+            for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) tasks.push_back(make_int4(i, bx, 0, 0));
             break;
         default: break;
         }
     }
-    if (g.tasks.size() > g.cap) {
-        if (g.d) (void)hipFree(g.d);
-        g.d = nullptr;
-        MMK_HIP(hipMalloc(&g.d, sizeof(int4) * g.tasks.size()));
-        g.cap = g.tasks.size();
-    }
+}
+
+// Task table of a group for its current tile, uploaded into the group's
+// slice of the workspace (sized at set-up for the largest candidate table).
+static int build_tasks(BatchImpl &b, BGroup &g)
+{
+    make_tasks(b, g, g.tile, g.tasks);
+    if (g.tasks.size() > g.cap) return fail(MM_EINVAL, "batch: task table over its capacity");
     MMK_HIP(hipMemcpy(g.d, g.tasks.data(), sizeof(int4) * g.tasks.size(), hipMemcpyHostToDevice));
     int maxt;
     shape_for(g.pass, g.L, g.tile, g.threads, g.lds, maxt);
@@ -314,12 +319,6 @@ static void free_batch(BatchImpl *b)
 {
     if (!b) return;
     drop_graph(*b);
-    for (BGroup &g : b->groups)
-        if (g.d) (void)hipFree(g.d);
-    if (b->d_inst) (void)hipFree(b->d_inst);
-    if (b->d_io) (void)hipFree(b->d_io);
-    if (b->d_stage) (void)hipFree(b->d_stage);
-    if (b->d_copy) (void)hipFree(b->d_copy);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (mm_plan p : b->plans) mm_destroy(p);
     delete b;
@@ -356,18 +355,17 @@ int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const
     b->lds_limit = plan_of(b->plans[0])->lds_limit;
     for (int i = 0; i < count; ++i) {
         const Plan &p = *plan_of(b->plans[i]);
+        if (p.lds_limit < b->lds_limit) b->lds_limit = p.lds_limit;
         BInst I{};
-        I.M = nullptr;
-        I.Sa = p.Sa; I.Sb = p.Sb; I.H = p.H; I.kacc = p.kacc; I.Hout = p.H;
-        I.X1 = p.X1; I.X2 = p.X2; I.Kt = p.Kt;
-        I.tw0 = p.tw[0]; I.tw1 = p.tw[1]; I.tw2 = p.tw[2];
         I.nx = p.nx; I.ny = p.ny; I.nz = p.nz;
         b->inst.push_back(I);
         const size_t n = (size_t)p.cells();
         for (size_t blk = 0; blk < (n + 255) / 256; ++blk) b->stage_tasks.push_back(make_int2(i, (int)blk));
         for (size_t blk = 0; blk < (3 * n + 767) / 768; ++blk) b->copy_tasks.push_back(make_int2(i, (int)blk));
     }
-    // one group per (pass, length) present in the batch
+    // one group per (pass, length) present in the batch; its device table
+    // holds the largest task list any candidate tile makes
+    std::vector<int4> scratch;
     for (int pass : DEMAG_ORDER) {
         std::vector<int> lens;
         for (const BInst &I : b->inst) {
@@ -380,27 +378,89 @@ int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const
             g.pass = pass;
             g.L = L;
             g.tile = default_tile_for(pass, L, b->lds_limit);
+            for (int t : tile_candidates_for(pass, L, b->lds_limit)) {
+                make_tasks(*b, g, t, scratch);
+                g.cap = std::max(g.cap, scratch.size());
+            }
+            make_tasks(*b, g, g.tile, scratch);
+            g.cap = std::max(g.cap, scratch.size());
             b->groups.push_back(g);
         }
     }
-    for (BGroup &g : b->groups)
-        if ((rc = build_tasks(*b, g)) != MM_OK) break;
-    auto up = [](void **dst, const void *src, size_t bytes) -> int {
-        if (hipMalloc(dst, bytes) != hipSuccess) return fail(MM_ENOMEM, "batch tables");
-        if (hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return fail(MM_EHIP, "batch upload");
-        return MM_OK;
-    };
-    if (rc == MM_OK) rc = up((void **)&b->d_inst, b->inst.data(), sizeof(BInst) * count);
-    if (rc == MM_OK) rc = up((void **)&b->d_io, b->inst.data(), sizeof(BInst) * count);
-    if (rc == MM_OK) rc = up((void **)&b->d_stage, b->stage_tasks.data(), sizeof(int2) * b->stage_tasks.size());
-    if (rc == MM_OK) rc = up((void **)&b->d_copy, b->copy_tasks.data(), sizeof(int2) * b->copy_tasks.size());
-    if (rc == MM_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
-        rc = fail(MM_EHIP, "batch stream");
-    if (rc != MM_OK) {
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        size_t pb = 0;
+        mm_plan_workspace_bytes(b->plans[i], &pb);
+        b->plan_bytes.push_back(al(pb));
+        total += al(pb);
+    }
+    for (const BGroup &g : b->groups) total += al(sizeof(int4) * g.cap);
+    total += 2 * al(sizeof(BInst) * count) + al(sizeof(int2) * b->stage_tasks.size()) +
+             al(sizeof(int2) * b->copy_tasks.size());
+    b->bytes = total;
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
         free_batch(b);
-        return rc;
+        return fail(MM_EHIP, "batch stream");
     }
     *out = new mm_batch_s{b};
+    return MM_OK;
+}
+
+int mm_batch_workspace_bytes(mm_batch batch, size_t *bytes)
+{
+    if (!batch || !batch->impl || !bytes) return fail(MM_EINVAL, "NULL batch or bytes");
+    *bytes = batch->impl->bytes;
+    return MM_OK;
+}
+
+int mm_batch_bind_workspace(mm_batch batch, void *ws, size_t bytes)
+{
+    if (!batch || !batch->impl || !ws) return fail(MM_EINVAL, "NULL batch or workspace");
+    BatchImpl &b = *batch->impl;
+    if ((uintptr_t)ws % 256 != 0) return fail(MM_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < b.bytes)
+        return fail(MM_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes; the batch needs " +
+                                   std::to_string(b.bytes));
+    drop_graph(b);
+    b.ws = nullptr;
+    b.bound_M.clear();
+    b.bound_params.clear();
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char *cur = (char *)ws;
+    int rc;
+    for (int i = 0; i < b.count; ++i) {
+        if ((rc = mm_plan_bind_workspace(b.plans[i], cur, b.plan_bytes[i])) != MM_OK) return rc;
+        cur += b.plan_bytes[i];
+        const Plan &p = *plan_of(b.plans[i]);
+        BInst &I = b.inst[i];
+        I.M = nullptr;
+        I.Sa = p.Sa; I.Sb = p.Sb; I.H = p.H; I.kacc = p.kacc; I.Hout = p.H;
+        I.X1 = p.X1; I.X2 = p.X2; I.Kt = p.Kt;
+        I.tw0 = p.tw[0]; I.tw1 = p.tw[1]; I.tw2 = p.tw[2];
+    }
+    for (BGroup &g : b.groups) {
+        g.d = (int4 *)cur;
+        cur += al(sizeof(int4) * g.cap);
+        if ((rc = build_tasks(b, g)) != MM_OK) return rc;
+    }
+    b.d_inst = (BInst *)cur; cur += al(sizeof(BInst) * b.count);
+    b.d_io = (BInst *)cur; cur += al(sizeof(BInst) * b.count);
+    b.d_stage = (int2 *)cur; cur += al(sizeof(int2) * b.stage_tasks.size());
+    b.d_copy = (int2 *)cur;
+    MMK_HIP(hipMemcpy(b.d_inst, b.inst.data(), sizeof(BInst) * b.count, hipMemcpyHostToDevice));
+    MMK_HIP(hipMemcpy(b.d_io, b.inst.data(), sizeof(BInst) * b.count, hipMemcpyHostToDevice));
+    MMK_HIP(hipMemcpy(b.d_stage, b.stage_tasks.data(), sizeof(int2) * b.stage_tasks.size(), hipMemcpyHostToDevice));
+    MMK_HIP(hipMemcpy(b.d_copy, b.copy_tasks.data(), sizeof(int2) * b.copy_tasks.size(), hipMemcpyHostToDevice));
+    MMK_HIP(hipDeviceSynchronize());
+    b.ws = (char *)ws;
+    return MM_OK;
+}
+
+static int batch_ready(mm_batch batch)
+{
+    if (!batch || !batch->impl) return fail(MM_EINVAL, "NULL batch");
+    if (!batch->impl->ws) return fail(MM_EINVAL, "batch has no workspace: call mm_batch_bind_workspace first");
     return MM_OK;
 }
 
@@ -413,7 +473,9 @@ void mm_batch_destroy(mm_batch batch)
 
 int mm_batch_demag(mm_batch batch, const float *const *M, float *const *H, void *stream)
 {
-    if (!batch || !batch->impl || !M || !H) return fail(MM_EINVAL, "NULL batch or pointer table");
+    int rc0 = batch_ready(batch);
+    if (rc0 != MM_OK) return rc0;
+    if (!M || !H) return fail(MM_EINVAL, "NULL pointer table");
     BatchImpl &b = *batch->impl;
     std::vector<BInst> io = b.inst;
     for (int i = 0; i < b.count; ++i) {
@@ -430,7 +492,9 @@ int mm_batch_demag(mm_batch batch, const float *const *M, float *const *H, void 
 
 int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M, int nsteps, void *stream)
 {
-    if (!batch || !batch->impl || !params || !M) return fail(MM_EINVAL, "NULL batch, params or M table");
+    int rc0 = batch_ready(batch);
+    if (rc0 != MM_OK) return rc0;
+    if (!params || !M) return fail(MM_EINVAL, "NULL params or M table");
     if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
     BatchImpl &b = *batch->impl;
     const int integrator = params[0].integrator;
@@ -438,6 +502,7 @@ int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M, 
         if (!M[i]) return fail(MM_EINVAL, "NULL M of instance " + std::to_string(i));
         if (params[i].integrator != integrator) return fail(MM_EINVAL, "batch: one integrator for all instances");
         if (!(params[i].Ms > 0.0) || !std::isfinite(params[i].dt)) return fail(MM_EINVAL, "batch: bad params");
+        if (params[i].demag_mode != MM_EXACT) return fail(MM_EINVAL, "batch: exact demag only");
     }
     if (nsteps == 0) return MM_OK;
     hipStream_t s = (hipStream_t)stream;
@@ -484,7 +549,8 @@ int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M, 
 
 int mm_batch_autotune(mm_batch batch, int reps, void *stream)
 {
-    if (!batch || !batch->impl) return fail(MM_EINVAL, "NULL batch");
+    int rc0 = batch_ready(batch);
+    if (rc0 != MM_OK) return rc0;
     BatchImpl &b = *batch->impl;
     if (reps < 1) reps = 1;
     hipStream_t s = (hipStream_t)stream;

@@ -29,10 +29,10 @@ __device__ __forceinline__ void conv_coords(int ny, int &bx, int &ky)
 
 // Per-plan kernels: one launch covers one pass of one grid.
 template <int L, int V>
-__global__ __launch_bounds__(1024) void k_xfwd(const float *__restrict__ M, float2 *__restrict__ X1, int nrows,
+__global__ __launch_bounds__(1024) void k_xfwd(const float *__restrict__ M, float2 *__restrict__ X1, int ncr,
                                                int lp2, const float2 *__restrict__ tw)
 {
-    xfwd_body<L, V>(M, X1, nrows, lp2, tw, blockIdx.x);
+    xfwd_body<L, V>(M, X1, ncr, lp2, tw, blockIdx.x);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yfwd(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc,
@@ -70,10 +70,10 @@ __global__ __launch_bounds__(1024) void k_yinv(const float2 *__restrict__ X2, fl
     yinv_body<L, V>(X2, X1, nxc, lp2, tw, bx, plane);
 }
 template <int L, int V>
-__global__ __launch_bounds__(1024) void k_xinv(const float2 *__restrict__ X1, float *__restrict__ H, int nrows,
+__global__ __launch_bounds__(1024) void k_xinv(const float2 *__restrict__ X1, float *__restrict__ H, int ncr,
                                                int lp2, const float2 *__restrict__ tw)
 {
-    xinv_body<L, V>(X1, H, nrows, lp2, tw, blockIdx.x);
+    xinv_body<L, V>(X1, H, ncr, lp2, tw, blockIdx.x);
 }
 
 // --------------------------------------------------------------- dispatch ---
@@ -236,11 +236,13 @@ int default_tile_for(int pass, int L, size_t lds_limit)
 bool pass_tile_valid(const Plan &p, int pass, int tile)
 {
     if (pass == MM_PASS_STAGE) return (tile == 1 || tile == 2 || tile == 4) && p.nx % tile == 0;
+    if (pass == MM_PASS_XSTAGE) return xstage_tile_valid(p, tile);
     return pass_active(p, pass) && tile_valid_for(pass, pass_length(p, pass), tile, p.lds_limit);
 }
 
 std::vector<int> pass_tile_candidates(const Plan &p, int pass)
 {
+    if (pass == MM_PASS_XSTAGE) return xstage_candidates(p);
     if (!pass_active(p, pass)) return {};
     return tile_candidates_for(pass, pass_length(p, pass), p.lds_limit);
 }
@@ -248,6 +250,7 @@ std::vector<int> pass_tile_candidates(const Plan &p, int pass)
 int pass_default_tile(const Plan &p, int pass)
 {
     if (pass == MM_PASS_STAGE) return p.nx % 4 == 0 ? 4 : (p.nx % 2 == 0 ? 2 : 1);
+    if (pass == MM_PASS_XSTAGE) return xstage_default_tile(p);
     if (!pass_active(p, pass)) return 0;
     return default_tile_for(pass, pass_length(p, pass), p.lds_limit);
 }
@@ -303,11 +306,11 @@ static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, 
     const int lp2 = ilog2(P);
     const dim3 block(P * Q);
     const int nxc = p.nxc;
-    const int nrows = 3 * p.nz * p.ny;
+    const int ncr = p.nz * p.ny;
+    const int pairs = 3 * ((ncr + 1) / 2);
     switch (pass) {
     case MM_PASS_XFWD: {
-        const int pairs = (nrows + 1) / 2;
-        MMK_LAUNCH(p, (k_xfwd<L, V>), dim3((pairs + P - 1) / P), block, lds, s, M, p.X1, nrows, lp2, p.tw[0]);
+        MMK_LAUNCH(p, (k_xfwd<L, V>), dim3((pairs + P - 1) / P), block, lds, s, M, p.X1, ncr, lp2, p.tw[0]);
         break;
     }
     case MM_PASS_YFWD:
@@ -319,8 +322,7 @@ static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, 
                            p.tw[1]);
         break;
     case MM_PASS_XINV: {
-        const int pairs = (nrows + 1) / 2;
-        MMK_LAUNCH(p, (k_xinv<L, V>), dim3((pairs + P - 1) / P), block, lds, s, p.X1, H, nrows, lp2, p.tw[0]);
+        MMK_LAUNCH(p, (k_xinv<L, V>), dim3((pairs + P - 1) / P), block, lds, s, p.X1, H, ncr, lp2, p.tw[0]);
         break;
     }
     default: break;
@@ -381,17 +383,22 @@ int launch_pass(Plan &p, int pass, const float *M, float *H, hipStream_t s)
     return MM_OK;
 }
 
+int demag_mid_enqueue(Plan &p, hipStream_t s)
+{
+    int rc;
+    if (p.nz > 1) {
+        if ((rc = launch_pass(p, MM_PASS_YFWD, nullptr, nullptr, s)) != MM_OK) return rc;
+        if ((rc = launch_pass(p, MM_PASS_ZCONV, nullptr, nullptr, s)) != MM_OK) return rc;
+        return launch_pass(p, MM_PASS_YINV, nullptr, nullptr, s);
+    }
+    return launch_pass(p, MM_PASS_YCONV, nullptr, nullptr, s);
+}
+
 int demag_enqueue(Plan &p, const float *M, float *H, hipStream_t s)
 {
     int rc;
     if ((rc = launch_pass(p, MM_PASS_XFWD, M, H, s)) != MM_OK) return rc;
-    if (p.nz > 1) {
-        if ((rc = launch_pass(p, MM_PASS_YFWD, M, H, s)) != MM_OK) return rc;
-        if ((rc = launch_pass(p, MM_PASS_ZCONV, M, H, s)) != MM_OK) return rc;
-        if ((rc = launch_pass(p, MM_PASS_YINV, M, H, s)) != MM_OK) return rc;
-    } else {
-        if ((rc = launch_pass(p, MM_PASS_YCONV, M, H, s)) != MM_OK) return rc;
-    }
+    if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
     return launch_pass(p, MM_PASS_XINV, M, H, s);
 }
 

@@ -57,12 +57,26 @@ __device__ __forceinline__ const float2 *stage_twiddles(float2 *lds, const float
 
 // ----------------------------------------------------------------- kernels ---
 
+// Rows of the x passes are paired within a component: pair m of the
+// 3 ceil(ncr/2) pairs covers rows 2mm and 2mm+1 of component m / ceil(ncr/2)
+// (ncr = nz ny rows per component), the second absent for the last pair of
+// an odd ncr.  The fused x-inverse/stage/x-forward pass pairs its rows the
+// same way, so both paths round identically.
+__device__ __forceinline__ void x_pair_rows(int m, int ncr, int &ra, bool &oka, bool &okb)
+{
+    const int hp = (ncr + 1) >> 1;
+    const int comp = m / hp, mm = m - comp * hp;
+    ra = comp * ncr + 2 * mm;
+    oka = comp < 3;
+    okb = oka && 2 * mm + 1 < ncr;
+}
+
 // x forward, two real rows per complex transform: z = a + i b (rows 2m and
 // 2m+1, length nx, zero-padded to L = 2nx), Z = FFT(z), then
 //   A_k = (Z_k + conj Z_{L-k}) / 2,   B_k = (Z_k - conj Z_{L-k}) / (2i),
 // k = 0..nx; Z_{L-k} is read back through LDS.
 template <int L, int V>
-__device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int nrows, int lp2,
+__device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int ncr, int lp2,
                                           const float2 *__restrict__ tw, int bx)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
@@ -70,8 +84,10 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int t = threadIdx.x;
     const int q = t % Q, p = t / Q;
-    const int ra = ((bx << lp2) + p) * 2, rb = ra + 1;
-    const bool oka = ra < nrows, okb = rb < nrows;
+    int ra;
+    bool oka, okb;
+    x_pair_rows((bx << lp2) + p, ncr, ra, oka, okb);
+    const int rb = ra + 1;
     constexpr int XS = lds_rows(L) + 1;  // slots per transform (odd)
     float2 *col = lds + tw_slots<L>() + p * XS;
     const LdsView s{lds + tw_slots<L>(), 1, p * XS};
@@ -423,7 +439,7 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
 // the Hermitian half-spectra of rows 2m and 2m+1; Re/Im of the inverse are
 // the two real rows.  Keep i < nx.
 template <int L, int V>
-__device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *__restrict__ H, int nrows, int lp2,
+__device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *__restrict__ H, int ncr, int lp2,
                                           const float2 *__restrict__ tw, int bx)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
@@ -431,8 +447,10 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int t = threadIdx.x;
     const int q = t % Q, p = t / Q;
-    const int ra = ((bx << lp2) + p) * 2, rb = ra + 1;
-    const bool oka = ra < nrows, okb = rb < nrows;
+    int ra;
+    bool oka, okb;
+    x_pair_rows((bx << lp2) + p, ncr, ra, oka, okb);
+    const int rb = ra + 1;
     const LdsView s{lds + tw_slots<L>(), 1, p * (lds_rows(L) + 1)};
     const float2 *sa = X1 + (size_t)ra * XP;
     const float2 *sb = X1 + (size_t)rb * XP;

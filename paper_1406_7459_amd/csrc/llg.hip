@@ -83,16 +83,39 @@ static int launch_stage(Plan &p, const float *S, const float *Mn, float *out, co
 
 // One step; on return M holds the new state.  RK4: S_1 = M, S_2 = Sa,
 // S_3 = Sb, S_4 = Sa; stage 4 writes M in place (each cell reads only its own
-// M there, neighbours come from Sa).  Euler: M -> Sa, then Sa is copied back.
+// M there, neighbours come from Sa).  Euler: M -> Sa, then Sa is copied back
+// (a pair of Euler steps, llg_enqueue_euler_pair, needs no copy).
+// With the fused pass (tile of MM_PASS_XSTAGE > 0) a stage's field never
+// leaves the chip: XFWD(M), then per stage the middle demag passes and one
+// fused x-inverse / stage / x-forward launch (the last stage without the
+// forward part).
 int llg_enqueue_step(Plan &p, const StageCoef &c, int integrator, float *M, hipStream_t s)
 {
     int rc;
     const size_t bytes = sizeof(float) * 3 * (size_t)p.cells();
+    const bool fused = p.tile[MM_PASS_XSTAGE] > 0;
     if (integrator == MM_EULER) {
-        if ((rc = demag_enqueue(p, M, p.H, s)) != MM_OK) return rc;
-        if ((rc = launch_stage<0>(p, M, M, p.Sa, c, s)) != MM_OK) return rc;
+        if (fused) {
+            if ((rc = launch_pass(p, MM_PASS_XFWD, M, nullptr, s)) != MM_OK) return rc;
+            if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
+            if ((rc = launch_xstage(p, 0, false, M, M, p.Sa, c, s)) != MM_OK) return rc;
+        } else {
+            if ((rc = demag_enqueue(p, M, p.H, s)) != MM_OK) return rc;
+            if ((rc = launch_stage<0>(p, M, M, p.Sa, c, s)) != MM_OK) return rc;
+        }
         MMK_HIP(hipMemcpyAsync(M, p.Sa, bytes, hipMemcpyDeviceToDevice, s));
         return MM_OK;
+    }
+    if (fused) {
+        if ((rc = launch_pass(p, MM_PASS_XFWD, M, nullptr, s)) != MM_OK) return rc;
+        if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
+        if ((rc = launch_xstage(p, 1, true, M, M, p.Sa, c, s)) != MM_OK) return rc;
+        if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
+        if ((rc = launch_xstage(p, 2, true, p.Sa, M, p.Sb, c, s)) != MM_OK) return rc;
+        if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
+        if ((rc = launch_xstage(p, 3, true, p.Sb, M, p.Sa, c, s)) != MM_OK) return rc;
+        if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
+        return launch_xstage(p, 4, false, p.Sa, M, M, c, s);
     }
     if ((rc = demag_enqueue(p, M, p.H, s)) != MM_OK) return rc;
     if ((rc = launch_stage<1>(p, M, M, p.Sa, c, s)) != MM_OK) return rc;
@@ -102,6 +125,24 @@ int llg_enqueue_step(Plan &p, const StageCoef &c, int integrator, float *M, hipS
     if ((rc = launch_stage<3>(p, p.Sb, M, p.Sa, c, s)) != MM_OK) return rc;
     if ((rc = demag_enqueue(p, p.Sa, p.H, s)) != MM_OK) return rc;
     return launch_stage<4>(p, p.Sa, M, M, c, s);
+}
+
+// Two explicit Euler steps, M -> Sa -> M: the state alternates between the
+// two buffers and nothing is copied.
+int llg_enqueue_euler_pair(Plan &p, const StageCoef &c, float *M, hipStream_t s)
+{
+    int rc;
+    if (p.tile[MM_PASS_XSTAGE] > 0) {
+        if ((rc = launch_pass(p, MM_PASS_XFWD, M, nullptr, s)) != MM_OK) return rc;
+        if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
+        if ((rc = launch_xstage(p, 0, true, M, M, p.Sa, c, s)) != MM_OK) return rc;
+        if ((rc = demag_mid_enqueue(p, s)) != MM_OK) return rc;
+        return launch_xstage(p, 0, false, p.Sa, p.Sa, M, c, s);
+    }
+    if ((rc = demag_enqueue(p, M, p.H, s)) != MM_OK) return rc;
+    if ((rc = launch_stage<0>(p, M, M, p.Sa, c, s)) != MM_OK) return rc;
+    if ((rc = demag_enqueue(p, p.Sa, p.H, s)) != MM_OK) return rc;
+    return launch_stage<0>(p, p.Sa, p.Sa, M, c, s);
 }
 
 // RK4 step whose stage-1 field is given (H1, the field of M) and whose
@@ -239,7 +280,7 @@ __global__ __launch_bounds__(64 * RED_VALS) void k_reduce_final(const double *__
     if (lane == 0) out[v] = r;
 }
 
-int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float *Hd, hipStream_t s)
+int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float *Hd, hipStream_t s, int slot)
 {
     const double mu0 = 4e-7 * M_PI;
     const double ex = 2.0 * q.A / (mu0 * q.Ms * q.Ms);
@@ -263,11 +304,31 @@ int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float 
     hipEvent_t ev0 = nullptr;
     timing_begin(p, MM_PASS_REDUCE, s, &ev0);
     hipLaunchKernelGGL(k_reduce_cells, dim3(p.red_blocks), dim3(256), 0, s, M, Hd, p.part, p.nx, p.ny, p.nz, c);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64 * RED_VALS), 0, s, p.part, p.red_blocks, p.red);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64 * RED_VALS), 0, s, p.part, p.red_blocks,
+                       p.red + 16 * (size_t)slot);
     timing_end(p, MM_PASS_REDUCE, s, ev0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MM_EHIP, std::string("reduce: ") + hipGetErrorString(e));
     return MM_OK;
+}
+
+// Observables (eq. (1) energies with V = dx dy dz per cell, max torque, <m>,
+// non-finite count) from one reduction record of RED_VALS sums.
+void stats_from_record(const Plan &p, const mm_llg_params &q, const double *r, mm_stats *out)
+{
+    const double mu0 = 4e-7 * M_PI;
+    const double V = p.dx * p.dy * p.dz;
+    const double N = (double)p.cells();
+    out->E_ex = q.A * V * r[0];
+    out->E_an = V * r[1];
+    out->E_d = -0.5 * mu0 * V * r[2];
+    out->E_z = -mu0 * V * r[3];
+    out->E_tot = out->E_ex + out->E_an + out->E_d + out->E_z;
+    out->m_avg[0] = r[4] / N;
+    out->m_avg[1] = r[5] / N;
+    out->m_avg[2] = r[6] / N;
+    out->nonfinite = (long long)r[7];
+    out->torque_max = r[8];
 }
 
 }  // namespace mmk

@@ -16,6 +16,10 @@
 
 namespace mmk {
 
+// Observables records kept on the device per mm_llg_step call before the host
+// reads them back.
+constexpr int RED_LOG = 256;
+
 // thread-local last-error detail
 void set_error(const std::string &msg);
 int fail(int code, const std::string &msg);
@@ -76,12 +80,18 @@ struct Plan {
     float *H = nullptr;          // [3][N] demag field scratch for the step driver
     float *Sa = nullptr, *Sb = nullptr, *kacc = nullptr;  // stage states and RK4 accumulator
     double *part = nullptr;      // reduction partials
-    double *red = nullptr;       // final reduction [16]
+    double *red = nullptr;       // final reductions, RED_LOG records of 16 doubles
     int red_blocks = 0;
     float2 *tw[3] = {nullptr, nullptr, nullptr};  // twiddles per axis length
-    size_t bytes = 0;
+    size_t bytes = 0;            // workspace bytes the plan needs
+    char *ws = nullptr;          // the caller's bound workspace (nullptr: unbound)
+    char *run = nullptr;         // run-time region of the workspace (set-up scratch before)
+    std::vector<float2> tw_host[3];  // twiddle tables, uploaded at bind
 
-    int tile[MM_PASS_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // learned demag increment attached for MM_SURROGATE stepping (mm_sur_attach)
+    void *sur = nullptr;
+
+    int tile[MM_PASS_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     bool timing = false;
     hipEvent_t tev[2] = {nullptr, nullptr};  // armed start/stop pair for the next launch
@@ -96,6 +106,12 @@ struct Plan {
 };
 
 Plan *plan_of(mm_plan h);
+// MM_OK if the plan has its workspace bound, else MM_EINVAL with a detail.
+int plan_ready(const Plan *p);
+// Carve (base != nullptr) or measure (base == nullptr) the plan workspace.
+size_t plan_layout(Plan &p, char *base);
+// FP64 scratch bytes of the spectrum set-up (tensor.hip).
+size_t spectrum_scratch_bytes(int nx, int ny, int nz);
 
 // Launch configurations by (pass, transform length) (demag.hip).
 bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt);
@@ -135,11 +151,24 @@ int newell_octant_device(int nx, int ny, int nz, double dx, double dy, double dz
                          hipStream_t s);
 int build_spectrum(Plan &p, hipStream_t s);
 
+// Fused x-inverse / stage / x-forward pass (xstage.hip).
+bool xstage_tile_valid(const Plan &p, int tile);
+std::vector<int> xstage_candidates(const Plan &p);
+int xstage_default_tile(const Plan &p);
+int launch_xstage(Plan &p, int stage, bool fwd, const float *S, const float *Mn, float *out, const StageCoef &c,
+                  hipStream_t s);
+// The passes of a demag evaluation between XFWD and XINV (YFWD, ZCONV, YINV;
+// or YCONV when nz = 1) (demag.hip).
+int demag_mid_enqueue(Plan &p, hipStream_t s);
+
 // LLG (llg.hip).
 StageCoef stage_coef(const Plan &p, const mm_llg_params &q);
 int llg_enqueue_step(Plan &p, const StageCoef &c, int integrator, float *M, hipStream_t s);
+// Two explicit Euler steps M -> Sa -> M (no copy back).
+int llg_enqueue_euler_pair(Plan &p, const StageCoef &c, float *M, hipStream_t s);
 int llg_step_with_fields(Plan &p, const StageCoef &c, float *M, const float *H1, hipStream_t s,
                          const std::function<int(int, const float *, float *)> &field);
-int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float *Hd, hipStream_t s);
+int reduce_enqueue(Plan &p, const mm_llg_params &q, const float *M, const float *Hd, hipStream_t s, int slot = 0);
+void stats_from_record(const Plan &p, const mm_llg_params &q, const double *r, mm_stats *out);
 
 }  // namespace mmk

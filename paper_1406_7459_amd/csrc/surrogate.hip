@@ -21,6 +21,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "mm_internal.hpp"
@@ -707,23 +708,52 @@ struct Sur {
     float *tmp = nullptr, *tmp2 = nullptr;  // [3][N] scratch
     float *H0 = nullptr, *Mprev = nullptr, *Hs = nullptr;  // step driver: anchor field, saved state, prediction
     int adam_t = 0;
-    std::vector<void *> owned;
+    size_t bytes = 0;                     // workspace the buffers above live in
+    char *ws = nullptr;                   // bound workspace (nullptr: unbound)
 };
 
 static const int RED_B = 512;
 static long long layer_stride() { return (long long)WSZ + SC; }  // weights then biases
 
-static int sur_alloc(Sur &s, void **p, size_t bytes)
+// Carve (base != nullptr) or measure the surrogate's buffers in one
+// workspace, every buffer 256-byte aligned; returns the bytes needed.
+static size_t sur_layout(Sur &s, char *base)
 {
-    if (hipMalloc(p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(MM_ENOMEM, "surrogate buffers");
+    size_t off = 0;
+    auto take = [&](auto **ptr, size_t bytes) {
+        if (base) *ptr = reinterpret_cast<std::remove_reference_t<decltype(**ptr)> *>(base + off);
+        off += (bytes + 255) & ~(size_t)255;
+    };
+    const size_t P = (size_t)NLAYER * layer_stride();
+    take(&s.w, P * 4);
+    take(&s.m, P * 4);
+    take(&s.v, P * 4);
+    take(&s.g, P * 4);
+    take(&s.wb, (size_t)NLAYER * WSZ * 2);
+    take(&s.wt, (size_t)NLAYER * WSZ * 2);
+    for (int l = 0; l < NLAYER; ++l) {
+        take(&s.X[l], (size_t)s.N * SC * 2);
+        if (l < NLAYER - 1) take(&s.Zh[l], (size_t)s.N * SC * 2);
+        take(&s.Xt[l], (size_t)s.pg.G * SC * 2);
     }
-    s.owned.push_back(*p);
-    return MM_OK;
+    take(&s.Zout, (size_t)s.N * 4 * 4);
+    take(&s.dZt, (size_t)s.pg.G * SC * 2);
+    take(&s.dZb[0], (size_t)s.N * SC * 2);
+    take(&s.dZb[1], (size_t)s.N * SC * 2);
+    take(&s.dZbL, (size_t)s.N * SC * 2);
+    take(&s.dZtL, (size_t)s.pg.G * SC * 2);
+    take(&s.part, (size_t)DW_BLOCKS * layer_stride() * 4);
+    take(&s.dpart, (size_t)2 * RED_B * 8);
+    take(&s.sig, 16);
+    take(&s.tmp, (size_t)3 * s.N * 4);
+    take(&s.tmp2, (size_t)3 * s.N * 4);
+    take(&s.H0, (size_t)3 * s.N * 4);
+    take(&s.Mprev, (size_t)3 * s.N * 4);
+    take(&s.Hs, (size_t)3 * s.N * 4);
+    return off;
 }
 
-static long long oracle_param_count()
+static long long flat_param_count()
 {
     long long n = 0;
     for (int l = 0; l < NLAYER; ++l) n += (long long)CH[l + 1] * CH[l] * NT + CH[l + 1];
@@ -855,11 +885,13 @@ static void from_masters(const float *src, float *dst)
     }
 }
 
-static void free_sur(Sur *s)
+static void free_sur(Sur *s) { delete s; }
+
+static int sur_ready(const Sur *s)
 {
-    if (!s) return;
-    for (void *p : s->owned) (void)hipFree(p);
-    delete s;
+    if (!s) return fail(MM_EINVAL, "NULL surrogate");
+    if (!s->ws) return fail(MM_EINVAL, "surrogate has no workspace: call mm_sur_bind_workspace first");
+    return MM_OK;
 }
 
 // residual of the surrogate against an exact field: |a-b|^2 / |b|^2
@@ -912,55 +944,59 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
     s->nz = nz;
     s->N = (long long)nx * ny * nz;
     s->pg = pad_geom(nx, ny, nz);
-    const size_t P = (size_t)NLAYER * layer_stride();
-    int rc = MM_OK;
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->w, P * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->m, P * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->v, P * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->g, P * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->wb, (size_t)NLAYER * WSZ * 2);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->wt, (size_t)NLAYER * WSZ * 2);
-    for (int l = 0; l < NLAYER && rc == MM_OK; ++l) {
-        rc = sur_alloc(*s, (void **)&s->X[l], (size_t)s->N * SC * 2);
-        if (rc == MM_OK && l < NLAYER - 1) rc = sur_alloc(*s, (void **)&s->Zh[l], (size_t)s->N * SC * 2);
-        if (rc == MM_OK) rc = sur_alloc(*s, (void **)&s->Xt[l], (size_t)s->pg.G * SC * 2);
-    }
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->Zout, (size_t)s->N * 4 * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZt, (size_t)s->pg.G * SC * 2);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[0], (size_t)s->N * SC * 2);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZb[1], (size_t)s->N * SC * 2);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZbL, (size_t)s->N * SC * 2);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dZtL, (size_t)s->pg.G * SC * 2);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->part, (size_t)DW_BLOCKS * layer_stride() * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->dpart, (size_t)2 * RED_B * 8);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->sig, 16);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->tmp, (size_t)3 * s->N * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->tmp2, (size_t)3 * s->N * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->H0, (size_t)3 * s->N * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->Mprev, (size_t)3 * s->N * 4);
-    rc = rc ? rc : sur_alloc(*s, (void **)&s->Hs, (size_t)3 * s->N * 4);
-    if (rc == MM_OK) {
-        hipError_t e = hipMemset(s->w, 0, P * 4);
-        if (e == hipSuccess) e = hipMemset(s->m, 0, P * 4);
-        if (e == hipSuccess) e = hipMemset(s->v, 0, P * 4);
-        if (e == hipSuccess) e = hipMemset(s->g, 0, P * 4);
-        // channels 8..31 of the network input stay zero (the input
-        // conversion writes channels 0..7 only)
-        if (e == hipSuccess) e = hipMemset(s->X[0], 0, (size_t)s->N * SC * 2);
-        // the padded copies are zero outside the grid's cells and stay so
-        for (int l = 0; l < NLAYER && e == hipSuccess; ++l) e = hipMemset(s->Xt[l], 0, (size_t)s->pg.G * SC * 2);
-        if (e == hipSuccess) e = hipMemset(s->dZt, 0, (size_t)s->pg.G * SC * 2);
-        if (e == hipSuccess) e = hipMemset(s->dZtL, 0, (size_t)s->pg.G * SC * 2);
-        if (e == hipSuccess) e = hipMemset(s->dZbL, 0, (size_t)s->N * SC * 2);
-        if (e != hipSuccess) rc = fail(MM_EHIP, "surrogate init");
-        refresh(*s, nullptr);
-        if (hipDeviceSynchronize() != hipSuccess) rc = fail(MM_EHIP, "surrogate init sync");
-    }
-    if (rc != MM_OK) {
-        free_sur(s);
-        return rc;
-    }
+    s->bytes = sur_layout(*s, nullptr);
     *out = new mm_sur_s{s};
+    return MM_OK;
+}
+
+int mm_sur_workspace_bytes(mm_sur sur, size_t *bytes)
+{
+    if (!sur || !bytes) return fail(MM_EINVAL, "NULL surrogate or bytes");
+    *bytes = sur->s->bytes;
+    return MM_OK;
+}
+
+int mm_sur_bind_workspace(mm_sur sur, void *ws, size_t bytes)
+{
+    if (!sur || !ws) return fail(MM_EINVAL, "NULL surrogate or workspace");
+    Sur &s = *sur->s;
+    if ((uintptr_t)ws % 256 != 0) return fail(MM_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < s.bytes)
+        return fail(MM_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes; the surrogate needs " +
+                                   std::to_string(s.bytes));
+    s.ws = nullptr;
+    sur_layout(s, (char *)ws);
+    const size_t P = (size_t)NLAYER * layer_stride();
+    // weights and Adam state zero; channels 8..31 of the network input stay
+    // zero (the input conversion writes channels 0..7 only); the padded
+    // copies are zero outside the grid's cells and stay so
+    MMK_HIP(hipMemset(s.w, 0, P * 4));
+    MMK_HIP(hipMemset(s.m, 0, P * 4));
+    MMK_HIP(hipMemset(s.v, 0, P * 4));
+    MMK_HIP(hipMemset(s.g, 0, P * 4));
+    MMK_HIP(hipMemset(s.X[0], 0, (size_t)s.N * SC * 2));
+    for (int l = 0; l < NLAYER; ++l) MMK_HIP(hipMemset(s.Xt[l], 0, (size_t)s.pg.G * SC * 2));
+    MMK_HIP(hipMemset(s.dZt, 0, (size_t)s.pg.G * SC * 2));
+    MMK_HIP(hipMemset(s.dZtL, 0, (size_t)s.pg.G * SC * 2));
+    MMK_HIP(hipMemset(s.dZbL, 0, (size_t)s.N * SC * 2));
+    s.adam_t = 0;
+    refresh(s, nullptr);
+    MMK_HIP(hipDeviceSynchronize());
+    s.ws = (char *)ws;
+    return MM_OK;
+}
+
+int mm_sur_attach(mm_plan plan, mm_sur sur)
+{
+    Plan *p = plan_of(plan);
+    if (!p) return fail(MM_EINVAL, "NULL plan");
+    if (!sur) {
+        p->sur = nullptr;
+        return MM_OK;
+    }
+    if (sur->s->N != p->cells() || sur->s->nx != p->nx || sur->s->ny != p->ny)
+        return fail(MM_EINVAL, "surrogate and plan grids differ");
+    p->sur = sur;
     return MM_OK;
 }
 
@@ -971,7 +1007,9 @@ int mm_sur_make_pair(mm_plan plan, const mm_llg_params *params, float *M, int ns
                      void *stream)
 {
     Plan *pp = plan_of(plan);
-    if (!pp || !params || !M || !dm || !dh || dm == dh) return fail(MM_EINVAL, "NULL or aliased argument");
+    int rc0 = plan_ready(pp);
+    if (rc0 != MM_OK) return rc0;
+    if (!params || !M || !dm || !dh || dm == dh) return fail(MM_EINVAL, "NULL or aliased argument");
     if (nsteps < 1) return fail(MM_EINVAL, "nsteps < 1");
     Plan &p = *pp;
     hipStream_t st = (hipStream_t)stream;
@@ -994,11 +1032,12 @@ void mm_sur_destroy(mm_sur sur)
     delete sur;
 }
 
-long long mm_sur_param_count(void) { return oracle_param_count(); }
+long long mm_sur_param_count(void) { return flat_param_count(); }
 
 int mm_sur_set_params(mm_sur sur, const float *host, long long n)
 {
-    if (!sur || !host || n != oracle_param_count()) return fail(MM_EINVAL, "surrogate params: bad pointer or count");
+    if (sur_ready(sur ? sur->s : nullptr) != MM_OK) return MM_EINVAL;
+    if (!host || n != flat_param_count()) return fail(MM_EINVAL, "surrogate params: bad pointer or count");
     Sur &s = *sur->s;
     std::vector<float> w;
     to_masters(host, w);
@@ -1013,7 +1052,8 @@ int mm_sur_set_params(mm_sur sur, const float *host, long long n)
 
 int mm_sur_get_params(mm_sur sur, float *host, long long n)
 {
-    if (!sur || !host || n != oracle_param_count()) return fail(MM_EINVAL, "surrogate params: bad pointer or count");
+    if (sur_ready(sur ? sur->s : nullptr) != MM_OK) return MM_EINVAL;
+    if (!host || n != flat_param_count()) return fail(MM_EINVAL, "surrogate params: bad pointer or count");
     Sur &s = *sur->s;
     std::vector<float> w((size_t)NLAYER * layer_stride());
     MMK_HIP(hipDeviceSynchronize());
@@ -1024,7 +1064,8 @@ int mm_sur_get_params(mm_sur sur, float *host, long long n)
 
 int mm_sur_forward(mm_sur sur, const float *dm, float *dh, int normalize, void *stream)
 {
-    if (!sur || !dm || !dh) return fail(MM_EINVAL, "NULL surrogate or field");
+    if (sur_ready(sur ? sur->s : nullptr) != MM_OK) return MM_EINVAL;
+    if (!dm || !dh) return fail(MM_EINVAL, "NULL surrogate or field");
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
     sur_input(s, dm, normalize, st);
@@ -1036,8 +1077,9 @@ int mm_sur_forward(mm_sur sur, const float *dm, float *dh, int normalize, void *
 int mm_sur_gradients(mm_sur sur, const float *dm, const float *dh, int normalize, double *loss, float *grads,
                      long long n, void *stream)
 {
-    if (!sur || !dm || !dh || !loss) return fail(MM_EINVAL, "NULL surrogate argument");
-    if (grads && n != oracle_param_count()) return fail(MM_EINVAL, "gradient count");
+    if (sur_ready(sur ? sur->s : nullptr) != MM_OK) return MM_EINVAL;
+    if (!dm || !dh || !loss) return fail(MM_EINVAL, "NULL surrogate argument");
+    if (grads && n != flat_param_count()) return fail(MM_EINVAL, "gradient count");
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
     sur_input(s, dm, normalize, st, true);
@@ -1053,7 +1095,8 @@ int mm_sur_gradients(mm_sur sur, const float *dm, const float *dh, int normalize
 int mm_sur_train_step(mm_sur sur, const float *dm, const float *dh, float lr, int normalize, double *loss,
                       void *stream)
 {
-    if (!sur || !dm || !dh || !loss) return fail(MM_EINVAL, "NULL surrogate argument");
+    if (sur_ready(sur ? sur->s : nullptr) != MM_OK) return MM_EINVAL;
+    if (!dm || !dh || !loss) return fail(MM_EINVAL, "NULL surrogate argument");
     if (!(lr > 0.f)) return fail(MM_EINVAL, "learning rate must be > 0");
     Sur &s = *sur->s;
     hipStream_t st = (hipStream_t)stream;
@@ -1074,7 +1117,7 @@ int mm_sur_train_step(mm_sur sur, const float *dm, const float *dh, float lr, in
 
 int mm_sur_zero(mm_sur sur)
 {
-    if (!sur) return fail(MM_EINVAL, "NULL surrogate");
+    if (sur_ready(sur ? sur->s : nullptr) != MM_OK) return MM_EINVAL;
     Sur &s = *sur->s;
     const size_t P = (size_t)NLAYER * layer_stride();
     MMK_HIP(hipMemset(s.w, 0, P * 4));
@@ -1091,7 +1134,8 @@ int mm_llg_step_surrogate(mm_plan plan, mm_sur sur, const mm_llg_params *params,
                           mm_sur_stats *stats, void *stream)
 {
     Plan *pp = plan_of(plan);
-    if (!pp || !sur || !params || !M) return fail(MM_EINVAL, "NULL plan, surrogate, params or M");
+    if (plan_ready(pp) != MM_OK || sur_ready(sur ? sur->s : nullptr) != MM_OK) return MM_EINVAL;
+    if (!params || !M) return fail(MM_EINVAL, "NULL params or M");
     if (params->integrator != MM_RK4) return fail(MM_EINVAL, "surrogate stepping needs RK4");
     if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
     Plan &p = *pp;

@@ -247,22 +247,35 @@ static int axis_transform(const double *in, double *out, int n, long long outer,
     return MM_OK;
 }
 
-int build_spectrum(Plan &p, hipStream_t s)
+// Two FP64 scratch arrays: A holds the tensor octant and the x-y transform,
+// B the x transform and the z transform.
+static void scratch_sizes(int nx, int ny, int nz, size_t &big, size_t &big2)
 {
-    const int nx = p.nx, ny = p.ny, nz = p.nz;
     const size_t n = (size_t)nx * ny * nz;
     const size_t sz_a = 6 * n;
     const size_t sz_b = 6 * (size_t)nz * ny * (nx + 1);
     const size_t sz_c = 6 * (size_t)nz * (ny + 1) * (nx + 1);
     const size_t sz_d = 6 * (size_t)(nz + 1) * (ny + 1) * (nx + 1);
-    double *A = nullptr, *B = nullptr;
-    size_t big = sz_a > sz_c ? sz_a : sz_c;
-    size_t big2 = sz_b > sz_d ? sz_b : sz_d;
-    MMK_HIP(hipMalloc(&A, big * sizeof(double)));
-    if (hipMalloc(&B, big2 * sizeof(double)) != hipSuccess) {
-        (void)hipFree(A);
-        return fail(MM_ENOMEM, "spectrum scratch");
-    }
+    big = sz_a > sz_c ? sz_a : sz_c;
+    big2 = sz_b > sz_d ? sz_b : sz_d;
+}
+
+size_t spectrum_scratch_bytes(int nx, int ny, int nz)
+{
+    size_t big, big2;
+    scratch_sizes(nx, ny, nz, big, big2);
+    return (((big * sizeof(double)) + 255) & ~(size_t)255) + big2 * sizeof(double);
+}
+
+// K~ into p.Kt, with the FP64 scratch in the plan's run-time region (the
+// workspace is bound and no step has run yet).
+int build_spectrum(Plan &p, hipStream_t s)
+{
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    size_t big, big2;
+    scratch_sizes(nx, ny, nz, big, big2);
+    double *A = reinterpret_cast<double *>(p.run);
+    double *B = reinterpret_cast<double *>(p.run + (((big * sizeof(double)) + 255) & ~(size_t)255));
     int rc = newell_octant_device(nx, ny, nz, p.dx, p.dy, p.dz, A, s);
     // x: A[6][nz*ny][nx] -> B[6][nz*ny][nx+1]
     if (rc == MM_OK) rc = axis_transform(A, B, nx, (long long)nz * ny, 1, 0, s);
@@ -288,8 +301,6 @@ int build_spectrum(Plan &p, hipStream_t s)
         if (e != hipSuccess) rc = fail(MM_EHIP, std::string("k_spectrum_store: ") + hipGetErrorString(e));
     }
     hipError_t e = hipStreamSynchronize(s);
-    (void)hipFree(A);
-    (void)hipFree(B);
     if (rc == MM_OK && e != hipSuccess) rc = fail(MM_EHIP, std::string("spectrum sync: ") + hipGetErrorString(e));
     return rc;
 }

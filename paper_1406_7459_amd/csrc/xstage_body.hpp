@@ -1,0 +1,257 @@
+// xstage_body.hpp -- the x-inverse of one demag evaluation, the LLG stage
+// that consumes its field and the x-forward of the stage's result, fused in
+// one pass over the rows of the grid.
+//
+// Per stage the unfused path runs XINV (half spectrum -> H), the stage
+// kernel (H, S, Mn, kacc -> S', kacc) and the next evaluation's XFWD
+// (S' -> half spectrum), moving H out and back and S' back in.  Here a
+// workgroup owns 2P consecutive cell rows (r = k ny + j) of all three
+// components:
+//   1. inverse C2R of its rows (xinv_body's arithmetic, one component per
+//      thread group) -> H of its cells in LDS;
+//   2. the stage on its cells (stage_cell, the same per-cell arithmetic as
+//      the stage kernel), H from LDS, neighbours and the rest from global
+//      memory; S' to global memory and into LDS in place of H;
+//   3. (FWD) forward R2C of S' from LDS (xfwd_body's arithmetic) -> X1.
+// X1 rows are read and rewritten by their owning workgroup only.  Every
+// value is computed by the same operations as on the unfused path, so the
+// states are bitwise those of XINV + stage + XFWD.
+#pragma once
+#include "demag_kernels.hpp"
+#include "stage_body.hpp"
+
+namespace mmk {
+
+// cells per thread task of the stage phase: 4 when nx % 4 == 0, else 2 or 1
+template <int L> constexpr int xs_width() { return (L / 2) % 4 == 0 ? 4 : ((L / 2) % 2 == 0 ? 2 : 1); }
+
+// LDS layout: twiddles | 3P transforms of XS slots (float2) | H/S' rows
+// [3][2P][nx] (float, 16-byte aligned).
+template <int L> constexpr int xs_slots() { return lds_rows(L) + 1; }
+template <int L> __host__ __device__ constexpr size_t xs_rows_offset(int P)
+{
+    return (((size_t)tw_slots<L>() + 3 * (size_t)P * xs_slots<L>()) * sizeof(float2) + 15) & ~(size_t)15;
+}
+template <int L> __host__ __device__ constexpr size_t xs_lds_bytes(int P)
+{
+    return xs_rows_offset<L>(P) + 3 * 2 * (size_t)P * (L / 2) * sizeof(float);
+}
+
+template <int L, int STAGE, bool FWD>
+__device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float *S, const float *Mn,
+                                            float *__restrict__ kacc, float *out, int ny, int nz, const StageCoef &c,
+                                            const float2 *__restrict__ tw, int lp2, int bx)
+{
+    constexpr int E = Factors<L>::E, Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
+    constexpr int W = xs_width<L>();
+    extern __shared__ float2 lds[];
+    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const int P = 1 << lp2;
+    const int PQ = P * Q;
+    const int t = threadIdx.x;
+    const int g = t / PQ;  // component of this thread's transforms
+    const int tt = t - g * PQ;
+    const int q = tt % Q, p = tt / Q;
+    const int ncr = nz * ny;  // cell rows per component
+    const int r0 = bx * 2 * P;
+    const int ra = r0 + 2 * p, rb = ra + 1;
+    const bool oka = ra < ncr, okb = rb < ncr;
+    constexpr int XS = xs_slots<L>();
+    float2 *fbuf = lds + tw_slots<L>();
+    float *rows = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + xs_rows_offset<L>(P));
+    const int rstride = 2 * P * NX;  // floats per component in `rows`
+    const LdsView s{fbuf, 1, (g * P + p) * XS};
+
+    // 1. inverse C2R of rows ra, rb of component g (as xinv_body)
+    {
+        const float2 *sa = X1 + ((size_t)g * ncr + ra) * XP;
+        const float2 *sb = sa + XP;
+        float2 v[E];
+        constexpr int R0 = first_radix<L, false>();
+#pragma unroll
+        for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int k = q + Q * b + r * (L / R0);
+                float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
+                if (k <= NX) {
+                    if (oka) A = sa[k];
+                    if (okb) B = sb[k];
+                    if (k == 0 || k == NX) {
+                        A.y = 0.f;
+                        B.y = 0.f;
+                    }
+                } else {
+                    if (oka) A = cconj(sa[L - k]);
+                    if (okb) B = cconj(sb[L - k]);
+                }
+                v[b * R0 + r] = make_float2(A.x - B.y, A.y + B.x);
+            }
+        fft_e<L, E, +1, false>(v, s, q, twl);
+        constexpr int RL = last_radix<L, false>();
+        float *ha = rows + g * rstride + 2 * p * NX;
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int i = q + Q * b + r * (L / RL);
+                const bool upper = r * (L / RL) >= NX;
+                if (!upper && i < NX) {
+                    ha[i] = v[b * RL + r].x;
+                    ha[NX + i] = v[b * RL + r].y;
+                }
+            }
+    }
+    __syncthreads();
+
+    // 2. the stage on cells [r0 nx, (r0 + 2P) nx), W consecutive cells of a
+    // row per task (as stage_body_vec, with the field from LDS)
+    {
+        typedef typename VecOf<W == 1 ? 2 : W>::T V2;
+        const unsigned nx = NX, nxy = (unsigned)NX * (unsigned)ny;
+        const unsigned n = nxy * (unsigned)nz;
+        const unsigned base = (unsigned)r0 * NX;
+        for (unsigned e = (unsigned)t * W; e < (unsigned)rstride; e += blockDim.x * W) {
+            const unsigned id = base + e;
+            if (id >= n) break;
+            const unsigned k = id / nxy;
+            const unsigned rem = id - k * nxy;
+            const unsigned j = rem / nx;
+            const unsigned i = rem - j * nx;
+            const unsigned ym = j > 0 ? id - nx : id, yp = j + 1 < (unsigned)ny ? id + nx : id;
+            const unsigned zm = k > 0 ? id - nxy : id, zp = k + 1 < (unsigned)nz ? id + nxy : id;
+            float m[3][W], y0[3][W], y1[3][W], z0[3][W], z1[3][W], mn[3][W], ka[3][W], hd[3][W];
+            float left[3], right[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float *sc = S + (size_t)a * n;
+                const float *mc = Mn + (size_t)a * n;
+                const float *kc = kacc + (size_t)a * n;
+                const float *hc = rows + a * rstride + e;
+                if constexpr (W == 1) {
+                    m[a][0] = ld32(sc, id);
+                    y0[a][0] = ld32(sc, ym);
+                    y1[a][0] = ld32(sc, yp);
+                    z0[a][0] = ld32(sc, zm);
+                    z1[a][0] = ld32(sc, zp);
+                    mn[a][0] = ld32(mc, id);
+                    ka[a][0] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? ld32(kc, id) : 0.f;
+                    hd[a][0] = hc[0];
+                } else {
+                    typedef typename VecOf<W>::T V;
+                    const V vm = ldv32<V>(sc, id), vy0 = ldv32<V>(sc, ym), vy1 = ldv32<V>(sc, yp);
+                    const V vz0 = ldv32<V>(sc, zm), vz1 = ldv32<V>(sc, zp), vmn = ldv32<V>(mc, id);
+                    V vka;
+                    if constexpr (STAGE == 2 || STAGE == 3 || STAGE == 4) vka = ldv32<V>(kc, id);
+                    const V vh = *reinterpret_cast<const V *>(hc);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        m[a][w] = lane_of<W>(vm, w);
+                        y0[a][w] = lane_of<W>(vy0, w);
+                        y1[a][w] = lane_of<W>(vy1, w);
+                        z0[a][w] = lane_of<W>(vz0, w);
+                        z1[a][w] = lane_of<W>(vz1, w);
+                        mn[a][w] = lane_of<W>(vmn, w);
+                        ka[a][w] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? lane_of<W>(vka, w) : 0.f;
+                        hd[a][w] = lane_of<W>(vh, w);
+                    }
+                }
+                left[a] = i > 0 ? ld32(sc, id - 1) : m[a][0];
+                right[a] = i + W < nx ? ld32(sc, id + W) : m[a][W - 1];
+            }
+            float o[3][W], kn[3][W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                float mm[3], xm[3], xp[3], a0[3], a1[3], b0[3], b1[3], h[3], mnn[3], kk[3], oo[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    mm[a] = m[a][w];
+                    xm[a] = w > 0 ? m[a][w - 1] : left[a];
+                    xp[a] = w + 1 < W ? m[a][w + 1] : right[a];
+                    a0[a] = y0[a][w];
+                    a1[a] = y1[a][w];
+                    b0[a] = z0[a][w];
+                    b1[a] = z1[a][w];
+                    h[a] = hd[a][w];
+                    mnn[a] = mn[a][w];
+                    kk[a] = ka[a][w];
+                }
+                stage_cell<STAGE>(mm, xm, xp, a0, a1, b0, b1, h, mnn, kk, oo, c);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    o[a][w] = oo[a];
+                    kn[a][w] = kk[a];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                float *oc = out + (size_t)a * n;
+                float *kc = kacc + (size_t)a * n;
+                float *hc = rows + a * rstride + e;
+                if constexpr (W == 1) {
+                    if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) st32(kc, id, kn[a][0]);
+                    st32(oc, id, o[a][0]);
+                    if constexpr (FWD) hc[0] = o[a][0];
+                } else {
+                    typedef typename VecOf<W>::T V;
+                    V vo, vk;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        set_lane<W>(vo, w, o[a][w]);
+                        set_lane<W>(vk, w, kn[a][w]);
+                    }
+                    if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) stv32<V>(kc, id, vk);
+                    stv32<V>(oc, id, vo);
+                    if constexpr (FWD) *reinterpret_cast<V *>(hc) = vo;
+                }
+            }
+        }
+        (void)sizeof(V2);
+    }
+    if constexpr (!FWD) return;
+
+    __syncthreads();
+    // 3. forward R2C of the new state's rows ra, rb of component g (as
+    // xfwd_body; a row past the grid enters as zeros)
+    {
+        const float *za = rows + g * rstride + 2 * p * NX;
+        const float *zb = za + NX;
+        float2 v[E];
+        constexpr int R0 = first_radix<L, false>();
+#pragma unroll
+        for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int i = q + Q * b + r * (L / R0);
+                const bool upper = r * (L / R0) >= NX;
+                const bool in = !upper && i < NX;
+                v[b * R0 + r] = make_float2(in && oka ? za[i] : 0.f, in && okb ? zb[i] : 0.f);
+            }
+        fft_e<L, E, -1, false>(v, s, q, twl);
+        constexpr int RL = last_radix<L, false>();
+        float2 *col = fbuf + (g * P + p) * XS;
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) col[lds_slot(q + Q * b + r * (L / RL))] = v[b * RL + r];
+        __syncthreads();
+        float2 *da = X1 + ((size_t)g * ncr + ra) * XP;
+        float2 *db = da + XP;
+#pragma unroll
+        for (int b = 0; b < E / RL; ++b)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int k = q + Q * b + r * (L / RL);
+                if (k <= NX) {
+                    const float2 z = v[b * RL + r];
+                    const float2 w = col[lds_slot(k == 0 ? 0 : L - k)];
+                    const float2 sp = make_float2(z.x + w.x, z.y - w.y);
+                    const float2 sm = make_float2(z.x - w.x, z.y + w.y);
+                    if (oka) da[k] = make_float2(0.5f * sp.x, 0.5f * sp.y);
+                    if (okb) db[k] = make_float2(0.5f * sm.y, -0.5f * sm.x);
+                }
+            }
+    }
+}
+
+}  // namespace mmk

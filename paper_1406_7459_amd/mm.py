@@ -19,16 +19,20 @@ LIB_PATH = os.path.join(_HERE, "libmm.so")
 MM_OK, MM_EINVAL, MM_ENOMEM, MM_ENODEV, MM_EHIP, MM_ENONFINITE, MM_ETUNE, MM_EUNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
 MM_RK4, MM_EULER = 0, 1
-PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv", "stage", "reduce")
+MM_EXACT, MM_SURROGATE = 0, 1
+PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv", "stage", "reduce", "xstage")
+NPASS = len(PASSES)
 PASS_INDEX = {n: i for i, n in enumerate(PASSES)}
 
-SYMBOLS = ("mm_demag_setup", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_llg_relax",
+SYMBOLS = ("mm_demag_setup", "mm_plan_workspace_bytes", "mm_plan_bind_workspace", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_llg_relax",
            "mm_newell_tensor",
            "mm_plan_spectrum", "mm_plan_query", "mm_plan_set_tile", "mm_plan_autotune",
            "mm_plan_set_timing", "mm_plan_timing", "mm_destroy", "mm_status_string",
-           "mm_last_error", "mm_batch_setup", "mm_batch_demag", "mm_batch_step",
+           "mm_last_error", "mm_batch_setup", "mm_batch_workspace_bytes",
+           "mm_batch_bind_workspace", "mm_batch_demag", "mm_batch_step",
            "mm_batch_autotune", "mm_batch_query", "mm_batch_group_tile", "mm_batch_destroy",
-           "mm_sur_create", "mm_sur_param_count", "mm_sur_set_params", "mm_sur_get_params",
+           "mm_sur_create", "mm_sur_workspace_bytes", "mm_sur_bind_workspace", "mm_sur_attach",
+           "mm_sur_param_count", "mm_sur_set_params", "mm_sur_get_params",
            "mm_sur_zero", "mm_sur_forward", "mm_sur_gradients", "mm_sur_train_step",
            "mm_llg_step_surrogate", "mm_sur_make_pair", "mm_sur_destroy")
 
@@ -53,24 +57,30 @@ class LLGParams(C.Structure):
     _fields_ = [("Ms", C.c_double), ("A", C.c_double), ("Ku", C.c_double),
                 ("axis", C.c_double * 3), ("alpha", C.c_double), ("gamma0", C.c_double),
                 ("Hext", C.c_double * 3), ("dt", C.c_double), ("integrator", C.c_int),
-                ("renorm", C.c_int)]
+                ("renorm", C.c_int), ("demag_mode", C.c_int), ("log_every", C.c_int),
+                ("sur_tol", C.c_double)]
 
     @classmethod
     def make(cls, Ms, A, Ku=0.0, axis=(1.0, 0.0, 0.0), alpha=0.5, gamma0=2.211e5,
-             Hext=(0.0, 0.0, 0.0), dt=1e-14, integrator="rk4", renorm=True):
+             Hext=(0.0, 0.0, 0.0), dt=1e-14, integrator="rk4", renorm=True, demag="exact",
+             log_every=0, sur_tol=1e-3):
         return cls(float(Ms), float(A), float(Ku), (C.c_double * 3)(*map(float, axis)),
                    float(alpha), float(gamma0), (C.c_double * 3)(*map(float, Hext)), float(dt),
-                   MM_EULER if integrator == "euler" else MM_RK4, 1 if renorm else 0)
+                   MM_EULER if integrator == "euler" else MM_RK4, 1 if renorm else 0,
+                   MM_SURROGATE if demag == "surrogate" else MM_EXACT, int(log_every),
+                   float(sur_tol))
 
 
 class Stats(C.Structure):
     _fields_ = [("E_ex", C.c_double), ("E_an", C.c_double), ("E_d", C.c_double),
                 ("E_z", C.c_double), ("E_tot", C.c_double), ("torque_max", C.c_double),
-                ("m_avg", C.c_double * 3), ("nonfinite", C.c_longlong)]
+                ("m_avg", C.c_double * 3), ("nonfinite", C.c_longlong), ("steps", C.c_longlong),
+                ("fallbacks", C.c_longlong)]
 
     def as_dict(self):
         return dict(E_ex=self.E_ex, E_an=self.E_an, E_d=self.E_d, E_z=self.E_z, E_tot=self.E_tot,
-                    torque_max=self.torque_max, m_avg=tuple(self.m_avg), nonfinite=self.nonfinite)
+                    torque_max=self.torque_max, m_avg=tuple(self.m_avg), nonfinite=self.nonfinite,
+                    steps=self.steps, fallbacks=self.fallbacks)
 
 
 class SurStats(C.Structure):
@@ -87,7 +97,7 @@ class SurStats(C.Structure):
 class PlanInfo(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("Lx", C.c_int),
                 ("Ly", C.c_int), ("Lz", C.c_int), ("spectrum_count", C.c_longlong),
-                ("workspace_bytes", C.c_longlong), ("cfg", C.c_int * 8)]
+                ("workspace_bytes", C.c_longlong), ("cfg", C.c_int * 9)]
 
 
 _lib = None
@@ -103,9 +113,12 @@ def lib():
                           "(expected at %s)" % LIB_PATH)
     L = C.CDLL(LIB_PATH)
     vp, i, d, ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
+    sz = C.c_size_t
     L.mm_demag_setup.argtypes = [i, i, i, d, d, d, C.POINTER(vp)]
+    L.mm_plan_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+    L.mm_plan_bind_workspace.argtypes = [vp, vp, sz]
     L.mm_demag_apply.argtypes = [vp, vp, vp, vp]
-    L.mm_llg_step.argtypes = [vp, C.POINTER(LLGParams), vp, i, vp]
+    L.mm_llg_step.argtypes = [vp, C.POINTER(LLGParams), vp, i, C.POINTER(Stats), vp]
     L.mm_reduce.argtypes = [vp, C.POINTER(LLGParams), vp, C.POINTER(Stats), vp]
     L.mm_llg_relax.argtypes = [vp, C.POINTER(LLGParams), vp, d, ll, i, C.POINTER(Stats),
                                C.POINTER(C.c_longlong), vp]
@@ -120,6 +133,8 @@ def lib():
     L.mm_destroy.restype = None
     ip, dp = C.POINTER(C.c_int), C.POINTER(C.c_double)
     L.mm_batch_setup.argtypes = [i, ip, ip, ip, dp, dp, dp, C.POINTER(vp)]
+    L.mm_batch_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+    L.mm_batch_bind_workspace.argtypes = [vp, vp, sz]
     L.mm_batch_demag.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
     L.mm_batch_step.argtypes = [vp, C.POINTER(LLGParams), C.POINTER(vp), i, vp]
     L.mm_batch_autotune.argtypes = [vp, i, vp]
@@ -128,6 +143,9 @@ def lib():
     L.mm_batch_destroy.argtypes = [vp]
     L.mm_batch_destroy.restype = None
     L.mm_sur_create.argtypes = [i, i, i, C.POINTER(vp)]
+    L.mm_sur_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+    L.mm_sur_bind_workspace.argtypes = [vp, vp, sz]
+    L.mm_sur_attach.argtypes = [vp, vp]
     L.mm_sur_param_count.argtypes = []
     L.mm_sur_set_params.argtypes = [vp, C.POINTER(C.c_float), ll]
     L.mm_sur_get_params.argtypes = [vp, C.POINTER(C.c_float), ll]
@@ -161,6 +179,15 @@ def _stream(stream=None) -> int:
     return s.cuda_stream
 
 
+def _workspace(query, bind, h, where):
+    """Allocate the object's device workspace through torch and bind it."""
+    n = C.c_size_t()
+    _check(query(h, C.byref(n)), where + " bytes")
+    ws = torch.empty(max(1, n.value), dtype=torch.uint8, device="cuda")
+    _check(bind(h, ws.data_ptr(), n.value), where + " bind")
+    return ws
+
+
 def _field(t: torch.Tensor, shape, name):
     if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
         raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
@@ -180,6 +207,9 @@ class Plan:
         self._h = h
         self.shape = (int(nx), int(ny), int(nz))
         self.cell = (float(dx), float(dy), float(dz))
+        # device memory of the plan, owned here (torch), bound to the plan
+        self.workspace = _workspace(L.mm_plan_workspace_bytes, L.mm_plan_bind_workspace, h,
+                                    "mm_plan_workspace")
 
     @property
     def field_shape(self):
@@ -203,9 +233,26 @@ class Plan:
 
     def step(self, params: LLGParams, M: torch.Tensor, nsteps: int, stream=None) -> torch.Tensor:
         pm = _field(M, self.field_shape, "M")
-        _check(lib().mm_llg_step(self._h, C.byref(params), pm, int(nsteps), _stream(stream)),
+        _check(lib().mm_llg_step(self._h, C.byref(params), pm, int(nsteps), None, _stream(stream)),
                "mm_llg_step")
         return M
+
+    @staticmethod
+    def stats_count(nsteps: int, log_every: int) -> int:
+        e = log_every if 0 < log_every < nsteps else max(nsteps, 1)
+        return max(1, -(-nsteps // e))
+
+    def step_stats(self, params: LLGParams, M: torch.Tensor, nsteps: int, stream=None,
+                   allow_nonfinite=False) -> list:
+        """mm_llg_step with a stats array: observables after every
+        params.log_every steps (and after the last)."""
+        pm = _field(M, self.field_shape, "M")
+        n = self.stats_count(int(nsteps), int(params.log_every))
+        st = (Stats * n)()
+        rc = lib().mm_llg_step(self._h, C.byref(params), pm, int(nsteps), st, _stream(stream))
+        if not (rc == MM_ENONFINITE and allow_nonfinite):
+            _check(rc, "mm_llg_step")
+        return [x.as_dict() for x in st]
 
     def reduce(self, params: LLGParams, M: torch.Tensor, stream=None, allow_nonfinite=False) -> dict:
         pm = _field(M, self.field_shape, "M")
@@ -233,7 +280,7 @@ class Plan:
         _check(lib().mm_plan_query(self._h, C.byref(inf)), "mm_plan_query")
         return dict(nx=inf.nx, ny=inf.ny, nz=inf.nz, Lx=inf.Lx, Ly=inf.Ly, Lz=inf.Lz,
                     spectrum_count=inf.spectrum_count, workspace_bytes=inf.workspace_bytes,
-                    tiles={PASSES[k]: inf.cfg[k] for k in range(8)})
+                    tiles={PASSES[k]: inf.cfg[k] for k in range(NPASS)})
 
     def spectrum(self, stream=None) -> torch.Tensor:
         """The stored K~ octant, float32 [nzK][ny+1][nx+1][6]."""
@@ -258,10 +305,10 @@ class Plan:
         _check(lib().mm_plan_set_timing(self._h, 1 if enable else 0), "mm_plan_set_timing")
 
     def timing(self) -> dict:
-        ms = (C.c_double * 8)()
-        n = (C.c_longlong * 8)()
+        ms = (C.c_double * NPASS)()
+        n = (C.c_longlong * NPASS)()
         _check(lib().mm_plan_timing(self._h, ms, n), "mm_plan_timing")
-        return {PASSES[k]: (ms[k], n[k]) for k in range(8)}
+        return {PASSES[k]: (ms[k], n[k]) for k in range(NPASS)}
 
 
 def newell_tensor(nx, ny, nz, dx, dy, dz, stream=None) -> torch.Tensor:
@@ -290,6 +337,8 @@ class Batch:
         self._h = h
         self.shapes = [tuple(map(int, s)) for s in shapes]
         self.count = n
+        self.workspace = _workspace(L.mm_batch_workspace_bytes, L.mm_batch_bind_workspace, h,
+                                    "mm_batch_workspace")
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -347,6 +396,13 @@ class Surrogate:
         _check(lib().mm_sur_create(int(nx), int(ny), int(nz), C.byref(h)), "mm_sur_create")
         self._h = h
         self.shape = (int(nx), int(ny), int(nz))
+        self.workspace = _workspace(lib().mm_sur_workspace_bytes, lib().mm_sur_bind_workspace, h,
+                                    "mm_sur_workspace")
+
+    def attach(self, plan: "Plan"):
+        """mm_sur_attach: MM_SURROGATE steps of `plan` use this network."""
+        _check(lib().mm_sur_attach(plan._h, self._h), "mm_sur_attach")
+        plan._sur = self  # keep the network alive while attached
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -71,7 +71,15 @@ def test_null_arguments_are_rejected(L):
     assert L.mm_demag_setup(4, 4, 4, 1e-9, 1e-9, 1e-9, None) == mm.MM_EINVAL
     assert L.mm_demag_apply(None, None, None, None) == mm.MM_EINVAL
     p = mm.LLGParams.make(Ms=8e5, A=1.3e-11)
-    assert L.mm_llg_step(None, C.byref(p), None, 1, None) == mm.MM_EINVAL
+    assert L.mm_llg_step(None, C.byref(p), None, 1, None, None) == mm.MM_EINVAL
+    n = C.c_size_t(7)
+    assert L.mm_plan_workspace_bytes(None, C.byref(n)) == mm.MM_EINVAL
+    assert L.mm_plan_bind_workspace(None, None, 0) == mm.MM_EINVAL
+    assert L.mm_batch_workspace_bytes(None, C.byref(n)) == mm.MM_EINVAL
+    assert L.mm_batch_bind_workspace(None, None, 0) == mm.MM_EINVAL
+    assert L.mm_sur_workspace_bytes(None, C.byref(n)) == mm.MM_EINVAL
+    assert L.mm_sur_bind_workspace(None, None, 0) == mm.MM_EINVAL
+    assert L.mm_sur_attach(None, None) == mm.MM_EINVAL
     assert L.mm_reduce(None, C.byref(p), None, None, None) == mm.MM_EINVAL
     assert L.mm_newell_tensor(4, 4, 4, 1e-9, 1e-9, 1e-9, None, None) == mm.MM_EINVAL
     L.mm_destroy(None)
@@ -92,3 +100,40 @@ def test_last_error_truncates(L):
     buf = C.create_string_buffer(4)
     n = L.mm_last_error(buf, 4)
     assert n > 3 and len(buf.value) == 3
+
+
+def test_params_and_stats_layout_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the header's field
+    offsets and sizes, as a C compiler lays them out."""
+    import subprocess
+    from paper_1406_7459_amd import mm
+    structs = {"mm_llg_params": mm.LLGParams, "mm_stats": mm.Stats, "mm_plan_info": mm.PlanInfo,
+               "mm_sur_stats": mm.SurStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f[0], cname, f[0]))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for ln in subprocess.check_output([str(exe)]).decode().split("\n"):
+        if ln:
+            a, b, c = ln.split()
+            got[(a, b)] = int(c)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_stats_count_rule():
+    from paper_1406_7459_amd import mm
+    assert mm.Plan.stats_count(10, 0) == 1
+    assert mm.Plan.stats_count(10, 3) == 4
+    assert mm.Plan.stats_count(10, 5) == 2
+    assert mm.Plan.stats_count(10, 10) == 1
+    assert mm.Plan.stats_count(0, 0) == 1

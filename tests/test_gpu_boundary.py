@@ -1,0 +1,173 @@
+"""The C-ABI boundary: caller-owned workspaces (mm_*_workspace_bytes /
+mm_*_bind_workspace), the stats records of mm_llg_step and surrogate
+stepping through mm_llg_step after mm_sur_attach.  State stays on the
+device and the caller moves data only at the start and the end (paper
+Sec. 3); observables follow eq. (1)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpucommon import rel_l2, say, to_dev, to_host
+from paper_1406_7459_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(mm, mat, **kw):
+    d = dict(Ms=mat.Ms, A=mat.A, Ku=mat.Ku, axis=mat.axis, alpha=mat.alpha, gamma0=mat.gamma0,
+             Hext=mat.Hext, dt=mat.dt)
+    d.update(kw)
+    return mm.LLGParams.make(**d)
+
+
+def test_unbound_plan_computes_nothing_and_binding_checks_size():
+    from paper_1406_7459_amd import mm
+    L = mm.lib()
+    h = C.c_void_p()
+    assert L.mm_demag_setup(16, 8, 4, 2e-9, 2e-9, 2e-9, C.byref(h)) == mm.MM_OK
+    M = to_dev(8e5 * W.random_unit(16, 8, 4, seed=1))
+    H = torch.empty_like(M)
+    assert L.mm_demag_apply(h, M.data_ptr(), H.data_ptr(), None) == mm.MM_EINVAL
+    n = C.c_size_t()
+    assert L.mm_plan_workspace_bytes(h, C.byref(n)) == mm.MM_OK
+    assert n.value > 0
+    ws = torch.empty(n.value + 512, dtype=torch.uint8, device="cuda")
+    assert L.mm_plan_bind_workspace(h, ws.data_ptr(), n.value - 1) == mm.MM_ENOMEM
+    assert L.mm_plan_bind_workspace(h, ws.data_ptr() + 8, n.value) == mm.MM_EINVAL
+    assert L.mm_plan_bind_workspace(h, ws.data_ptr(), n.value) == mm.MM_OK
+    assert L.mm_demag_apply(h, M.data_ptr(), H.data_ptr(), None) == mm.MM_OK
+    torch.cuda.synchronize()
+    L.mm_destroy(h)
+
+
+def test_rebinding_moves_the_plan_and_keeps_results_bitwise():
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 24, 12, 6
+    plan = mm.Plan(nx, ny, nz, 2e-9, 2e-9, 2e-9)
+    M = to_dev(8e5 * W.random_unit(nx, ny, nz, seed=2))
+    h1 = to_host(plan.demag(M))
+    L = mm.lib()
+    n = C.c_size_t()
+    L.mm_plan_workspace_bytes(plan._h, C.byref(n))
+    ws2 = torch.full((n.value,), 0x7F, dtype=torch.uint8, device="cuda")  # garbage content
+    assert L.mm_plan_bind_workspace(plan._h, ws2.data_ptr(), n.value) == mm.MM_OK
+    plan.workspace = ws2
+    h2 = to_host(plan.demag(M))
+    assert np.array_equal(h1, h2)
+    assert plan.info()["workspace_bytes"] == n.value
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "euler"])
+def test_step_stats_records_match_reduce(integrator):
+    """mm_llg_step with log_every = 4 over 10 steps fills 3 records (after
+    4, 8 and 10 steps) equal to mm_reduce of the states reached by plain
+    stepping, and the final state equals plain stepping bitwise."""
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 16, 8, 4
+    d = (2e-9, 2e-9, 2e-9)
+    mat = W.Material(Ms=1e6, A=1.5e-11, Ku=5e4, axis=(1, 0, 0), alpha=0.2, Hext=(1e4, 0, 0))
+    p = _params(mm, mat, integrator=integrator, log_every=4)
+    plan = mm.Plan(nx, ny, nz, *d)
+    M0 = to_dev(mat.Ms * W.random_unit(nx, ny, nz, seed=3))
+    a = M0.clone()
+    recs = plan.step_stats(p, a, 10)
+    assert [r["steps"] for r in recs] == [4, 8, 10]
+    b = M0.clone()
+    ref = []
+    for k in (4, 4, 2):
+        plan.step(p, b, k)
+        ref.append(plan.reduce(p, b))
+    assert np.array_equal(to_host(a), to_host(b))
+    for r, q in zip(recs, ref):
+        for k in ("E_ex", "E_an", "E_d", "E_z", "E_tot", "torque_max"):
+            assert r[k] == q[k], k
+        assert r["m_avg"] == q["m_avg"]
+        assert r["fallbacks"] == 0
+
+
+def test_step_stats_of_zero_steps_is_the_current_state_and_matches_oracle():
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 12, 8, 3
+    d = (2e-9, 3e-9, 2e-9)
+    mat = W.Material(Ms=1e6, A=1.5e-11, Ku=5e4, axis=(0, 1, 0), alpha=0.1, Hext=(2e4, 0, -1e4))
+    p = _params(mm, mat)
+    plan = mm.Plan(nx, ny, nz, *d)
+    M = to_dev(mat.Ms * W.random_unit(nx, ny, nz, seed=4))
+    Mq = to_host(M)
+    (r,) = plan.step_stats(p, M, 0)
+    assert r["steps"] == 0
+    po = oracle.Params(Ms=mat.Ms, A=mat.A, Ku=mat.Ku, axis=mat.axis, alpha=mat.alpha,
+                       gamma0=mat.gamma0, Hext=mat.Hext, dt=mat.dt)
+    ob = oracle.Demag(nx, ny, nz, *d).observables(po, Mq)
+    for k in ("E_ex", "E_an", "E_d", "E_z", "E_tot"):
+        assert r[k] == pytest.approx(ob[k], rel=1e-5, abs=1e-8 * abs(ob["E_tot"])), k
+    assert np.array_equal(to_host(M), Mq)
+
+
+def test_more_records_than_the_device_log_holds():
+    """600 records (more than the 256 kept on the device between read-backs)
+    come back in order."""
+    from paper_1406_7459_amd import mm
+    plan = mm.Plan(8, 8, 1, 4e-9, 4e-9, 4e-9)
+    p = mm.LLGParams.make(Ms=8e5, A=1.3e-11, alpha=0.5, dt=1e-14, log_every=1)
+    M = to_dev(8e5 * W.random_unit(8, 8, 1, seed=5))
+    recs = plan.step_stats(p, M, 600)
+    assert [r["steps"] for r in recs] == list(range(1, 601))
+    E = np.array([r["E_tot"] for r in recs])
+    assert np.all(np.diff(E) <= 1e-6 * np.abs(E[:-1]))
+
+
+def test_nonfinite_record_is_reported():
+    from paper_1406_7459_amd import mm
+    plan = mm.Plan(8, 8, 2, 2e-9, 2e-9, 2e-9)
+    p = mm.LLGParams.make(Ms=8e5, A=1.3e-11)
+    M = to_dev(8e5 * W.random_unit(8, 8, 2, 3))
+    M[0, 1, 2, 3] = float("nan")
+    with pytest.raises(mm.MMError) as ei:
+        plan.step_stats(p, M, 2)
+    assert ei.value.code == mm.MM_ENONFINITE
+
+
+def test_surrogate_mode_through_llg_step():
+    """mm_sur_attach + demag_mode MM_SURROGATE: at sur_tol = 0 every step
+    that tries the surrogate is redone exactly (and the next step skips it),
+    so the state equals the exact path bitwise and 5 steps count 3
+    fallbacks; without an attached network the mode is rejected."""
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 32, 16, 2
+    d = (4e-9, 4e-9, 4e-9)
+    mat = W.Material(Ms=8e5, A=1.3e-11, Ku=0.0, axis=(1, 0, 0), alpha=0.1, Hext=(1e4, 0, 0))
+    plan = mm.Plan(nx, ny, nz, *d)
+    M0 = to_dev(mat.Ms * W.random_unit(nx, ny, nz, seed=6))
+    ps = _params(mm, mat, demag="surrogate", sur_tol=0.0)
+    with pytest.raises(mm.MMError) as ei:
+        plan.step(ps, M0.clone(), 1)
+    assert ei.value.code == mm.MM_EINVAL
+    sur = mm.Surrogate(nx, ny, nz)
+    sur.attach(plan)
+    a = M0.clone()
+    (r,) = plan.step_stats(ps, a, 5)
+    b = M0.clone()
+    for _ in range(5):
+        plan.step(_params(mm, mat), b, 1)
+    assert np.array_equal(to_host(a), to_host(b))
+    assert r["fallbacks"] == 3 and r["steps"] == 5
+    # a generous gate keeps the surrogate steps (no fallback) and stays close
+    pl = _params(mm, mat, demag="surrogate", sur_tol=-1.0)
+    c = M0.clone()
+    plan.step(pl, c, 3)
+    say("no-network surrogate drift", rel_l2(to_host(c), to_host(b)))
+    assert np.isfinite(to_host(c)).all()
+
+
+def test_batch_workspace_binding():
+    from paper_1406_7459_amd import mm
+    b = mm.Batch([(16, 8, 2), (8, 8, 1)], [(2e-9,) * 3, (4e-9,) * 3])
+    n = C.c_size_t()
+    assert mm.lib().mm_batch_workspace_bytes(b._h, C.byref(n)) == mm.MM_OK
+    assert n.value == b.workspace.numel()
+    ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+    assert mm.lib().mm_batch_bind_workspace(b._h, ws.data_ptr(), n.value - 256) == mm.MM_ENOMEM

@@ -175,12 +175,15 @@ def test_relax_reaches_torque_tolerance_and_lowers_energy():
     assert st["E_tot"] < e0
 
 
-def test_timing_mode_counts_every_kernel_and_matches_untimed():
+@pytest.mark.parametrize("fused", [True, False])
+def test_timing_mode_counts_every_kernel_and_matches_untimed(fused):
     from paper_1406_7459_amd import mm
     nx, ny, nz = 32, 16, 4
     d = (2e-9, 2e-9, 2e-9)
     p = mm.LLGParams.make(Ms=8e5, A=1.3e-11, alpha=0.2, dt=1e-14)
     plan = mm.Plan(nx, ny, nz, *d)
+    if not fused:
+        plan.set_tile("xstage", 0)
     M0 = to_dev(8e5 * W.random_unit(nx, ny, nz, 12))
     a = M0.clone()
     plan.step(p, a, 10)
@@ -191,9 +194,51 @@ def test_timing_mode_counts_every_kernel_and_matches_untimed():
     t = plan.timing()
     plan.set_timing(False)
     assert np.array_equal(to_host(a), to_host(b))
-    for k in ("xfwd", "yfwd", "zconv", "yinv", "xinv", "stage"):
-        assert t[k][1] == 40, (k, t[k])   # 10 steps x 4 stages
-        assert t[k][0] > 0.0
+    if fused:
+        expect = dict(xfwd=10, yfwd=40, zconv=40, yinv=40, xstage=40, xinv=0, stage=0)
+    else:
+        expect = dict(xfwd=40, yfwd=40, zconv=40, yinv=40, xinv=40, stage=40, xstage=0)
+    for k, n in expect.items():
+        assert t[k][1] == n, (k, t[k])
+        assert (t[k][0] > 0.0) == (n > 0)
+
+
+FUSED_GRIDS = [(24, 12, 3), (6, 3, 3), (32, 16, 1), (64, 32, 8), (16, 8, 2), (3, 4, 6), (1, 1, 1), (48, 24, 12)]
+
+
+@pytest.mark.parametrize("integrator", ["rk4", "euler"])
+@pytest.mark.parametrize("grid", FUSED_GRIDS)
+def test_fused_stage_pass_is_bitwise_the_unfused_path(grid, integrator):
+    """The fused x-inverse / stage / x-forward pass (every tile) gives
+    bitwise the states of XINV + stage kernel + XFWD, including grids with an
+    odd number of rows per component, films and a single cell; odd and even
+    step counts (Euler pairs and the copying single step)."""
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = grid
+    mat = W.Material(Ms=8e5, A=1.3e-11, Ku=2e4, axis=(0.6, 0.0, 0.8), alpha=0.3, Hext=(1e4, -5e3, 2e4))
+    pg, _ = _params(mm, mat, integrator=integrator)
+    plan = mm.Plan(nx, ny, nz, 4e-9, 4e-9, 2e-9)
+    assert plan.info()["tiles"]["xstage"] > 0  # fused by default
+    M0 = to_dev(mat.Ms * W.random_unit(nx, ny, nz, seed=34))
+    plan.set_tile("xstage", 0)
+    ref = {}
+    for n in (1, 2, 5):
+        M = M0.clone()
+        plan.step(pg, M, n)
+        ref[n] = to_host(M)
+    tiles = []
+    for P in (1, 2, 4, 8, 16, 32, 64):
+        try:
+            plan.set_tile("xstage", P)
+        except mm.MMError:
+            continue
+        tiles.append(P)
+        for n in (1, 2, 5):
+            M = M0.clone()
+            plan.step(pg, M, n)
+            assert np.array_equal(to_host(M), ref[n]), (P, n)
+    say("fused tiles", grid, tiles)
+    assert tiles
 
 
 @pytest.mark.parametrize("integrator", ["rk4", "euler"])
