@@ -153,6 +153,20 @@ int mm_plan_bind_workspace(mm_plan plan, void *ws_dev, size_t bytes);
  * Errors: MM_EINVAL (NULL plan/pointer, M == H, no workspace bound), MM_EHIP. */
 int mm_demag_apply(mm_plan plan, const float *M_dev, float *H_dev, void *stream);
 
+/* For callers that cannot allocate device memory at all (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * mm_demag_apply with its half-spectrum buffers (X1 and X2 above) in a
+ * fixed device array of the library, mm_demag_static_scratch_bytes() = 64
+ * MiB on each GPU it runs on (held until the process ends), instead of the
+ * plan's workspace; the plan still supplies K~ and the twiddles.  The
+ * result equals mm_demag_apply's bitwise.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads) race.  Allocates nothing.
+ * Errors: MM_EINVAL (as mm_demag_apply, or a grid whose half spectra exceed
+ * the array), MM_EHIP.                                                      */
+int mm_demag_apply_static(mm_plan plan, const float *M_dev, float *H_dev, void *stream);
+size_t mm_demag_static_scratch_bytes(void);
+
 /* Advance M_dev (in place) by nsteps time steps of eq. (6) under H_eff of
  * eq. (2), with classical RK4 (four demag evaluations per step) or explicit
  * Euler (one); params->demag_mode MM_SURROGATE takes the attached learned

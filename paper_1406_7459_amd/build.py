@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmm.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "demag.hip", "tensor.hip", "llg.hip", "xstage.hip", "batch.hip", "surrogate.hip"]
+SOURCES = ["api.hip", "demag.hip", "tensor.hip", "llg.hip", "xstage.hip", "batch.hip", "surrogate.hip",
+           "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

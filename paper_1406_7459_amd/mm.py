@@ -24,7 +24,8 @@ PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv", "stage", "reduce", "
 NPASS = len(PASSES)
 PASS_INDEX = {n: i for i, n in enumerate(PASSES)}
 
-SYMBOLS = ("mm_demag_setup", "mm_plan_workspace_bytes", "mm_plan_bind_workspace", "mm_demag_apply", "mm_llg_step", "mm_reduce", "mm_llg_relax",
+SYMBOLS = ("mm_demag_setup", "mm_plan_workspace_bytes", "mm_plan_bind_workspace", "mm_demag_apply",
+           "mm_demag_apply_static", "mm_demag_static_scratch_bytes", "mm_llg_step", "mm_reduce", "mm_llg_relax",
            "mm_newell_tensor",
            "mm_plan_spectrum", "mm_plan_query", "mm_plan_set_tile", "mm_plan_autotune",
            "mm_plan_set_timing", "mm_plan_timing", "mm_destroy", "mm_status_string",
@@ -118,6 +119,8 @@ def lib():
     L.mm_plan_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
     L.mm_plan_bind_workspace.argtypes = [vp, vp, sz]
     L.mm_demag_apply.argtypes = [vp, vp, vp, vp]
+    L.mm_demag_apply_static.argtypes = [vp, vp, vp, vp]
+    L.mm_demag_static_scratch_bytes.argtypes = []
     L.mm_llg_step.argtypes = [vp, C.POINTER(LLGParams), vp, i, C.POINTER(Stats), vp]
     L.mm_reduce.argtypes = [vp, C.POINTER(LLGParams), vp, C.POINTER(Stats), vp]
     L.mm_llg_relax.argtypes = [vp, C.POINTER(LLGParams), vp, d, ll, i, C.POINTER(Stats),
@@ -162,8 +165,10 @@ def lib():
     L.mm_status_string.restype = C.c_char_p
     L.mm_last_error.argtypes = [C.c_char_p, C.c_size_t]
     for name in SYMBOLS:
-        if name not in ("mm_destroy", "mm_status_string", "mm_batch_destroy", "mm_sur_destroy"):
+        if name not in ("mm_destroy", "mm_status_string", "mm_batch_destroy", "mm_sur_destroy",
+                        "mm_demag_static_scratch_bytes"):
             getattr(L, name).restype = C.c_int
+    L.mm_demag_static_scratch_bytes.restype = C.c_size_t
     L.mm_sur_param_count.restype = ll
     _lib = L
     return L
