@@ -532,6 +532,33 @@ def table1_euler(torch, mm, W):
     return out
 
 
+def relax_sweep(torch, mm, W, sizes=(8, 16, 32, 64), tol=1e3, max_steps=40000, check_every=250):
+    """The structure of the paper's cube benchmark (relaxation of N^3 cubes
+    with uniaxial anisotropy to the minimum-energy state): mm_llg_relax on
+    cubes of the cube workload's material with alpha 1, from a random state,
+    until max |M x H_eff| / Ms <= tol; steps, time and final observables."""
+    out = []
+    for n in sizes:
+        wl = W.cube(n)
+        m = wl.mat
+        plan = mm.Plan(n, n, n, *wl.cell)
+        p = mm.LLGParams.make(Ms=m.Ms, A=m.A, Ku=m.Ku, axis=m.axis, alpha=1.0, gamma0=m.gamma0,
+                              dt=m.dt)
+        M = torch.from_numpy((m.Ms * wl.initial_unit()).astype("float32")).cuda()
+        e0 = plan.reduce(p, M)["E_tot"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = plan.relax(p, M, torque_tol=tol, max_steps=max_steps, check_every=check_every)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out.append({"N": n, "steps": st["steps"], "seconds": el, "converged": st["torque_max"] <= tol,
+                    "torque_max_A_per_m": st["torque_max"], "E_start_J": e0, "E_final_J": st["E_tot"],
+                    "m_avg": st["m_avg"]})
+        plan.close()
+    return {"material": "cube workload (Ms 1e6, A 1.5e-11, Ku 5e4 along x, 2 nm cells), alpha 1, dt 1e-14",
+            "torque_tol_A_per_m": tol, "check_every": check_every, "rows": out}
+
+
 def other_configs(torch, mm, W):
     """RK4 step and isolated demag times of the other grid sizes of the
     throughput table (64^3 and 256^3 cubes) and of the learned-form film
@@ -794,6 +821,7 @@ def main():
         "note": "paper Table 1 (Euler, FP32, AMD HD 7970): other hardware, context only"}
     if not args.no_other_configs:
         out["other_configs"] = other_configs(torch, mm, W)
+        out["relax_sweep"] = relax_sweep(torch, mm, W)
     if not args.no_batch:
         out["batched"] = batch_measure(torch, mm, W)
     if not args.no_surrogate:

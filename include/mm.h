@@ -103,8 +103,8 @@ typedef struct {
 /* Plan description filled by mm_plan_query. */
 typedef struct {
     int nx, ny, nz;
-    int Lx, Ly, Lz;            /* padded FFT lengths 2nx, 2ny, 2nz (Lz = 1 when nz = 1: collapsed) */
-    long long spectrum_count;  /* floats in the stored K~ octant: 6 * (nx+1)(ny+1)(nz+1), nz=1: 6(nx+1)(ny+1) */
+    int Lx, Ly, Lz;            /* padded FFT lengths >= 2nx, 2ny, 2nz (Lz = 1 when nz = 1: collapsed) */
+    long long spectrum_count;  /* floats in the stored K~ octant: 6 (Lx/2+1)(Ly/2+1)(Lz/2+1), nz=1: 6(Lx/2+1)(Ly/2+1) */
     long long workspace_bytes; /* device bytes the plan works in (mm_plan_workspace_bytes) */
     int cfg[9];                /* launch tile per pass kind (see MM_PASS_*) */
 } mm_plan_info;
@@ -127,8 +127,11 @@ enum {
  * cell labelling and eq. (7)-(12)): sizes, padded transform lengths, launch
  * configuration and the workspace it needs.  Allocates no device memory;
  * the plan computes nothing until a workspace is bound.
- * Supported n per axis: 2^a or 3*2^a, 1 <= n <= 512 (padded lengths 2n of
- * 2, 4, 6, 8, 12, 16, 24, ..., 512, 768, 1024: radices 2, 3, 4, 8).
+ * Any 1 <= n <= 512 per axis: each axis is padded to the smallest transform
+ * length L >= 2n of 2, 4, 6, 8, 12, 16, 24, ..., 512, 768, 1024 (radices 2,
+ * 3, 4, 8); the zero-padded convolution needs L >= 2n - 1 (Sec. 2 zero
+ * padding), so L = 2n exactly when n is 2^a or 3*2^a and the result is the
+ * same convolution for any L (mm_plan_info reports Lx, Ly, Lz).
  * Errors: MM_EINVAL (bad sizes), MM_ENODEV, MM_EHIP.                        */
 int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_plan *out);
 
@@ -211,9 +214,9 @@ int mm_llg_relax(mm_plan plan, const mm_llg_params *params, float *M_dev, double
 int mm_newell_tensor(int nx, int ny, int nz, double dx, double dy, double dz, double *N_dev,
                      void *stream);
 
-/* Copy the plan's stored K~ octant (FP32, [nzK][ny+1][nx+1][6] with the six
- * components xx, yy, zz, xy, xz, yz per frequency, nzK = nz+1, or 1 when
- * nz = 1; scale and sign folded in) to Kt_dev, which holds
+/* Copy the plan's stored K~ octant (FP32, [nzK][Ly/2+1][Lx/2+1][6] with the
+ * six components xx, yy, zz, xy, xz, yz per frequency, nzK = Lz/2+1, or 1
+ * when nz = 1; scale and sign folded in) to Kt_dev, which holds
  * `count` floats (>= mm_plan_info.spectrum_count).  Asynchronous.           */
 int mm_plan_spectrum(mm_plan plan, float *Kt_dev, long long count, void *stream);
 

@@ -67,6 +67,47 @@ def loss_and_grads(params, dm, dh):
     return loss.item(), [(w.grad.clone(), b.grad.clone()) for w, b in ps]
 
 
+def gelu_prime(x: torch.Tensor) -> torch.Tensor:
+    """Derivative of the tanh-form GELU: with u = sqrt(2/pi) (x + 0.044715
+    x^3), d/dx [x/2 (1 + tanh u)] = (1 + tanh u)/2 + x/2 (1 - tanh^2 u) du/dx."""
+    c = math.sqrt(2.0 / math.pi)
+    t = torch.tanh(c * (x + 0.044715 * x ** 3))
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * c * (1.0 + 3 * 0.044715 * x * x)
+
+
+def loss_and_grads_rounded(params, dm, dh, rnd=None):
+    """MSE loss and gradients by an explicit backward pass (chain rule
+    written out layer by layer), with a rounding `rnd` applied where the
+    half-precision matrix-core path stores a tensor: the network input and
+    every layer input, every hidden pre-activation as the argument of the
+    GELU derivative, and every back-propagated pre-activation gradient dZ.
+    Arithmetic is FP64.  rnd = None is the exact backward (it must equal
+    loss_and_grads)."""
+    r = rnd if rnd is not None else (lambda t: t)
+    n = len(params)
+    X = [r(dm)]
+    Zs = []
+    for li, (w, b) in enumerate(params):
+        z = conv3(X[-1], w, b)
+        Zs.append(z)
+        if li < n - 1:
+            X.append(r(gelu(z)))
+    out = Zs[-1]
+    loss = mse(out, dh)
+    dz = r(2.0 * (out - dh) / out.numel())
+    grads = [None] * n
+    for li in range(n - 1, -1, -1):
+        w, b = params[li]
+        x = X[li]
+        # dL/dw[co][ci][a][b][c] = sum over cells of dz[co] x[ci] at the tap's source
+        gw = torch.nn.grad.conv3d_weight(x[None], w.shape, dz[None], padding=1)
+        grads[li] = (gw, dz.sum(dim=(1, 2, 3)))
+        if li > 0:
+            dx = torch.nn.grad.conv3d_input(x[None].shape, w, dz[None], padding=1)[0]
+            dz = r(dx * gelu_prime(r(Zs[li - 1])))
+    return loss.item(), grads
+
+
 def init_params(seed: int, channels=CHANNELS):
     """He-style uniform initialisation, biases zero (seeded)."""
     g = np.random.Generator(np.random.PCG64(seed))

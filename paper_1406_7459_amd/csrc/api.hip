@@ -21,6 +21,7 @@ int fail(int code, const std::string &msg)
 }
 
 bool length_supported(int L);
+int padded_length(int n);
 
 // ------------------------------------------------------------------ timing ---
 static hipEvent_t take_event(Plan &p)
@@ -123,12 +124,12 @@ static void free_plan(PlanOwner *o)
     delete o;
 }
 
-static bool axis_ok(int n) { return n >= 1 && n <= 512 && length_supported(2 * n); }
+static bool axis_ok(int n) { return n >= 1 && n <= 512 && padded_length(n) > 0; }
 
 static int check_grid(int nx, int ny, int nz, double dx, double dy, double dz)
 {
     if (!axis_ok(nx) || !axis_ok(ny) || !axis_ok(nz))
-        return fail(MM_EINVAL, "grid sizes must be 2^a or 3*2^a, 1..512");
+        return fail(MM_EINVAL, "grid sizes must be 1..512 cells per axis");
     if (!(dx > 0.0) || !(dy > 0.0) || !(dz > 0.0) || !std::isfinite(dx) || !std::isfinite(dy) ||
         !std::isfinite(dz))
         return fail(MM_EINVAL, "cell sizes must be finite and > 0");
@@ -144,9 +145,9 @@ size_t plan_layout(Plan &p, char *base)
 {
     const size_t N = (size_t)p.nx * p.ny * p.nz;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const size_t szK = sizeof(float) * 6 * (size_t)p.nzK * (ny + 1) * p.xp;
+    const size_t szK = sizeof(float) * 6 * (size_t)p.nzK * (p.Ly / 2 + 1) * p.xp;
     const size_t szX1 = sizeof(float2) * 3 * (size_t)nz * ny * p.xp;
-    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * 2 * ny * p.xp : 0;
+    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * p.Ly * p.xp : 0;
     const size_t szF = sizeof(float) * 3 * N;
     const size_t szPart = sizeof(double) * 9 * (size_t)p.red_blocks;
     const size_t szRed = sizeof(double) * 16 * (size_t)RED_LOG;
@@ -155,7 +156,7 @@ size_t plan_layout(Plan &p, char *base)
     const int Ls[3] = {p.Lx, p.Ly, nz > 1 ? p.Lz : 0};
     for (int a = 0; a < 3; ++a) tw += Ls[a] ? al(sizeof(float2) * (size_t)Ls[a]) : 0;
     const size_t run = al(szX1) + al(szX2) + 4 * al(szF);
-    const size_t scratch = al(spectrum_scratch_bytes(nx, ny, nz));
+    const size_t scratch = al(spectrum_scratch_bytes(nx, ny, nz, p.Lx, p.Ly, p.Lz));
     const size_t total = al(szK) + tw + al(szPart) + al(szRed) + (run > scratch ? run : scratch);
     if (!base) return total;
     char *cur = base;
@@ -244,10 +245,11 @@ int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_p
     Plan &p = o->p;
     p.nx = nx; p.ny = ny; p.nz = nz;
     p.dx = dx; p.dy = dy; p.dz = dz;
-    p.Lx = 2 * nx; p.Ly = 2 * ny; p.Lz = nz > 1 ? 2 * nz : 1;
-    p.nxc = nx + 1;
+    // each axis padded to the smallest supported transform length >= 2n
+    p.Lx = padded_length(nx); p.Ly = padded_length(ny); p.Lz = nz > 1 ? padded_length(nz) : 1;
+    p.nxc = p.Lx / 2 + 1;
     p.xp = x_pitch(p.nxc);
-    p.nzK = nz > 1 ? nz + 1 : 1;
+    p.nzK = nz > 1 ? p.Lz / 2 + 1 : 1;
     if (hipGetDevice(&p.device) != hipSuccess) {
         free_plan(o);
         return fail(MM_EHIP, "hipGetDevice");
@@ -258,7 +260,7 @@ int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_p
         if (p.lds_limit > 160 * 1024) p.lds_limit = 160 * 1024;
         if (p.lds_limit < 32768) p.lds_limit = 32768;
     }
-    p.nK = 6LL * p.nzK * (ny + 1) * (nx + 1);
+    p.nK = 6LL * p.nzK * (p.Ly / 2 + 1) * p.nxc;
     p.red_blocks = 1024;
     p.bytes = plan_layout(p, nullptr);
     const int Ls[3] = {p.Lx, p.Ly, nz > 1 ? p.Lz : 0};
@@ -521,7 +523,7 @@ int mm_plan_spectrum(mm_plan plan, float *Kt, long long count, void *stream)
     if (!Kt) return fail(MM_EINVAL, "NULL Kt");
     if (count < p->nK) return fail(MM_EINVAL, "Kt too small");
     const size_t rec = 6 * sizeof(float);
-    MMK_HIP(hipMemcpy2DAsync(Kt, rec * p->nxc, p->Kt, rec * p->xp, rec * p->nxc, (size_t)p->nzK * (p->ny + 1),
+    MMK_HIP(hipMemcpy2DAsync(Kt, rec * p->nxc, p->Kt, rec * p->xp, rec * p->nxc, (size_t)p->nzK * (p->Ly / 2 + 1),
                              hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return MM_OK;
 }

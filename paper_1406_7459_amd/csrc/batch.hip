@@ -31,6 +31,7 @@ struct BInst {
     const float *Kt;
     const float2 *tw0, *tw1, *tw2;
     int nx, ny, nz, pad;
+    int Lx, Ly, Lz;  // padded transform lengths (>= 2n; Lz = 1 when nz = 1)
     StageCoef c;
 };
 
@@ -42,14 +43,14 @@ __global__ __launch_bounds__(1024) void kb_xfwd(const BInst *__restrict__ B, con
 {
     const int4 t = T[blockIdx.x];
     const BInst &I = B[t.x];
-    xfwd_body<L, V>(bsel(I, sel), I.X1, I.nz * I.ny, lp2, I.tw0, t.y);
+    xfwd_body<L, V>(bsel(I, sel), I.X1, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void kb_yfwd(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
 {
     const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
-    yfwd_body<L, V>(I.X1, I.X2, I.nx + 1, lp2, I.tw1, t.y, t.z);
+    yfwd_body<L, V>(I.X1, I.X2, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z);
 }
 template <int L, bool Z>
 __global__ __launch_bounds__(conv_max_threads<L>()) void kb_reg3(const BInst *__restrict__ B,
@@ -57,28 +58,30 @@ __global__ __launch_bounds__(conv_max_threads<L>()) void kb_reg3(const BInst *__
 {
     const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
-    conv_reg3_body<L, Z>(Z ? I.X2 : I.X1, I.Kt, I.nx + 1, I.ny, lp2, Z ? I.tw2 : I.tw1, t.y, t.z);
+    conv_reg3_body<L, Z>(Z ? I.X2 : I.X1, I.Kt, I.Lx / 2 + 1, I.Ly / 2, Z ? I.nz : I.ny, lp2, Z ? I.tw2 : I.tw1, t.y,
+                         t.z);
 }
 template <int L, int V, bool Z>
 __global__ __launch_bounds__(1024) void kb_split(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
 {
     const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
-    conv_split_body<L, V, Z>(Z ? I.X2 : I.X1, I.Kt, I.nx + 1, I.ny, lp2, Z ? I.tw2 : I.tw1, t.y, t.z);
+    conv_split_body<L, V, Z>(Z ? I.X2 : I.X1, I.Kt, I.Lx / 2 + 1, I.Ly / 2, Z ? I.nz : I.ny, lp2, Z ? I.tw2 : I.tw1,
+                             t.y, t.z);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void kb_yinv(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
 {
     const int4 t = T[xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
-    yinv_body<L, V>(I.X2, I.X1, I.nx + 1, lp2, I.tw1, t.y, t.z);
+    yinv_body<L, V>(I.X2, I.X1, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void kb_xinv(const BInst *__restrict__ B, const int4 *__restrict__ T, int lp2)
 {
     const int4 t = T[blockIdx.x];
     const BInst &I = B[t.x];
-    xinv_body<L, V>(I.X1, I.Hout, I.nz * I.ny, lp2, I.tw0, t.y);
+    xinv_body<L, V>(I.X1, I.Hout, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
 }
 template <int STAGE>
 __global__ __launch_bounds__(256) void kb_stage(const BInst *__restrict__ B, const int2 *__restrict__ T, int ssel,
@@ -132,11 +135,11 @@ static int pass_len_of(const BInst &I, int pass)
 {
     switch (pass) {
     case MM_PASS_XFWD:
-    case MM_PASS_XINV: return 2 * I.nx;
+    case MM_PASS_XINV: return I.Lx;
     case MM_PASS_YFWD:
-    case MM_PASS_YINV: return I.nz > 1 ? 2 * I.ny : 0;
-    case MM_PASS_ZCONV: return I.nz > 1 ? 2 * I.nz : 0;
-    case MM_PASS_YCONV: return I.nz == 1 ? 2 * I.ny : 0;
+    case MM_PASS_YINV: return I.nz > 1 ? I.Ly : 0;
+    case MM_PASS_ZCONV: return I.nz > 1 ? I.Lz : 0;
+    case MM_PASS_YCONV: return I.nz == 1 ? I.Ly : 0;
     default: return 0;
     }
 }
@@ -150,7 +153,7 @@ static void make_tasks(const BatchImpl &b, const BGroup &g, int tile, std::vecto
     for (int i = 0; i < b.count; ++i) {
         const BInst &I = b.inst[i];
         if (pass_len_of(I, g.pass) != g.L) continue;
-        const int nxc = I.nx + 1, ncr = I.nz * I.ny;
+        const int nxc = I.Lx / 2 + 1, ncr = I.nz * I.ny;
         switch (g.pass) {
         case MM_PASS_XFWD:
         case MM_PASS_XINV: {
@@ -164,9 +167,10 @@ static void make_tasks(const BatchImpl &b, const BGroup &g, int tile, std::vecto
                 for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) tasks.push_back(make_int4(i, bx, pl, 0));
             break;
         case MM_PASS_ZCONV:  // the two rows of a mirror pair next to each other, then the tile
-            for (int m = 0; m < I.ny; ++m)
+            for (int m = 0; m < I.Ly / 2; ++m)
                 for (int bx = 0; bx < (nxc + P - 1) / P; ++bx)
-                    for (int h = 0; h < 2; ++h) tasks.push_back(make_int4(i, bx, ky_of_slot(2 * m + h, I.ny), 0));
+                    for (int h = 0; h < 2; ++h)
+                        tasks.push_back(make_int4(i, bx, ky_of_slot(2 * m + h, I.Ly / 2), 0));
             break;
         case MM_PASS_YCONV:
             for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) tasks.push_back(make_int4(i, bx, 0, 0));
@@ -358,6 +362,7 @@ int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const
         if (p.lds_limit < b->lds_limit) b->lds_limit = p.lds_limit;
         BInst I{};
         I.nx = p.nx; I.ny = p.ny; I.nz = p.nz;
+        I.Lx = p.Lx; I.Ly = p.Ly; I.Lz = p.Lz;
         b->inst.push_back(I);
         const size_t n = (size_t)p.cells();
         for (size_t blk = 0; blk < (n + 255) / 256; ++blk) b->stage_tasks.push_back(make_int2(i, (int)blk));

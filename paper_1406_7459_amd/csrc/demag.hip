@@ -18,62 +18,63 @@ __device__ __forceinline__ void column_coords(int &bx, int &plane)
     bx = (int)(l % nt);
     plane = (int)(l / nt);
 }
-__device__ __forceinline__ void conv_coords(int ny, int &bx, int &ky)
+__device__ __forceinline__ void conv_coords(int hy, int &bx, int &ky)
 {
-    const unsigned nt = gridDim.x, nb = nt * gridDim.y;  // gridDim.y = 2 ny slots
+    const unsigned nt = gridDim.x, nb = nt * gridDim.y;  // gridDim.y = Ly = 2 hy slots
     const unsigned l = xcd_block(blockIdx.y * nt + blockIdx.x, nb);
     const unsigned r = l >> 1;
     bx = (int)(r % nt);
-    ky = ky_of_slot((int)(2 * (r / nt) + (l & 1)), ny);
+    ky = ky_of_slot((int)(2 * (r / nt) + (l & 1)), hy);
 }
 
 // Per-plan kernels: one launch covers one pass of one grid.
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_xfwd(const float *__restrict__ M, float2 *__restrict__ X1, int ncr,
-                                               int lp2, const float2 *__restrict__ tw)
+                                               int nx, int lp2, const float2 *__restrict__ tw)
 {
-    xfwd_body<L, V>(M, X1, ncr, lp2, tw, blockIdx.x);
+    xfwd_body<L, V>(M, X1, ncr, nx, lp2, tw, blockIdx.x);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yfwd(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc,
-                                               int lp2, const float2 *__restrict__ tw)
+                                               int ny, int lp2, const float2 *__restrict__ tw)
 {
     int bx, plane;
     column_coords(bx, plane);
-    yfwd_body<L, V>(X1, X2, nxc, lp2, tw, bx, plane);
+    yfwd_body<L, V>(X1, X2, nxc, ny, lp2, tw, bx, plane);
 }
 template <int L, bool ZAXIS>
 __global__ __launch_bounds__(conv_max_threads<L>()) void k_conv_reg3(float2 *__restrict__ X,
-                                                                      const float *__restrict__ Kt, int nxc, int ny,
-                                                                      int lp2, const float2 *__restrict__ tw)
+                                                                      const float *__restrict__ Kt, int nxc, int hy,
+                                                                      int nlive, int lp2,
+                                                                      const float2 *__restrict__ tw)
 {
     int bx, ky = 0;
-    if constexpr (ZAXIS) conv_coords(ny, bx, ky);
+    if constexpr (ZAXIS) conv_coords(hy, bx, ky);
     else bx = (int)xcd_block(blockIdx.x, gridDim.x);
-    conv_reg3_body<L, ZAXIS>(X, Kt, nxc, ny, lp2, tw, bx, ky);
+    conv_reg3_body<L, ZAXIS>(X, Kt, nxc, hy, nlive, lp2, tw, bx, ky);
 }
 template <int L, int V, bool ZAXIS>
 __global__ __launch_bounds__(1024) void k_conv_split(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc,
-                                                      int ny, int lp2, const float2 *__restrict__ tw)
+                                                      int hy, int nlive, int lp2, const float2 *__restrict__ tw)
 {
     int bx, ky = 0;
-    if constexpr (ZAXIS) conv_coords(ny, bx, ky);
+    if constexpr (ZAXIS) conv_coords(hy, bx, ky);
     else bx = (int)xcd_block(blockIdx.x, gridDim.x);
-    conv_split_body<L, V, ZAXIS>(X, Kt, nxc, ny, lp2, tw, bx, ky);
+    conv_split_body<L, V, ZAXIS>(X, Kt, nxc, hy, nlive, lp2, tw, bx, ky);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yinv(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc,
-                                               int lp2, const float2 *__restrict__ tw)
+                                               int ny, int lp2, const float2 *__restrict__ tw)
 {
     int bx, plane;
     column_coords(bx, plane);
-    yinv_body<L, V>(X2, X1, nxc, lp2, tw, bx, plane);
+    yinv_body<L, V>(X2, X1, nxc, ny, lp2, tw, bx, plane);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_xinv(const float2 *__restrict__ X1, float *__restrict__ H, int ncr,
-                                               int lp2, const float2 *__restrict__ tw)
+                                               int nx, int lp2, const float2 *__restrict__ tw)
 {
-    xinv_body<L, V>(X1, H, ncr, lp2, tw, blockIdx.x);
+    xinv_body<L, V>(X1, H, ncr, nx, lp2, tw, blockIdx.x);
 }
 
 // --------------------------------------------------------------- dispatch ---
@@ -119,6 +120,17 @@ bool length_supported(int L)
 {
     KInfo k;
     return kinfo_for(L, k);
+}
+
+// Padded transform length of an axis of n cells: the smallest supported
+// length >= 2n (the zero-padded convolution needs at least 2n - 1); 0 if
+// none (n > 512).
+int padded_length(int n)
+{
+    static const int lens[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+    for (int L : lens)
+        if (L >= 2 * n) return L;
+    return 0;
 }
 
 static int pass_length(const Plan &p, int pass)
@@ -310,19 +322,19 @@ static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, 
     const int pairs = 3 * ((ncr + 1) / 2);
     switch (pass) {
     case MM_PASS_XFWD: {
-        MMK_LAUNCH(p, (k_xfwd<L, V>), dim3((pairs + P - 1) / P), block, lds, s, M, p.X1, ncr, lp2, p.tw[0]);
+        MMK_LAUNCH(p, (k_xfwd<L, V>), dim3((pairs + P - 1) / P), block, lds, s, M, p.X1, ncr, p.nx, lp2, p.tw[0]);
         break;
     }
     case MM_PASS_YFWD:
-        MMK_LAUNCH(p, (k_yfwd<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X1, p.X2, nxc, lp2,
+        MMK_LAUNCH(p, (k_yfwd<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X1, p.X2, nxc, p.ny, lp2,
                            p.tw[1]);
         break;
     case MM_PASS_YINV:
-        MMK_LAUNCH(p, (k_yinv<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X2, p.X1, nxc, lp2,
+        MMK_LAUNCH(p, (k_yinv<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X2, p.X1, nxc, p.ny, lp2,
                            p.tw[1]);
         break;
     case MM_PASS_XINV: {
-        MMK_LAUNCH(p, (k_xinv<L, V>), dim3((pairs + P - 1) / P), block, lds, s, p.X1, H, ncr, lp2, p.tw[0]);
+        MMK_LAUNCH(p, (k_xinv<L, V>), dim3((pairs + P - 1) / P), block, lds, s, p.X1, H, ncr, p.nx, lp2, p.tw[0]);
         break;
     }
     default: break;
@@ -337,19 +349,20 @@ static void launch_conv(Plan &p, int pass, int P, int var, size_t lds, hipStream
     const bool z = pass == MM_PASS_ZCONV;
     float2 *X = z ? p.X2 : p.X1;
     const float2 *tw = z ? p.tw[2] : p.tw[1];
-    const dim3 grid((nxc + P - 1) / P, z ? 2 * p.ny : 1);
+    const dim3 grid((nxc + P - 1) / P, z ? p.Ly : 1);
+    const int hy = p.Ly / 2, nl = z ? p.nz : p.ny;
     if (var == 0) {
         const dim3 block(P * (L / Factors<L>::E));
-        if (z) MMK_LAUNCH(p, (k_conv_reg3<L, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
-        else MMK_LAUNCH(p, (k_conv_reg3<L, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_reg3<L, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        else MMK_LAUNCH(p, (k_conv_reg3<L, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
     } else if (var == 1) {
         const dim3 block(3 * P * (L / ept<L, 0>()));
-        if (z) MMK_LAUNCH(p, (k_conv_split<L, 0, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
-        else MMK_LAUNCH(p, (k_conv_split<L, 0, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_split<L, 0, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        else MMK_LAUNCH(p, (k_conv_split<L, 0, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
     } else {
         const dim3 block(3 * P * (L / ept<L, 1>()));
-        if (z) MMK_LAUNCH(p, (k_conv_split<L, 1, true>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
-        else MMK_LAUNCH(p, (k_conv_split<L, 1, false>), grid, block, lds, s, X, p.Kt, nxc, p.ny, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_split<L, 1, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        else MMK_LAUNCH(p, (k_conv_split<L, 1, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
     }
 }
 

@@ -15,8 +15,11 @@
 //          z inverse, rows k < nz written back
 //   YINV   X2 -> X1                                               y: keep j < ny
 //   XINV   X1 -> H [3][nz][ny][nx] f32                            x: C2R, keep i < nx
-// (xp = x_pitch(nx + 1): rows of nx + 1 values padded to 128 bytes; the
-// padding is never read or written.)
+// (xp = x_pitch(Lx/2 + 1): rows of Lx/2 + 1 values padded to 128 bytes; the
+// padding is never read or written.)  An axis of n cells is padded to a
+// supported transform length L >= 2n (L = 2n when n is 2^a or 3 2^a): the
+// zero-padded convolution only needs L >= 2n - 1, so the live count n is a
+// run-time argument of every body and L a template parameter.
 // For nz = 1 the padded z axis has length 2 with the second slot zero, so the
 // z transform is the identity up to a factor folded into K~; YCONV then does
 // y forward, product and y inverse in one pass (XFWD, YCONV, XINV).
@@ -76,8 +79,8 @@ __device__ __forceinline__ void x_pair_rows(int m, int ncr, int &ra, bool &oka, 
 //   A_k = (Z_k + conj Z_{L-k}) / 2,   B_k = (Z_k - conj Z_{L-k}) / (2i),
 // k = 0..nx; Z_{L-k} is read back through LDS.
 template <int L, int V>
-__device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int ncr, int lp2,
-                                          const float2 *__restrict__ tw, int bx)
+__device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int ncr, int nx,
+                                          int lp2, const float2 *__restrict__ tw, int bx)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
@@ -93,15 +96,15 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
     const LdsView s{lds + tw_slots<L>(), 1, p * XS};
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
-    const float *sa = M + (size_t)ra * NX;
-    const float *sb = M + (size_t)rb * NX;
+    const float *sa = M + (size_t)ra * nx;
+    const float *sb = M + (size_t)rb * nx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int i = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NX;  // compile-time after unrolling
-            const bool in = !upper && i < NX;
+            const bool in = !upper && i < nx;
             v[b * R0 + r] = make_float2(in && oka ? sa[i] : 0.f, in && okb ? sb[i] : 0.f);
         }
     fft_e<L, E, -1, false>(v, s, q, twl);
@@ -132,8 +135,8 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
 
 // y forward on a tile of P kx columns of one (component, z) plane.
 template <int L, int V>
-__device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc, int lp2,
-                                          const float2 *__restrict__ tw, int bx, int plane)
+__device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc, int ny,
+                                          int lp2, const float2 *__restrict__ tw, int bx, int plane)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
     extern __shared__ float2 lds[];
@@ -149,14 +152,14 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
     constexpr int R0 = first_radix<L, false>();
     // this thread's row q; the other rows are compile-time multiples of the
     // (uniform) row pitch away
-    const float2 *src = X1 + ((size_t)plane * NY + q) * xp + kx;
+    const float2 *src = X1 + ((size_t)plane * ny + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const int j = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NY;
-            v[b * R0 + r] = (!upper && ok && j < NY) ? float2(src[(size_t)(Q * b + r * (L / R0)) * xp])
+            v[b * R0 + r] = (!upper && ok && j < ny) ? float2(src[(size_t)(Q * b + r * (L / R0)) * xp])
                                                      : make_float2(0.f, 0.f);
         }
     fft_e<L, E, -1, false>(v, s, q, twl);
@@ -206,8 +209,8 @@ template <int L> constexpr int conv_max_threads() { return Factors<L>::E > 8 ? 2
 // inverse for P kx columns at one ky, in place on X2 (rows k < nz).  Else
 // (nz = 1): the same along y on X1 (rows j < ny), with xz = yz = 0.
 template <int L, bool ZAXIS>
-__device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int ny,
-                                               int lp2, const float2 *__restrict__ tw, int bx, int ky)
+__device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int hy,
+                                               int nlive, int lp2, const float2 *__restrict__ tw, int bx, int ky)
 {
     constexpr int E = Factors<L>::E, Q = L / E, NH = L / 2;
     extern __shared__ float2 lds[];
@@ -221,8 +224,8 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     // two exchange buffers (ping-pong transforms: one barrier per exchange)
     const LdsView s{lds + tw_slots<L>(), P, p};
     const LdsView s1{lds + tw_slots<L>() + lds_rows(L) * P, P, p};
-    const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;  // stride along the transform
-    const size_t cs = (size_t)NH * rs;                            // component stride
+    const size_t rs = ZAXIS ? (size_t)2 * hy * xp : (size_t)xp;  // stride along the transform
+    const size_t cs = (size_t)nlive * rs;                         // component stride
     float2 *base = X + (size_t)ky * xp + kx + (size_t)q * rs;  // this thread's row q
     float2 va[E], vb[E], vc[E];
     constexpr int R0 = first_radix<L, false>();
@@ -233,7 +236,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             const int k = q + Q * b + r * (L / R0);
             const size_t o = (size_t)(Q * b + r * (L / R0)) * rs;  // uniform
             const bool upper = r * (L / R0) >= NH;
-            const bool ld = !upper && ok && k < NH;
+            const bool ld = !upper && ok && k < nlive;
             // (values, not lvalues, on both sides: a select between two
             // lvalues of class type would become a flat load through a
             // selected pointer to either global or private memory)
@@ -246,9 +249,9 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     fft_pp<L, -1, false>(vc, s, s1, q, twl);
 
     constexpr int RL = last_radix<L, false>();
-    const int nyk = ny + 1;
-    const int kyf = ky <= ny ? ky : 2 * ny - ky;
-    const float sy0 = ky <= ny ? 1.f : -1.f;
+    const int nyk = hy + 1;
+    const int kyf = ky <= hy ? ky : 2 * hy - ky;
+    const float sy0 = ky <= hy ? 1.f : -1.f;
     // K~ records of six floats (xx, yy, zz, xy, xz, yz) per octant frequency
     const float2 *Kb = reinterpret_cast<const float2 *>(Kt) +
                        3 * ((ZAXIS ? (size_t)kyf * xp : 0) + (size_t)(ok ? kx : 0));
@@ -284,7 +287,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             const int k = q + Q * b + r * (L / R0);
             const size_t o = (size_t)(Q * b + r * (L / R0)) * rs;
             const bool upper = r * (L / R0) >= NH;
-            if (!upper && ok && k < NH) {
+            if (!upper && ok && k < nlive) {
                 base[o] = va[b * R0 + r];
                 base[cs + o] = vb[b * R0 + r];
                 base[2 * cs + o] = vc[b * R0 + r];
@@ -298,8 +301,8 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
 // reads the other two components at the same frequencies, forms its own row
 // of K~ . M~, and inverse-transforms it.
 template <int L, int V, bool ZAXIS>
-__device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int ny,
-                                                int lp2, const float2 *__restrict__ tw, int bx, int ky)
+__device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int hy,
+                                                int nlive, int lp2, const float2 *__restrict__ tw, int bx, int ky)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NH = L / 2;
     extern __shared__ float2 lds[];
@@ -315,8 +318,8 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     constexpr int GS = lds_rows(L);  // slots per component group
     float2 *buf = lds + tw_slots<L>();
     const LdsView s{buf + (size_t)g * GS * P, P, p};
-    const size_t rs = ZAXIS ? (size_t)2 * ny * xp : (size_t)xp;
-    const size_t cs = (size_t)NH * rs;
+    const size_t rs = ZAXIS ? (size_t)2 * hy * xp : (size_t)xp;
+    const size_t cs = (size_t)nlive * rs;
     float2 *base = X + (size_t)g * cs + (size_t)ky * xp + kx + (size_t)q * rs;
     float2 v[E];
     constexpr int R0 = first_radix<L, false>();
@@ -326,7 +329,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
         for (int r = 0; r < R0; ++r) {
             const int k = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NH;
-            v[b * R0 + r] = (!upper && ok && k < NH) ? float2(base[(size_t)(Q * b + r * (L / R0)) * rs])
+            v[b * R0 + r] = (!upper && ok && k < nlive) ? float2(base[(size_t)(Q * b + r * (L / R0)) * rs])
                                                      : make_float2(0.f, 0.f);
         }
     // this group's row of the symmetric tensor: (xx,xy,xz), (xy,yy,yz), (xz,yz,zz);
@@ -338,9 +341,9 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     const int c0 = g == 0 ? 0 : (g == 1 ? 3 : 4);
     const int c1 = g == 0 ? 3 : (g == 1 ? 1 : 5);
     const int c2 = g == 0 ? 4 : (g == 1 ? 5 : 2);
-    const int nyk = ny + 1;
-    const int kyf = ky <= ny ? ky : 2 * ny - ky;
-    const float sy0 = ky <= ny ? 1.f : -1.f;
+    const int nyk = hy + 1;
+    const int kyf = ky <= hy ? ky : 2 * hy - ky;
+    const float sy0 = ky <= hy ? 1.f : -1.f;
     const float *Kb = Kt + 6 * ((ZAXIS ? (size_t)kyf * xp : 0) + (size_t)(ok ? kx : 0));
     float kr[E][3];
     auto load_k = [&]() {
@@ -395,14 +398,14 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
         for (int r = 0; r < R0; ++r) {
             const int k = q + Q * b + r * (L / R0);
             const bool upper = r * (L / R0) >= NH;
-            if (!upper && ok && k < NH) base[(size_t)(Q * b + r * (L / R0)) * rs] = v[b * R0 + r];
+            if (!upper && ok && k < nlive) base[(size_t)(Q * b + r * (L / R0)) * rs] = v[b * R0 + r];
         }
 }
 
 // y inverse on a tile of P kx columns of one (component, z) plane, keep j < ny.
 template <int L, int V>
-__device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc, int lp2,
-                                          const float2 *__restrict__ tw, int bx, int plane)
+__device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc, int ny,
+                                          int lp2, const float2 *__restrict__ tw, int bx, int plane)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
     extern __shared__ float2 lds[];
@@ -424,14 +427,14 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
             v[b * R0 + r] = ok ? float2(src[(size_t)(Q * b + r * (L / R0)) * xp]) : make_float2(0.f, 0.f);
     fft_e<L, E, +1, false>(v, s, q, twl);
     constexpr int RL = last_radix<L, false>();
-    float2 *dst = X1 + ((size_t)plane * NY + q) * xp + kx;
+    float2 *dst = X1 + ((size_t)plane * ny + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int j = q + Q * b + r * (L / RL);
             const bool upper = r * (L / RL) >= NY;
-            if (!upper && ok && j < NY) dst[(size_t)(Q * b + r * (L / RL)) * xp] = v[b * RL + r];
+            if (!upper && ok && j < ny) dst[(size_t)(Q * b + r * (L / RL)) * xp] = v[b * RL + r];
         }
 }
 
@@ -439,8 +442,8 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
 // the Hermitian half-spectra of rows 2m and 2m+1; Re/Im of the inverse are
 // the two real rows.  Keep i < nx.
 template <int L, int V>
-__device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *__restrict__ H, int ncr, int lp2,
-                                          const float2 *__restrict__ tw, int bx)
+__device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *__restrict__ H, int ncr, int nx,
+                                          int lp2, const float2 *__restrict__ tw, int bx)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
@@ -477,15 +480,15 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
         }
     fft_e<L, E, +1, false>(v, s, q, twl);
     constexpr int RL = last_radix<L, false>();
-    float *da = H + (size_t)ra * NX;
-    float *db = H + (size_t)rb * NX;
+    float *da = H + (size_t)ra * nx;
+    float *db = H + (size_t)rb * nx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
         for (int r = 0; r < RL; ++r) {
             const int i = q + Q * b + r * (L / RL);
             const bool upper = r * (L / RL) >= NX;
-            if (!upper && i < NX) {
+            if (!upper && i < nx) {
                 if (oka) da[i] = v[b * RL + r].x;
                 if (okb) db[i] = v[b * RL + r].y;
             }

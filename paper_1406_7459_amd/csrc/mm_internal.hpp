@@ -66,17 +66,17 @@ struct GraphCache {
 struct Plan {
     int nx = 0, ny = 0, nz = 0;
     double dx = 0, dy = 0, dz = 0;
-    int Lx = 0, Ly = 0, Lz = 0;  // Lz = 1 when nz == 1 (z collapsed)
-    int nxc = 0;                 // nx + 1
+    int Lx = 0, Ly = 0, Lz = 0;  // padded lengths (>= 2n); Lz = 1 when nz == 1 (z collapsed)
+    int nxc = 0;                 // Lx/2 + 1 half-spectrum columns
     int xp = 0;                  // x_pitch(nxc): row pitch of X1, X2 and K~
-    int nzK = 0;                 // octant depth of K~: nz + 1, or 1 when nz == 1
+    int nzK = 0;                 // octant depth of K~: Lz/2 + 1, or 1 when nz == 1
     int device = 0;
     size_t lds_limit = 65536;
 
-    float *Kt = nullptr;         // [nzK][ny+1][xp][6], kx < nx + 1 used
-    long long nK = 0;            // 6 nzK (ny+1) (nx+1): the exported (unpadded) count
+    float *Kt = nullptr;         // [nzK][Ly/2+1][xp][6], kx < nxc used
+    long long nK = 0;            // 6 nzK (Ly/2+1) nxc: the exported (unpadded) count
     float2 *X1 = nullptr;        // [3][nz][ny][xp]
-    float2 *X2 = nullptr;        // [3][nz][2ny][xp] (nz > 1 only)
+    float2 *X2 = nullptr;        // [3][nz][Ly][xp] (nz > 1 only)
     float *H = nullptr;          // [3][N] demag field scratch for the step driver
     float *Sa = nullptr, *Sb = nullptr, *kacc = nullptr;  // stage states and RK4 accumulator
     double *part = nullptr;      // reduction partials
@@ -111,7 +111,7 @@ int plan_ready(const Plan *p);
 // Carve (base != nullptr) or measure (base == nullptr) the plan workspace.
 size_t plan_layout(Plan &p, char *base);
 // FP64 scratch bytes of the spectrum set-up (tensor.hip).
-size_t spectrum_scratch_bytes(int nx, int ny, int nz);
+size_t spectrum_scratch_bytes(int nx, int ny, int nz, int Lx, int Ly, int Lz);
 
 // Launch configurations by (pass, transform length) (demag.hip).
 bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt);

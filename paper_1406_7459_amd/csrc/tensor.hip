@@ -8,18 +8,19 @@
 //     cell edge, and beyond that from the pair-average of the point-dipole
 //     kernel (tent weight, 4 Gauss-Legendre nodes per half-axis), where the
 //     closed form loses digits to cancellation.
-//  2. The transform of the padded, wrapped K over 2nx x 2ny x 2nz: every
-//     component is even or odd in each axis (N(-r) = N(r) componentwise up
-//     to the sign of the odd axes), so it is real and equals separable
-//     cosine sums (even axes) and sine sums (odd axes) over the octant:
-//       even:  K~(k) = K(0) + 2 sum_{X>=1} K(X) cos(pi k X / n)
-//       odd:   K~(k) = -2i sum_{X>=1} K(X) sin(pi k X / n)
-//     with the spare slot (offset +-n) zero.  Each off-diagonal component is
-//     odd in exactly two axes, so (-i)^2 = -1 makes it real too.  Three
+//  2. The transform of the padded, wrapped K over Lx x Ly x Lz (each L >= 2n;
+//     L = 2n when n is 2^a or 3 2^a): every component is even or odd in each
+//     axis (N(-r) = N(r) componentwise up to the sign of the odd axes), so it
+//     is real and equals separable cosine sums (even axes) and sine sums (odd
+//     axes) over the octant of offsets X < n:
+//       even:  K~(k) = K(0) + 2 sum_{1<=X<n} K(X) cos(2 pi k X / L)
+//       odd:   K~(k) = -2i sum_{1<=X<n} K(X) sin(2 pi k X / L)
+//     with the slots of offsets n .. L-n zero.  Each off-diagonal component
+//     is odd in exactly two axes, so (-i)^2 = -1 makes it real too.  Three
 //     dense FP64 contractions (x, then y, then z) produce the octant
-//     0..n of every axis, which holds the whole spectrum by parity.
-//  3. K~ is scaled by the inverse-transform normalisation 1/(2nx 2ny 2nz)
-//     (for nz = 1 the trivial z axis is dropped and 1/(2nx 2ny) is used),
+//     0..L/2 of every axis, which holds the whole spectrum by parity.
+//  3. K~ is scaled by the inverse-transform normalisation 1/(Lx Ly Lz)
+//     (for nz = 1 the trivial z axis is dropped and 1/(Lx Ly) is used),
 //     rounded once to FP32 and stored as a six-float record per octant
 //     frequency, [kz][ky][kx][xx yy zz xy xz yz]: the spectral product reads
 //     one 24-byte record per frequency.
@@ -166,38 +167,40 @@ __device__ __host__ static inline bool odd_axis(int c, int a)
     return (c == 3 && (a == 0 || a == 1)) || (c == 4 && (a == 0 || a == 2)) || (c == 5 && (a == 1 || a == 2));
 }
 
-// Contract the innermost-but-`stride` axis of length n (octant 0..n-1) to
-// n+1 outputs: out[.., k, ..] = sum_X w(k,X) in[.., X, ..].  Layout: `in` is
-// [6][outer][n][inner], `out` is [6][outer][n+1][inner]; one thread per
+// Contract the innermost-but-`stride` axis of n live offsets (octant
+// 0..n-1) to the L/2 + 1 octant frequencies of the padded length L:
+// out[.., k, ..] = sum_X w(k,X) in[.., X, ..].  Layout: `in` is
+// [6][outer][n][inner], `out` is [6][outer][L/2+1][inner]; one thread per
 // output element.  The trig table for the axis sits in LDS.
-__global__ void k_axis_transform(const double *__restrict__ in, double *__restrict__ out, int n,
+__global__ void k_axis_transform(const double *__restrict__ in, double *__restrict__ out, int n, int L,
                                  long long outer, long long inner, int axis)
 {
-    extern __shared__ double tab[];  // cos then sin of pi m / n, m < 2n
-    for (int m = threadIdx.x; m < 2 * n; m += blockDim.x) {
+    extern __shared__ double tab[];  // cos then sin of 2 pi m / L, m < L
+    for (int m = threadIdx.x; m < L; m += blockDim.x) {
         double sv, cv;
-        sincospi((double)m / (double)n, &sv, &cv);
+        sincospi(2.0 * (double)m / (double)L, &sv, &cv);
         tab[m] = cv;
-        tab[2 * n + m] = sv;
+        tab[L + m] = sv;
     }
     __syncthreads();
-    const long long per_c = outer * (long long)(n + 1) * inner;
+    const int nk = L / 2 + 1;
+    const long long per_c = outer * (long long)nk * inner;
     const long long total = 6 * per_c;
     for (long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x; id < total;
          id += (long long)gridDim.x * blockDim.x) {
         const int c = (int)(id / per_c);
         long long r = id - c * per_c;
-        const long long o = r / ((long long)(n + 1) * inner);
-        r -= o * (long long)(n + 1) * inner;
+        const long long o = r / ((long long)nk * inner);
+        r -= o * (long long)nk * inner;
         const int k = (int)(r / inner);
         const long long e = r - (long long)k * inner;
         const double *src = in + ((long long)c * outer + o) * (long long)n * inner + e;
         double acc = 0.0;
         if (odd_axis(c, axis)) {
-            for (int X = 1; X < n; ++X) acc += 2.0 * tab[2 * n + (int)(((long long)k * X) % (2 * n))] * src[(long long)X * inner];
+            for (int X = 1; X < n; ++X) acc += 2.0 * tab[L + (int)(((long long)k * X) % L)] * src[(long long)X * inner];
         } else {
             acc = src[0];
-            for (int X = 1; X < n; ++X) acc += 2.0 * tab[(int)(((long long)k * X) % (2 * n))] * src[(long long)X * inner];
+            for (int X = 1; X < n; ++X) acc += 2.0 * tab[(int)(((long long)k * X) % L)] * src[(long long)X * inner];
         }
         out[id] = acc;
     }
@@ -233,15 +236,15 @@ int newell_octant_device(int nx, int ny, int nz, double dx, double dy, double dz
     return MM_OK;
 }
 
-static int axis_transform(const double *in, double *out, int n, long long outer, long long inner, int axis,
+static int axis_transform(const double *in, double *out, int n, int L, long long outer, long long inner, int axis,
                           hipStream_t s)
 {
-    const long long total = 6 * outer * (long long)(n + 1) * inner;
+    const long long total = 6 * outer * (long long)(L / 2 + 1) * inner;
     const int bs = 256;
     long long blocks = (total + bs - 1) / bs;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_axis_transform, dim3((unsigned)blocks), dim3(bs), 4 * n * sizeof(double), s, in, out,
-                       n, outer, inner, axis);
+    hipLaunchKernelGGL(k_axis_transform, dim3((unsigned)blocks), dim3(bs), 2 * L * sizeof(double), s, in, out,
+                       n, L, outer, inner, axis);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MM_EHIP, std::string("k_axis_transform: ") + hipGetErrorString(e));
     return MM_OK;
@@ -249,21 +252,22 @@ static int axis_transform(const double *in, double *out, int n, long long outer,
 
 // Two FP64 scratch arrays: A holds the tensor octant and the x-y transform,
 // B the x transform and the z transform.
-static void scratch_sizes(int nx, int ny, int nz, size_t &big, size_t &big2)
+static void scratch_sizes(int nx, int ny, int nz, int Lx, int Ly, int Lz, size_t &big, size_t &big2)
 {
     const size_t n = (size_t)nx * ny * nz;
+    const size_t kx = Lx / 2 + 1, ky = Ly / 2 + 1, kz = nz > 1 ? Lz / 2 + 1 : 1;
     const size_t sz_a = 6 * n;
-    const size_t sz_b = 6 * (size_t)nz * ny * (nx + 1);
-    const size_t sz_c = 6 * (size_t)nz * (ny + 1) * (nx + 1);
-    const size_t sz_d = 6 * (size_t)(nz + 1) * (ny + 1) * (nx + 1);
+    const size_t sz_b = 6 * (size_t)nz * ny * kx;
+    const size_t sz_c = 6 * (size_t)nz * ky * kx;
+    const size_t sz_d = 6 * kz * ky * kx;
     big = sz_a > sz_c ? sz_a : sz_c;
     big2 = sz_b > sz_d ? sz_b : sz_d;
 }
 
-size_t spectrum_scratch_bytes(int nx, int ny, int nz)
+size_t spectrum_scratch_bytes(int nx, int ny, int nz, int Lx, int Ly, int Lz)
 {
     size_t big, big2;
-    scratch_sizes(nx, ny, nz, big, big2);
+    scratch_sizes(nx, ny, nz, Lx, Ly, Lz, big, big2);
     return (((big * sizeof(double)) + 255) & ~(size_t)255) + big2 * sizeof(double);
 }
 
@@ -272,30 +276,31 @@ size_t spectrum_scratch_bytes(int nx, int ny, int nz)
 int build_spectrum(Plan &p, hipStream_t s)
 {
     const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const int kx = p.Lx / 2 + 1, ky = p.Ly / 2 + 1;
     size_t big, big2;
-    scratch_sizes(nx, ny, nz, big, big2);
+    scratch_sizes(nx, ny, nz, p.Lx, p.Ly, p.Lz, big, big2);
     double *A = reinterpret_cast<double *>(p.run);
     double *B = reinterpret_cast<double *>(p.run + (((big * sizeof(double)) + 255) & ~(size_t)255));
     int rc = newell_octant_device(nx, ny, nz, p.dx, p.dy, p.dz, A, s);
-    // x: A[6][nz*ny][nx] -> B[6][nz*ny][nx+1]
-    if (rc == MM_OK) rc = axis_transform(A, B, nx, (long long)nz * ny, 1, 0, s);
-    // y: B[6][nz][ny][nx+1] -> A[6][nz][ny+1][nx+1]
-    if (rc == MM_OK) rc = axis_transform(B, A, ny, nz, nx + 1, 1, s);
+    // x: A[6][nz*ny][nx] -> B[6][nz*ny][kx]
+    if (rc == MM_OK) rc = axis_transform(A, B, nx, p.Lx, (long long)nz * ny, 1, 0, s);
+    // y: B[6][nz][ny][kx] -> A[6][nz][ky][kx]
+    if (rc == MM_OK) rc = axis_transform(B, A, ny, p.Ly, nz, kx, 1, s);
     const double *D = A;
     double scale;
     if (nz > 1) {
-        // z: A[6][nz][(ny+1)(nx+1)] -> B[6][nz+1][(ny+1)(nx+1)]
-        if (rc == MM_OK) rc = axis_transform(A, B, nz, 1, (long long)(ny + 1) * (nx + 1), 2, s);
+        // z: A[6][nz][ky kx] -> B[6][Lz/2+1][ky kx]
+        if (rc == MM_OK) rc = axis_transform(A, B, nz, p.Lz, 1, (long long)ky * kx, 2, s);
         D = B;
-        scale = 1.0 / (8.0 * (double)nx * ny * nz);
+        scale = 1.0 / ((double)p.Lx * p.Ly * p.Lz);
     } else {
-        scale = 1.0 / (4.0 * (double)nx * ny);
+        scale = 1.0 / ((double)p.Lx * p.Ly);
     }
     if (rc == MM_OK) {
-        const long long per_c = (long long)p.nzK * (ny + 1) * (nx + 1);
+        const long long per_c = (long long)p.nzK * ky * kx;
         long long blocks = (6 * per_c + 255) / 256;
         if (blocks > 65536) blocks = 65536;
-        hipLaunchKernelGGL(k_spectrum_store, dim3((unsigned)blocks), dim3(256), 0, s, D, p.Kt, per_c, nx + 1, p.xp, scale,
+        hipLaunchKernelGGL(k_spectrum_store, dim3((unsigned)blocks), dim3(256), 0, s, D, p.Kt, per_c, kx, p.xp, scale,
                            nz == 1 ? 1 : 0);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) rc = fail(MM_EHIP, std::string("k_spectrum_store: ") + hipGetErrorString(e));

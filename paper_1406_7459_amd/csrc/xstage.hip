@@ -5,15 +5,15 @@
 
 namespace mmk {
 
-template <int L, int STAGE, bool FWD>
+template <int L, int STAGE, bool FWD, int W>
 __global__ __launch_bounds__(1024) void k_xstage(float2 *__restrict__ X1, const float *S, const float *Mn,
-                                                 float *__restrict__ kacc, float *out, int ny, int nz, StageCoef c,
-                                                 const float2 *__restrict__ tw, int lp2)
+                                                 float *__restrict__ kacc, float *out, int nx, int ny, int nz,
+                                                 StageCoef c, const float2 *__restrict__ tw, int lp2)
 {
     // each XCD a contiguous range of row blocks: its L2 keeps the +-y and
     // +-z neighbour rows of the stage
     const int bx = (int)xcd_block(blockIdx.x, gridDim.x);
-    xstage_body<L, STAGE, FWD>(X1, S, Mn, kacc, out, ny, nz, c, tw, lp2, bx);
+    xstage_body<L, STAGE, FWD, W>(X1, S, Mn, kacc, out, nx, ny, nz, c, tw, lp2, bx);
 }
 
 #define MMK_XS_LENGTHS(X)                                                                                \
@@ -35,33 +35,42 @@ static bool xs_shape(int L, int P, int &threads, size_t &lds)
     }
 }
 
-// The fused pass's tile is P = 2^k row pairs per workgroup; 0 selects the
-// unfused path (XINV, stage kernel, XFWD).
+// The fused pass's tile is P + 256 w: P = 2^k row pairs per workgroup and
+// the stage phase's cells per thread task W = 1, 2, 4 for w = 0, 1, 2 (nx
+// % W == 0; wider tasks take more registers); 0 selects the unfused path
+// (XINV, stage kernel, XFWD).
+static int xs_w(int tile) { return 1 << (tile >> 8); }
+
 bool xstage_tile_valid(const Plan &p, int tile)
 {
     if (tile == 0) return true;
-    if (tile < 0 || (tile & (tile - 1)) != 0 || tile > 64) return false;
+    const int P = tile & 255, w = tile >> 8;
+    if (tile < 0 || P < 1 || (P & (P - 1)) != 0 || P > 64 || w > 2) return false;
+    if (p.nx % xs_w(tile) != 0) return false;
     int threads;
     size_t lds;
-    if (!xs_shape(p.Lx, tile, threads, lds)) return false;
+    if (!xs_shape(p.Lx, P, threads, lds)) return false;
     return threads <= 1024 && lds <= p.lds_limit;
 }
 
 std::vector<int> xstage_candidates(const Plan &p)
 {
     std::vector<int> out;
-    for (int P = 1; P <= 64; P *= 2) {
-        int threads;
-        size_t lds;
-        if (!xstage_tile_valid(p, P) || !xs_shape(p.Lx, P, threads, lds)) continue;
-        if (threads < 64 && xstage_tile_valid(p, 2 * P)) continue;  // underfilled wave
-        if (P > 1 && P >= p.ny * p.nz) break;                        // the half tile already held every row
-        out.push_back(P);
-    }
+    for (int w = 0; w <= 2; ++w)
+        for (int P = 1; P <= 64; P *= 2) {
+            const int tile = P + 256 * w;
+            int threads;
+            size_t lds;
+            if (!xstage_tile_valid(p, tile) || !xs_shape(p.Lx, P, threads, lds)) continue;
+            if (threads < 64 && xstage_tile_valid(p, 2 * P + 256 * w)) continue;  // underfilled wave
+            if (P > 1 && P >= p.ny * p.nz) break;  // the half tile already held every row
+            out.push_back(tile);
+        }
     return out;
 }
 
-// the largest P with at most 256 threads (at least one pair)
+// one cell per task (the fewest registers), the largest P with at most 256
+// threads (at least one pair)
 int xstage_default_tile(const Plan &p)
 {
     int best = 0;
@@ -74,7 +83,7 @@ int xstage_default_tile(const Plan &p)
     return best;
 }
 
-template <int L, int STAGE, bool FWD>
+template <int L, int STAGE, bool FWD, int W>
 static void xs_launch(Plan &p, int P, const float *S, const float *Mn, float *out, const StageCoef &c, hipStream_t s)
 {
     int lp2 = 0;
@@ -84,24 +93,34 @@ static void xs_launch(Plan &p, int P, const float *S, const float *Mn, float *ou
     const dim3 block((unsigned)(3 * P * (L / Factors<L>::E)));
     const size_t lds = xs_lds_bytes<L>(P);
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_xstage<L, STAGE, FWD>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-    MMK_LAUNCH(p, (k_xstage<L, STAGE, FWD>), grid, block, lds, s, p.X1, S, Mn, p.kacc, out, p.ny, p.nz, c, p.tw[0],
-               lp2);
+        (void)hipFuncSetAttribute((const void *)k_xstage<L, STAGE, FWD, W>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    MMK_LAUNCH(p, (k_xstage<L, STAGE, FWD, W>), grid, block, lds, s, p.X1, S, Mn, p.kacc, out, p.nx, p.ny, p.nz, c,
+               p.tw[0], lp2);
+}
+
+template <int L, int W>
+static int xs_dispatch_w(Plan &p, int P, int stage, bool fwd, const float *S, const float *Mn, float *out,
+                         const StageCoef &c, hipStream_t s)
+{
+    if (stage == 1 && fwd) xs_launch<L, 1, true, W>(p, P, S, Mn, out, c, s);
+    else if (stage == 2 && fwd) xs_launch<L, 2, true, W>(p, P, S, Mn, out, c, s);
+    else if (stage == 3 && fwd) xs_launch<L, 3, true, W>(p, P, S, Mn, out, c, s);
+    else if (stage == 4 && !fwd) xs_launch<L, 4, false, W>(p, P, S, Mn, out, c, s);
+    else if (stage == 0 && fwd) xs_launch<L, 0, true, W>(p, P, S, Mn, out, c, s);
+    else if (stage == 0 && !fwd) xs_launch<L, 0, false, W>(p, P, S, Mn, out, c, s);
+    else return fail(MM_EINVAL, "fused stage: unsupported stage/forward combination");
+    return MM_OK;
 }
 
 template <int L>
-static int xs_dispatch(Plan &p, int P, int stage, bool fwd, const float *S, const float *Mn, float *out,
+static int xs_dispatch(Plan &p, int tile, int stage, bool fwd, const float *S, const float *Mn, float *out,
                        const StageCoef &c, hipStream_t s)
 {
-    if (stage == 1 && fwd) xs_launch<L, 1, true>(p, P, S, Mn, out, c, s);
-    else if (stage == 2 && fwd) xs_launch<L, 2, true>(p, P, S, Mn, out, c, s);
-    else if (stage == 3 && fwd) xs_launch<L, 3, true>(p, P, S, Mn, out, c, s);
-    else if (stage == 4 && !fwd) xs_launch<L, 4, false>(p, P, S, Mn, out, c, s);
-    else if (stage == 0 && fwd) xs_launch<L, 0, true>(p, P, S, Mn, out, c, s);
-    else if (stage == 0 && !fwd) xs_launch<L, 0, false>(p, P, S, Mn, out, c, s);
-    else return fail(MM_EINVAL, "fused stage: unsupported stage/forward combination");
-    return MM_OK;
+    const int P = tile & 255, W = xs_w(tile);
+    if (W == 4) return xs_dispatch_w<L, 4>(p, P, stage, fwd, S, Mn, out, c, s);
+    if (W == 2) return xs_dispatch_w<L, 2>(p, P, stage, fwd, S, Mn, out, c, s);
+    return xs_dispatch_w<L, 1>(p, P, stage, fwd, S, Mn, out, c, s);
 }
 
 // The x-inverse of the field in X1, stage `stage` (0 Euler, 1..4 RK4) from
@@ -110,7 +129,7 @@ static int xs_dispatch(Plan &p, int P, int stage, bool fwd, const float *S, cons
 int launch_xstage(Plan &p, int stage, bool fwd, const float *S, const float *Mn, float *out, const StageCoef &c,
                   hipStream_t s)
 {
-    const int P = p.tile[MM_PASS_XSTAGE];
+    const int P = p.tile[MM_PASS_XSTAGE];  // P + 256 w
     if (P <= 0 || !xstage_tile_valid(p, P)) return fail(MM_EINVAL, "invalid fused-stage tile");
     timing_arm(p);
     int rc = MM_OK;

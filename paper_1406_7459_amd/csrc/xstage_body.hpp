@@ -22,11 +22,8 @@
 
 namespace mmk {
 
-// cells per thread task of the stage phase: 4 when nx % 4 == 0, else 2 or 1
-template <int L> constexpr int xs_width() { return (L / 2) % 4 == 0 ? 4 : ((L / 2) % 2 == 0 ? 2 : 1); }
-
 // LDS layout: twiddles | 3P transforms of XS slots (float2) | H/S' rows
-// [3][2P][nx] (float, 16-byte aligned).
+// [3][2P][nx] (float, 16-byte aligned; sized for nx = L/2, the largest).
 template <int L> constexpr int xs_slots() { return lds_rows(L) + 1; }
 template <int L> __host__ __device__ constexpr size_t xs_rows_offset(int P)
 {
@@ -37,13 +34,13 @@ template <int L> __host__ __device__ constexpr size_t xs_lds_bytes(int P)
     return xs_rows_offset<L>(P) + 3 * 2 * (size_t)P * (L / 2) * sizeof(float);
 }
 
-template <int L, int STAGE, bool FWD>
+// W: cells per thread task of the stage phase (nx % W == 0).
+template <int L, int STAGE, bool FWD, int W>
 __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float *S, const float *Mn,
-                                            float *__restrict__ kacc, float *out, int ny, int nz, const StageCoef &c,
-                                            const float2 *__restrict__ tw, int lp2, int bx)
+                                            float *__restrict__ kacc, float *out, int nx_, int ny, int nz,
+                                            const StageCoef &c, const float2 *__restrict__ tw, int lp2, int bx)
 {
     constexpr int E = Factors<L>::E, Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
-    constexpr int W = xs_width<L>();
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int P = 1 << lp2;
@@ -59,7 +56,7 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
     constexpr int XS = xs_slots<L>();
     float2 *fbuf = lds + tw_slots<L>();
     float *rows = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + xs_rows_offset<L>(P));
-    const int rstride = 2 * P * NX;  // floats per component in `rows`
+    const int rstride = 2 * P * nx_;  // floats per component in `rows`
     const LdsView s{fbuf, 1, (g * P + p) * XS};
 
     // 1. inverse C2R of rows ra, rb of component g (as xinv_body)
@@ -89,16 +86,16 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
             }
         fft_e<L, E, +1, false>(v, s, q, twl);
         constexpr int RL = last_radix<L, false>();
-        float *ha = rows + g * rstride + 2 * p * NX;
+        float *ha = rows + g * rstride + 2 * p * nx_;
 #pragma unroll
         for (int b = 0; b < E / RL; ++b)
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const int i = q + Q * b + r * (L / RL);
                 const bool upper = r * (L / RL) >= NX;
-                if (!upper && i < NX) {
+                if (!upper && i < nx_) {
                     ha[i] = v[b * RL + r].x;
-                    ha[NX + i] = v[b * RL + r].y;
+                    ha[nx_ + i] = v[b * RL + r].y;
                 }
             }
     }
@@ -107,10 +104,9 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
     // 2. the stage on cells [r0 nx, (r0 + 2P) nx), W consecutive cells of a
     // row per task (as stage_body_vec, with the field from LDS)
     {
-        typedef typename VecOf<W == 1 ? 2 : W>::T V2;
-        const unsigned nx = NX, nxy = (unsigned)NX * (unsigned)ny;
+        const unsigned nx = (unsigned)nx_, nxy = (unsigned)nx_ * (unsigned)ny;
         const unsigned n = nxy * (unsigned)nz;
-        const unsigned base = (unsigned)r0 * NX;
+        const unsigned base = (unsigned)r0 * nx;
         for (unsigned e = (unsigned)t * W; e < (unsigned)rstride; e += blockDim.x * W) {
             const unsigned id = base + e;
             if (id >= n) break;
@@ -206,7 +202,6 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
                 }
             }
         }
-        (void)sizeof(V2);
     }
     if constexpr (!FWD) return;
 
@@ -214,8 +209,8 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
     // 3. forward R2C of the new state's rows ra, rb of component g (as
     // xfwd_body; a row past the grid enters as zeros)
     {
-        const float *za = rows + g * rstride + 2 * p * NX;
-        const float *zb = za + NX;
+        const float *za = rows + g * rstride + 2 * p * nx_;
+        const float *zb = za + nx_;
         float2 v[E];
         constexpr int R0 = first_radix<L, false>();
 #pragma unroll
@@ -224,7 +219,7 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
             for (int r = 0; r < R0; ++r) {
                 const int i = q + Q * b + r * (L / R0);
                 const bool upper = r * (L / R0) >= NX;
-                const bool in = !upper && i < NX;
+                const bool in = !upper && i < nx_;
                 v[b * R0 + r] = make_float2(in && oka ? za[i] : 0.f, in && okb ? zb[i] : 0.f);
             }
         fft_e<L, E, -1, false>(v, s, q, twl);

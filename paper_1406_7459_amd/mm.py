@@ -288,11 +288,12 @@ class Plan:
                     tiles={PASSES[k]: inf.cfg[k] for k in range(NPASS)})
 
     def spectrum(self, stream=None) -> torch.Tensor:
-        """The stored K~ octant, float32 [nzK][ny+1][nx+1][6]."""
+        """The stored K~ octant, float32 [nzK][Ly/2+1][Lx/2+1][6] (nzK = Lz/2+1,
+        or 1 when nz = 1)."""
         inf = self.info()
-        nx, ny, nz = self.shape
-        nzk = nz + 1 if nz > 1 else 1
-        out = torch.empty((nzk, ny + 1, nx + 1, 6), dtype=torch.float32, device="cuda")
+        nz = self.shape[2]
+        nzk = inf["Lz"] // 2 + 1 if nz > 1 else 1
+        out = torch.empty((nzk, inf["Ly"] // 2 + 1, inf["Lx"] // 2 + 1, 6), dtype=torch.float32, device="cuda")
         _check(lib().mm_plan_spectrum(self._h, out.data_ptr(), out.numel(), _stream(stream)),
                "mm_plan_spectrum")
         assert out.numel() == inf["spectrum_count"]

@@ -47,8 +47,8 @@ def test_status_strings(L):
 
 @pytest.mark.parametrize("args", [
     (0, 4, 4, 1e-9, 1e-9, 1e-9), (4, -1, 4, 1e-9, 1e-9, 1e-9), (4, 4, 4, 0.0, 1e-9, 1e-9),
-    (5, 4, 4, 1e-9, 1e-9, 1e-9), (4, 4, 1024, 1e-9, 1e-9, 1e-9), (4, 4, 4, float("nan"), 1e-9, 1e-9),
-    (7, 7, 1, 1e-9, 1e-9, 1e-9)])
+    (513, 4, 4, 1e-9, 1e-9, 1e-9), (4, 4, 1024, 1e-9, 1e-9, 1e-9), (4, 4, 4, float("nan"), 1e-9, 1e-9),
+    (7, 600, 1, 1e-9, 1e-9, 1e-9), (4, 4, 4, 1e-9, -1e-9, 1e-9)])
 def test_setup_rejects_bad_grid_before_device_work(L, args):
     h = C.c_void_p(123)
     rc = L.mm_demag_setup(*args, C.byref(h))

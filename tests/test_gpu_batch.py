@@ -86,7 +86,7 @@ def test_batch_rejects_bad_input():
     with pytest.raises(ValueError):
         b.step([], [M], 1)
     with pytest.raises(mm.MMError):
-        mm.Batch([(7, 8, 2)], [(1e-9, 1e-9, 1e-9)])
+        mm.Batch([(513, 8, 2)], [(1e-9, 1e-9, 1e-9)])
     b.close()
 
 

@@ -74,20 +74,23 @@ def test_gradients_match_reference(grid):
     dm = S.bf16(torch.from_numpy(W.random_unit(nx, ny, nz, 4)))
     dh = torch.from_numpy(0.3 * W.random_unit(nx, ny, nz, 5)).float().double()
     loss_g, g = sur.gradients(to_dev(dm.numpy()), to_dev(dh.numpy()))
-    # reference: the same bf16 operands, FP64 arithmetic, straight-through rounding
-    pr = [(w.clone().requires_grad_(True), b.clone().requires_grad_(True)) for w, b in ps]
-    out, _ = S.forward(pr, dm, bf16_between=True)
-    loss = S.mse(out, dh)
-    loss.backward()
-    gref = flat([(w.grad, b.grad) for w, b in pr])
-    assert loss_g == pytest.approx(loss.item(), rel=2e-2)
+    # reference: the same bf16 operands, FP64 arithmetic, and bf16 rounding at
+    # the points where the matrix-core path stores a tensor (layer inputs,
+    # pre-activations as the GELU derivative's argument, every dZ)
+    loss, gr = S.loss_and_grads_rounded(ps, dm, dh, rnd=S.bf16)
+    gref = flat(gr)
+    assert loss_g == pytest.approx(loss, rel=1e-2)
     o = 0
+    worst = 0.0
     for li, (w, b) in enumerate(ps):
         n = w.numel() + b.numel()
         e = rel_l2(g[o:o + n], gref[o:o + n])
         say("layer", li, "grad rel L2", e)
-        assert e < 5e-2
+        worst = max(worst, e)
         o += n
+    # FP32 accumulation against FP64 moves a few bf16 roundings by one ulp
+    # (2^-8): the gradients agree far below that per layer
+    assert worst < 1e-2
 
 
 def test_gradients_are_deterministic():

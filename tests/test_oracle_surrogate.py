@@ -95,3 +95,40 @@ def test_bf16_rounding_is_nearest_even():
     x = torch.tensor([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -7], dtype=torch.float64)
     y = S.bf16(x)
     assert y.tolist() == [1.0, 1.0 + 2 ** -6, 1.0 + 2 ** -7]
+
+
+def test_explicit_backward_equals_autograd_without_rounding():
+    """The layer-by-layer backward (the form whose rounding points follow the
+    matrix-core path) equals autograd's gradients when nothing is rounded."""
+    chans = (3, 4, 5, 3)
+    params = S.init_params(4, chans)
+    g = np.random.default_rng(5)
+    dm = torch.from_numpy(g.standard_normal((3, 3, 4, 5)))
+    dh = torch.from_numpy(g.standard_normal((3, 3, 4, 5)))
+    l0, g0 = S.loss_and_grads(params, dm, dh)
+    l1, g1 = S.loss_and_grads_rounded(params, dm, dh)
+    assert l1 == pytest.approx(l0, rel=1e-14)
+    for (a, b), (c, d) in zip(g0, g1):
+        assert torch.allclose(a, c, rtol=1e-12, atol=1e-14)
+        assert torch.allclose(b, d, rtol=1e-12, atol=1e-14)
+
+
+def test_gelu_prime_matches_finite_difference():
+    x = torch.linspace(-4, 4, 41, dtype=torch.float64)
+    h = 1e-6
+    fd = (S.gelu(x + h) - S.gelu(x - h)) / (2 * h)
+    assert torch.allclose(S.gelu_prime(x), fd, atol=1e-9)
+
+
+def test_rounded_backward_rounds_where_stated():
+    """With a rounding that zeroes everything the backward sees only zeros:
+    the rounding is applied to the input (so the first layer's weight
+    gradient vanishes) and to every dZ (so every gradient vanishes)."""
+    chans = (3, 4, 3)
+    params = S.init_params(6, chans)
+    g = np.random.default_rng(7)
+    dm = torch.from_numpy(g.standard_normal((3, 2, 3, 4)))
+    dh = torch.from_numpy(g.standard_normal((3, 2, 3, 4)))
+    _, gr = S.loss_and_grads_rounded(params, dm, dh, rnd=lambda t: t * 0.0)
+    for w, b in gr:
+        assert float(w.abs().max()) == 0.0 and float(b.abs().max()) == 0.0
