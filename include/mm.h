@@ -107,6 +107,7 @@ typedef struct {
     long long spectrum_count;  /* floats in the stored K~ octant: 6 (Lx/2+1)(Ly/2+1)(Lz/2+1), nz=1: 6(Lx/2+1)(Ly/2+1) */
     long long workspace_bytes; /* device bytes the plan works in (mm_plan_workspace_bytes) */
     int cfg[9];                /* launch tile per pass kind (see MM_PASS_*) */
+    int tune_source;           /* 0 defaults or set by hand, 1 timed by mm_plan_autotune, 2 read from the tune cache */
 } mm_plan_info;
 
 /* Pass kinds of one demag evaluation, for tiles and per-kernel timing. */
@@ -243,9 +244,17 @@ int mm_plan_set_tile(mm_plan plan, int pass, int tile);
 /* Time every candidate tile of every pass on this plan's buffers and keep
  * the fastest: a candidate is timed as `reps` complete demag evaluations
  * (hipEvents around the loop only), the other passes keeping their current
- * tiles, and the passes are swept twice.  Overwrites the plan's stage
- * buffers.  Candidates agree bitwise; the chosen tiles are readable with
- * mm_plan_query.  Synchronises.  Errors: MM_ETUNE if no candidate ran.       */
+ * tiles, and the passes are swept twice; then the fused stage pass's tiles,
+ * each timed as `reps` RK4 steps.  Candidates are the tile P, the schedule
+ * variant and, for the product passes, the radix order (variants 3, 4);
+ * one order's candidates agree bitwise, different orders within rounding.
+ * Overwrites the plan's stage buffers.  The chosen tiles are readable with
+ * mm_plan_query.  Synchronises.
+ * Tune cache: when the environment variable MM_TUNE_CACHE names a file, a
+ * plan whose (device architecture, compute units, grid) key is in it takes
+ * the stored tiles without timing (tune_source 2); otherwise the timed
+ * result is added to the file (one JSON object, one key per line).
+ * Errors: MM_ETUNE if no candidate ran.                                     */
 int mm_plan_autotune(mm_plan plan, int reps, void *stream);
 
 /* Per-kernel timing: when enabled, every launch of the plan is timed with a

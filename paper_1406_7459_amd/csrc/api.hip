@@ -4,8 +4,12 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "mm_internal.hpp"
 
@@ -179,6 +183,76 @@ size_t plan_layout(Plan &p, char *base)
     return total;
 }
 
+// ------------------------------------------------------------ tune cache ---
+// A JSON object with one key per line,
+//   "gfx950/256cu/128x128x128": {"xfwd": 8, "yfwd": 16, ...},
+// naming the device and grid and giving the tile of every pass kind.
+static const char *const PASS_NAMES[MM_PASS_COUNT] = {"xfwd",  "yfwd",  "zconv",  "yinv",  "xinv",
+                                                      "yconv", "stage", "reduce", "xstage"};
+
+static std::string tune_key(const Plan &p)
+{
+    return p.arch + "/" + std::to_string(p.nx) + "x" + std::to_string(p.ny) + "x" + std::to_string(p.nz);
+}
+
+static std::map<std::string, std::string> tune_cache_load(const char *path)
+{
+    std::map<std::string, std::string> out;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t a = line.find('"');
+        const size_t b = a == std::string::npos ? a : line.find('"', a + 1);
+        const size_t c = b == std::string::npos ? b : line.find('{', b);
+        const size_t d = c == std::string::npos ? c : line.find('}', c);
+        if (d == std::string::npos) continue;
+        out[line.substr(a + 1, b - a - 1)] = line.substr(c, d - c + 1);
+    }
+    return out;
+}
+
+// Apply a cached entry for this plan; false if absent or any tile in it is
+// not launchable here.
+bool tune_cache_read(Plan &p, const char *path)
+{
+    const auto m = tune_cache_load(path);
+    const auto it = m.find(tune_key(p));
+    if (it == m.end()) return false;
+    int tiles[MM_PASS_COUNT];
+    for (int k = 0; k < MM_PASS_COUNT; ++k) {
+        const std::string pat = std::string("\"") + PASS_NAMES[k] + "\":";
+        const size_t at = it->second.find(pat);
+        if (at == std::string::npos) return false;
+        tiles[k] = std::atoi(it->second.c_str() + at + pat.size());
+        if (tiles[k] != 0 && k != MM_PASS_REDUCE && !pass_tile_valid(p, k, tiles[k])) return false;
+        if (tiles[k] == 0 && k != MM_PASS_REDUCE && k != MM_PASS_XSTAGE && p.tile[k] != 0) return false;
+    }
+    for (int k = 0; k < MM_PASS_COUNT; ++k) p.tile[k] = tiles[k];
+    return true;
+}
+
+// Add (or replace) this plan's entry; the file is rewritten through a
+// temporary and renamed into place.
+void tune_cache_write(const Plan &p, const char *path)
+{
+    auto m = tune_cache_load(path);
+    std::string v = "{";
+    for (int k = 0; k < MM_PASS_COUNT; ++k)
+        v += std::string(k ? ", " : "") + "\"" + PASS_NAMES[k] + "\": " + std::to_string(p.tile[k]);
+    v += "}";
+    m[tune_key(p)] = v;
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+    {
+        std::ofstream f(tmp);
+        f << "{\n";
+        size_t i = 0;
+        for (const auto &kv : m) f << "\"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+        f << "}\n";
+        if (!f) return;
+    }
+    (void)std::rename(tmp.c_str(), path);
+}
+
 int plan_ready(const Plan *p)
 {
     if (!p) return fail(MM_EINVAL, "NULL plan");
@@ -256,6 +330,7 @@ int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_p
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, p.device) == hipSuccess) {
+        p.arch = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
         p.lds_limit = prop.sharedMemPerBlock;
         if (p.lds_limit > 160 * 1024) p.lds_limit = 160 * 1024;
         if (p.lds_limit < 32768) p.lds_limit = 32768;
@@ -537,6 +612,7 @@ int mm_plan_query(mm_plan plan, mm_plan_info *info)
     info->spectrum_count = p->nK;
     info->workspace_bytes = (long long)p->bytes;
     for (int k = 0; k < MM_PASS_COUNT; ++k) info->cfg[k] = p->tile[k];
+    info->tune_source = p->tune_source;
     return MM_OK;
 }
 
@@ -546,6 +622,7 @@ int mm_plan_set_tile(mm_plan plan, int pass, int tile)
     if (!p) return fail(MM_EINVAL, "NULL plan");
     if (!pass_tile_valid(*p, pass, tile)) return fail(MM_EINVAL, "tile not launchable for this pass");
     p->tile[pass] = tile;
+    p->tune_source = 0;
     return MM_OK;
 }
 
@@ -576,6 +653,12 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
     Plan *p = P(plan);
     if (plan_ready(p) != MM_OK) return MM_EINVAL;
     if (reps < 1) reps = 1;
+    const char *cache = std::getenv("MM_TUNE_CACHE");
+    if (cache && *cache && tune_cache_read(*p, cache)) {
+        p->tune_source = 2;
+        drop_plan_graph(*p);
+        return MM_OK;
+    }
     hipStream_t s = (hipStream_t)stream;
     // Each candidate is timed as the duration of `reps` complete demag
     // evaluations (two events around the loop, none between the launches),
@@ -661,6 +744,8 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
     drop_plan_graph(*p);
     if (rc != MM_OK) return rc;
     if (tuned == 0) return fail(MM_ETUNE, "no candidate ran");
+    p->tune_source = 1;
+    if (cache && *cache) tune_cache_write(*p, cache);
     return MM_OK;
 }
 

@@ -384,6 +384,7 @@ int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const
             g.L = L;
             g.tile = default_tile_for(pass, L, b->lds_limit);
             for (int t : tile_candidates_for(pass, L, b->lds_limit)) {
+                if ((t >> 8) > 2) continue;  // the batch runs the default radix orders
                 make_tasks(*b, g, t, scratch);
                 g.cap = std::max(g.cap, scratch.size());
             }
@@ -578,6 +579,7 @@ int mm_batch_autotune(mm_batch batch, int reps, void *stream)
         float best = 1e30f;
         int best_tile = keep;
         for (int t : tile_candidates_for(g.pass, g.L, b.lds_limit)) {
+            if ((t >> 8) > 2) continue;  // the batch runs the default radix orders
             g.tile = t;
             if ((rc = build_tasks(b, g)) != MM_OK) break;
             if ((rc = batch_demag_enqueue(b, b.d_inst, 1, s)) != MM_OK) break;

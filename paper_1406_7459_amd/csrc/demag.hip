@@ -42,16 +42,16 @@ __global__ __launch_bounds__(1024) void k_yfwd(const float2 *__restrict__ X1, fl
     column_coords(bx, plane);
     yfwd_body<L, V>(X1, X2, nxc, ny, lp2, tw, bx, plane);
 }
-template <int L, bool ZAXIS>
-__global__ __launch_bounds__(conv_max_threads<L>()) void k_conv_reg3(float2 *__restrict__ X,
-                                                                      const float *__restrict__ Kt, int nxc, int hy,
-                                                                      int nlive, int lp2,
-                                                                      const float2 *__restrict__ tw)
+template <int L, bool ZAXIS, int O>
+__global__ __launch_bounds__((conv_max_threads<L, O>())) void k_conv_reg3(float2 *__restrict__ X,
+                                                                         const float *__restrict__ Kt, int nxc,
+                                                                         int hy, int nlive, int lp2,
+                                                                         const float2 *__restrict__ tw)
 {
     int bx, ky = 0;
     if constexpr (ZAXIS) conv_coords(hy, bx, ky);
     else bx = (int)xcd_block(blockIdx.x, gridDim.x);
-    conv_reg3_body<L, ZAXIS>(X, Kt, nxc, hy, nlive, lp2, tw, bx, ky);
+    conv_reg3_body<L, ZAXIS, O>(X, Kt, nxc, hy, nlive, lp2, tw, bx, ky);
 }
 template <int L, int V, bool ZAXIS>
 __global__ __launch_bounds__(1024) void k_conv_split(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc,
@@ -81,7 +81,8 @@ __global__ __launch_bounds__(1024) void k_xinv(const float2 *__restrict__ X1, fl
 // A launch configuration ("tile") is P + 256 * variant: P transforms (rows
 // for x, kx columns for y/z) per workgroup, a power of two, and a schedule
 // variant: for the single-component passes 0 = default values per thread E,
-// 1 = 2E; for the product passes 0 = reg3, 1 = split (E), 2 = split (2E).
+// 1 = 2E; for the product passes 0 = reg3, 1 = split (E), 2 = split (2E),
+// 3 = reg3 in radix order 1, 4 = reg3 in radix order 2 (fft_engine.hpp).
 
 static int ilog2(int v)
 {
@@ -95,11 +96,18 @@ struct KInfo {
     int E1;      // variant-1 values per thread (== E0 when 2E0 > L)
     int nstage;
     int conv_max;  // launch bound of the reg3 product kernel
+    int Eo[3];     // values per thread of radix orders 0, 1, 2 (0: no such order)
+    int maxo[3];   // launch bound of the reg3 kernel in each order
 };
+
+template <int L, int O> static constexpr int order_e() { if constexpr (Factors<L, O>::valid) return Factors<L, O>::E; else return 0; }
+template <int L, int O> static constexpr int order_max() { if constexpr (Factors<L, O>::valid) return conv_max_threads<L, O>(); else return 0; }
 
 template <int L> static KInfo kinfo()
 {
-    return {Factors<L>::E, ept<L, 1>(), Factors<L>::N, conv_max_threads<L>()};
+    return {Factors<L>::E, ept<L, 1>(), Factors<L>::N, conv_max_threads<L>(),
+            {order_e<L, 0>(), order_e<L, 1>(), order_e<L, 2>()},
+            {order_max<L, 0>(), order_max<L, 1>(), order_max<L, 2>()}};
 }
 
 #define MMK_ALL_LENGTHS(X)                                                                               \
@@ -166,9 +174,11 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
     const size_t tws = k.nstage > 1 ? (size_t)L : 0;
     maxt = 1024;
     if (is_conv(pass)) {
-        if (var == 0) {
-            threads = P * (L / k.E0);
-            maxt = k.conv_max;
+        if (var == 0 || var == 3 || var == 4) {
+            const int o = var == 0 ? 0 : var - 2;
+            if (!k.Eo[o]) return false;
+            threads = P * (L / k.Eo[o]);
+            maxt = k.maxo[o];
             // two exchange buffers (ping-pong transforms)
             lds = (tws + (k.nstage > 1 ? 2 * (size_t)lds_rows(L) * P : 0)) * sizeof(float2);
         } else if (var == 1 || var == 2) {
@@ -206,7 +216,7 @@ bool tile_valid_for(int pass, int L, int tile, size_t lds_limit)
 std::vector<int> tile_candidates_for(int pass, int L, size_t lds_limit)
 {
     std::vector<int> out;
-    for (int var = 0; var < 3; ++var)
+    for (int var = 0; var < 5; ++var)
         for (int P = 1; P <= 128; P *= 2) {
             const int tile = P + 256 * var;
             if (!tile_valid_for(pass, L, tile, lds_limit)) continue;
@@ -282,7 +292,7 @@ static hipError_t raise_lds(size_t limit)
         raise_one(k_yfwd<L, 0>, lim),        raise_one(k_yfwd<L, 1>, lim),
         raise_one(k_yinv<L, 0>, lim),        raise_one(k_yinv<L, 1>, lim),
         raise_one(k_xinv<L, 0>, lim),        raise_one(k_xinv<L, 1>, lim),
-        raise_one(k_conv_reg3<L, true>, lim), raise_one(k_conv_reg3<L, false>, lim),
+        raise_one(k_conv_reg3<L, true, 0>, lim), raise_one(k_conv_reg3<L, false, 0>, lim),
         raise_one(k_conv_split<L, 0, true>, lim), raise_one(k_conv_split<L, 1, true>, lim),
         raise_one(k_conv_split<L, 0, false>, lim), raise_one(k_conv_split<L, 1, false>, lim)};
     for (hipError_t e : es)
@@ -353,8 +363,28 @@ static void launch_conv(Plan &p, int pass, int P, int var, size_t lds, hipStream
     const int hy = p.Ly / 2, nl = z ? p.nz : p.ny;
     if (var == 0) {
         const dim3 block(P * (L / Factors<L>::E));
-        if (z) MMK_LAUNCH(p, (k_conv_reg3<L, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
-        else MMK_LAUNCH(p, (k_conv_reg3<L, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_reg3<L, true, 0>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        else MMK_LAUNCH(p, (k_conv_reg3<L, false, 0>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+    } else if (var == 3 || var == 4) {
+        if constexpr (Factors<L, 1>::valid || Factors<L, 2>::valid) {
+            auto go = [&](auto kern, int E) {
+                if (lds > 65536)
+                    (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                MMK_LAUNCH(p, kern, grid, dim3(P * (L / E)), lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+            };
+            if constexpr (Factors<L, 1>::valid) {
+                if (var == 3) {
+                    if (z) go(k_conv_reg3<L, true, 1>, Factors<L, 1>::E);
+                    else go(k_conv_reg3<L, false, 1>, Factors<L, 1>::E);
+                }
+            }
+            if constexpr (Factors<L, 2>::valid) {
+                if (var == 4) {
+                    if (z) go(k_conv_reg3<L, true, 2>, Factors<L, 2>::E);
+                    else go(k_conv_reg3<L, false, 2>, Factors<L, 2>::E);
+                }
+            }
+        }
     } else if (var == 1) {
         const dim3 block(3 * P * (L / ept<L, 0>()));
         if (z) MMK_LAUNCH(p, (k_conv_split<L, 0, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);

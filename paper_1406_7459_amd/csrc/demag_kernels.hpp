@@ -36,16 +36,8 @@ namespace mmk {
 
 // Twiddles live at the head of the dynamic LDS block (copied once per
 // workgroup; the first read comes after the first exchange barrier, and a
-// single-stage transform reads none).  MMK_TW_GLOBAL keeps them in global
-// memory instead (for A/B timing).
-template <int L> constexpr int tw_slots()
-{
-#ifdef MMK_TW_GLOBAL
-    return 0;
-#else
-    return Factors<L>::N > 1 ? L : 0;
-#endif
-}
+// single-stage transform reads none).
+template <int L> constexpr int tw_slots() { return Factors<L>::N > 1 ? L : 0; }
 
 template <int L>
 __device__ __forceinline__ const float2 *stage_twiddles(float2 *lds, const float2 *__restrict__ tw)
@@ -202,17 +194,22 @@ __device__ __forceinline__ void kdot(float2 &a, float2 &b, float2 &c, float kxx,
 }
 
 // Three components stay in VGPRs across the product: cap the workgroup so
-// the allocator gets 256 (E = 8) or 512 (E = 24) registers per lane.
-template <int L> constexpr int conv_max_threads() { return Factors<L>::E > 8 ? 256 : 512; }
+// the allocator gets 128 (E = 4), 256 (E = 8) or 512 (E >= 12) registers
+// per lane.
+template <int L, int O = 0> constexpr int conv_max_threads()
+{
+    return Factors<L, O>::E > 8 ? 256 : (Factors<L, O>::E > 4 ? 512 : 1024);
+}
 
-// Schedule "reg3" of the product pass.  ZAXIS: z forward -> product -> z
-// inverse for P kx columns at one ky, in place on X2 (rows k < nz).  Else
-// (nz = 1): the same along y on X1 (rows j < ny), with xz = yz = 0.
-template <int L, bool ZAXIS>
+// Schedule "reg3" of the product pass in radix order O.  ZAXIS: z forward
+// -> product -> z inverse for P kx columns at one ky, in place on X2 (rows
+// k < nz).  Else (nz = 1): the same along y on X1 (rows j < ny), with
+// xz = yz = 0.
+template <int L, bool ZAXIS, int O = 0>
 __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int hy,
                                                int nlive, int lp2, const float2 *__restrict__ tw, int bx, int ky)
 {
-    constexpr int E = Factors<L>::E, Q = L / E, NH = L / 2;
+    constexpr int E = Factors<L, O>::E, Q = L / E, NH = L / 2;
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int P = 1 << lp2;
@@ -228,7 +225,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const size_t cs = (size_t)nlive * rs;                         // component stride
     float2 *base = X + (size_t)ky * xp + kx + (size_t)q * rs;  // this thread's row q
     float2 va[E], vb[E], vc[E];
-    constexpr int R0 = first_radix<L, false>();
+    constexpr int R0 = first_radix<L, false, O>();
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -244,11 +241,11 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             vb[b * R0 + r] = ld ? float2(base[cs + o]) : make_float2(0.f, 0.f);
             vc[b * R0 + r] = ld ? float2(base[2 * cs + o]) : make_float2(0.f, 0.f);
         }
-    fft_pp<L, -1, false>(va, s, s1, q, twl);
-    fft_pp<L, -1, false>(vb, s, s1, q, twl);
-    fft_pp<L, -1, false>(vc, s, s1, q, twl);
+    fft_pp<L, -1, false, O>(va, s, s1, q, twl);
+    fft_pp<L, -1, false, O>(vb, s, s1, q, twl);
+    fft_pp<L, -1, false, O>(vc, s, s1, q, twl);
 
-    constexpr int RL = last_radix<L, false>();
+    constexpr int RL = last_radix<L, false, O>();
     const int nyk = hy + 1;
     const int kyf = ky <= hy ? ky : 2 * hy - ky;
     const float sy0 = ky <= hy ? 1.f : -1.f;
@@ -276,9 +273,9 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     // mixing them lifts the register peak from ~106 to ~134 VGPRs at L = 256
     // (three waves per SIMD instead of four).
     __builtin_amdgcn_sched_barrier(0);
-    fft_pp<L, +1, true>(va, s, s1, q, twl);
-    fft_pp<L, +1, true>(vb, s, s1, q, twl);
-    fft_pp<L, +1, true>(vc, s, s1, q, twl);
+    fft_pp<L, +1, true, O>(va, s, s1, q, twl);
+    fft_pp<L, +1, true, O>(vb, s, s1, q, twl);
+    fft_pp<L, +1, true, O>(vc, s, s1, q, twl);
     // the reversed order ends with radix R0: outputs sit where the inputs did
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)

@@ -93,6 +93,41 @@ __device__ __forceinline__ void bfly8(float2 *x)
     }
 }
 
+// 16-point DFT in natural order as 4 x 4: with n = j + 4m and k = k1 + 4k2,
+// X[k] = sum_j w16^(j k1) w4^(j k2) (sum_m x[j + 4m] w4^(m k1)).
+template <int DIR>
+__device__ __forceinline__ void bfly16(float2 *x)
+{
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;  // cos, sin of pi/8
+    const float h = 0.70710678118654752440f;
+    float2 y[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float2 t[4] = {x[j], x[j + 4], x[j + 8], x[j + 12]};
+        bfly4<DIR>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) y[j][k1] = t[k1];
+    }
+    // w16^(j k1) for j, k1 = 1..3: exponents 1, 2, 3, 2, 4, 6, 3, 6, 9
+    const float2 w1 = make_float2(c1, DIR * s1), w2 = make_float2(h, DIR * h), w3 = make_float2(s1, DIR * c1);
+    y[1][1] = cmul(y[1][1], w1);
+    y[1][2] = cmul(y[1][2], w2);
+    y[1][3] = cmul(y[1][3], w3);
+    y[2][1] = cmul(y[2][1], w2);
+    y[2][2] = mul_mi<DIR>(y[2][2]);
+    y[2][3] = cmul(y[2][3], make_float2(-h, DIR * h));
+    y[3][1] = cmul(y[3][1], w3);
+    y[3][2] = cmul(y[3][2], make_float2(-h, DIR * h));
+    y[3][3] = cmul(y[3][3], make_float2(-c1, -DIR * s1));
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        bfly4<DIR>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = t[k2];
+    }
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void bfly(float2 *x)
 {
@@ -100,55 +135,83 @@ __device__ __forceinline__ void bfly(float2 *x)
     else if constexpr (R == 3) bfly3<DIR>(x);
     else if constexpr (R == 4) bfly4<DIR>(x);
     else if constexpr (R == 8) bfly8<DIR>(x);
-    else static_assert(R == 2 || R == 3 || R == 4 || R == 8, "radix");
+    else if constexpr (R == 16) bfly16<DIR>(x);
+    else static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "radix");
 }
 
 // ------------------------------------------------- factorisation tables ---
-// Radix order of the forward transform and values per thread E (E must be
-// a multiple of every radix; Q = L/E threads share one transform).
-template <int L> struct Factors;
-#define MMK_FACTORS(LEN, EPT, ...)                                   \
-    template <> struct Factors<LEN> {                                \
+// Radix order O of the forward transform and values per thread E (E must
+// be a multiple of every radix; Q = L/E threads share one transform).
+// O = 0 is the default; O = 1 and 2 are the alternative orders the product
+// pass's autotuner tries (1: radix 16 first, E = 16, for 2^a, and radix 3
+// then 4s, E = 12, for 3 2^a; 2: radix 4 only, E = 4, for 2^a).  Orders
+// round differently; every schedule of one order is bitwise identical.
+template <int L, int O = 0> struct Factors { static constexpr bool valid = false; };
+#define MMK_FACTORS(LEN, ORD, EPT, ...)                              \
+    template <> struct Factors<LEN, ORD> {                           \
+        static constexpr bool valid = true;                          \
         static constexpr int E = EPT;                                \
         static constexpr int R[] = {__VA_ARGS__};                    \
         static constexpr int N = sizeof(R) / sizeof(int);            \
     };
-MMK_FACTORS(2, 2, 2)
-MMK_FACTORS(4, 4, 4)
-MMK_FACTORS(6, 6, 3, 2)
-MMK_FACTORS(8, 8, 8)
-MMK_FACTORS(12, 12, 3, 4)
-MMK_FACTORS(16, 8, 8, 2)
-MMK_FACTORS(24, 24, 3, 8)
-MMK_FACTORS(32, 8, 8, 4)
-MMK_FACTORS(48, 24, 3, 8, 2)
-MMK_FACTORS(64, 8, 8, 8)
-MMK_FACTORS(96, 24, 3, 8, 4)
-MMK_FACTORS(128, 8, 8, 4, 4)
-MMK_FACTORS(192, 24, 3, 8, 8)
-MMK_FACTORS(256, 8, 8, 8, 4)
-MMK_FACTORS(384, 24, 3, 8, 4, 4)
-MMK_FACTORS(512, 8, 8, 8, 8)
-MMK_FACTORS(768, 24, 3, 8, 8, 4)
-MMK_FACTORS(1024, 8, 8, 8, 4, 4)
+MMK_FACTORS(2, 0, 2, 2)
+MMK_FACTORS(4, 0, 4, 4)
+MMK_FACTORS(6, 0, 6, 3, 2)
+MMK_FACTORS(8, 0, 8, 8)
+MMK_FACTORS(12, 0, 12, 3, 4)
+MMK_FACTORS(16, 0, 8, 8, 2)
+MMK_FACTORS(24, 0, 24, 3, 8)
+MMK_FACTORS(32, 0, 8, 8, 4)
+MMK_FACTORS(48, 0, 24, 3, 8, 2)
+MMK_FACTORS(64, 0, 8, 8, 8)
+MMK_FACTORS(96, 0, 24, 3, 8, 4)
+MMK_FACTORS(128, 0, 8, 8, 4, 4)
+MMK_FACTORS(192, 0, 24, 3, 8, 8)
+MMK_FACTORS(256, 0, 8, 8, 8, 4)
+MMK_FACTORS(384, 0, 24, 3, 8, 4, 4)
+MMK_FACTORS(512, 0, 8, 8, 8, 8)
+MMK_FACTORS(768, 0, 24, 3, 8, 8, 4)
+MMK_FACTORS(1024, 0, 8, 8, 8, 4, 4)
+// radix 16 first (2^a), radix 3 then 4s (3 2^a)
+MMK_FACTORS(16, 1, 16, 16)
+MMK_FACTORS(24, 1, 12, 3, 4, 2)
+MMK_FACTORS(32, 1, 16, 16, 2)
+MMK_FACTORS(48, 1, 12, 3, 4, 4)
+MMK_FACTORS(64, 1, 16, 16, 4)
+MMK_FACTORS(96, 1, 12, 3, 4, 4, 2)
+MMK_FACTORS(128, 1, 16, 16, 8)
+MMK_FACTORS(192, 1, 12, 3, 4, 4, 4)
+MMK_FACTORS(256, 1, 16, 16, 16)
+MMK_FACTORS(384, 1, 12, 3, 4, 4, 4, 2)
+MMK_FACTORS(512, 1, 16, 16, 8, 4)
+MMK_FACTORS(768, 1, 12, 3, 4, 4, 4, 4)
+MMK_FACTORS(1024, 1, 16, 16, 16, 4)
+// radix 4 only (2^a, E = 4)
+MMK_FACTORS(16, 2, 4, 4, 4)
+MMK_FACTORS(32, 2, 4, 4, 4, 2)
+MMK_FACTORS(64, 2, 4, 4, 4, 4)
+MMK_FACTORS(128, 2, 4, 4, 4, 4, 2)
+MMK_FACTORS(256, 2, 4, 4, 4, 4, 4)
+MMK_FACTORS(512, 2, 4, 4, 4, 4, 4, 2)
+MMK_FACTORS(1024, 2, 4, 4, 4, 4, 4, 4)
 #undef MMK_FACTORS
 
-template <int L, bool REV>
+template <int L, bool REV, int O = 0>
 __device__ __host__ constexpr int radix_at(int s)
 {
-    return REV ? Factors<L>::R[Factors<L>::N - 1 - s] : Factors<L>::R[s];
+    return REV ? Factors<L, O>::R[Factors<L, O>::N - 1 - s] : Factors<L, O>::R[s];
 }
-template <int L, bool REV>
+template <int L, bool REV, int O = 0>
 __device__ __host__ constexpr int ns_before(int s)
 {
     int p = 1;
-    for (int i = 0; i < s; ++i) p *= radix_at<L, REV>(i);
+    for (int i = 0; i < s; ++i) p *= radix_at<L, REV, O>(i);
     return p;
 }
-template <int L, bool REV>
-__device__ __host__ constexpr int first_radix() { return radix_at<L, REV>(0); }
-template <int L, bool REV>
-__device__ __host__ constexpr int last_radix() { return radix_at<L, REV>(Factors<L>::N - 1); }
+template <int L, bool REV, int O = 0>
+__device__ __host__ constexpr int first_radix() { return radix_at<L, REV, O>(0); }
+template <int L, bool REV, int O = 0>
+__device__ __host__ constexpr int last_radix() { return radix_at<L, REV, O>(Factors<L, O>::N - 1); }
 
 // LDS rows are padded: row r of a transform sits in slot r + r/8 (one spare
 // slot after every 8 rows).  The exchanges write with lane strides of R*NS
@@ -230,17 +293,17 @@ __device__ __forceinline__ void exchange(float2 (&v)[E], const LdsView &s, int q
     if constexpr (TRAIL) __syncthreads();
 }
 
-template <int L, int E, int DIR, bool REV, int S>
+template <int L, int E, int DIR, bool REV, int S, int O = 0>
 __device__ __forceinline__ void run_stages(float2 (&v)[E], const LdsView &s, int q,
                                            const float2 *__restrict__ tw)
 {
-    constexpr int R = radix_at<L, REV>(S);
-    constexpr int NS = ns_before<L, REV>(S);
+    constexpr int R = radix_at<L, REV, O>(S);
+    constexpr int NS = ns_before<L, REV, O>(S);
     stage_compute<L, E, R, NS, DIR>(v, q, tw);
-    if constexpr (S + 1 < Factors<L>::N) {
-        constexpr int R2 = radix_at<L, REV>(S + 1);
+    if constexpr (S + 1 < Factors<L, O>::N) {
+        constexpr int R2 = radix_at<L, REV, O>(S + 1);
         exchange<L, E, R, NS, R2>(v, s, q);
-        run_stages<L, E, DIR, REV, S + 1>(v, s, q, tw);
+        run_stages<L, E, DIR, REV, S + 1, O>(v, s, q, tw);
     }
 }
 
@@ -251,27 +314,28 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], const LdsView &s, int
 // buffer 0 (an odd number of exchanges), since the next transform's first
 // exchange writes buffer 0 again.  The caller must not write either buffer
 // between transforms without a barrier.
-template <int L, int E, int DIR, bool REV, int S>
+template <int L, int E, int DIR, bool REV, int S, int O = 0>
 __device__ __forceinline__ void run_stages_pp(float2 (&v)[E], const LdsView &s0, const LdsView &s1, int q,
                                               const float2 *__restrict__ tw)
 {
-    constexpr int R = radix_at<L, REV>(S);
-    constexpr int NS = ns_before<L, REV>(S);
-    constexpr int N = Factors<L>::N;
+    constexpr int R = radix_at<L, REV, O>(S);
+    constexpr int NS = ns_before<L, REV, O>(S);
+    constexpr int N = Factors<L, O>::N;
     stage_compute<L, E, R, NS, DIR>(v, q, tw);
     if constexpr (S + 1 < N) {
-        constexpr int R2 = radix_at<L, REV>(S + 1);
+        constexpr int R2 = radix_at<L, REV, O>(S + 1);
         constexpr bool TRAIL = S == N - 2 && S % 2 == 0;
         exchange<L, E, R, NS, R2, TRAIL>(v, S % 2 ? s1 : s0, q);
-        run_stages_pp<L, E, DIR, REV, S + 1>(v, s0, s1, q, tw);
+        run_stages_pp<L, E, DIR, REV, S + 1, O>(v, s0, s1, q, tw);
     }
 }
 
-template <int L, int DIR, bool REV>
-__device__ __forceinline__ void fft_pp(float2 (&v)[Factors<L>::E], const LdsView &s0, const LdsView &s1, int q,
+template <int L, int DIR, bool REV, int O = 0, int E>
+__device__ __forceinline__ void fft_pp(float2 (&v)[E], const LdsView &s0, const LdsView &s1, int q,
                                        const float2 *__restrict__ tw)
 {
-    run_stages_pp<L, Factors<L>::E, DIR, REV, 0>(v, s0, s1, q, tw);
+    static_assert(E == Factors<L, O>::E, "values per thread of the radix order");
+    run_stages_pp<L, E, DIR, REV, 0, O>(v, s0, s1, q, tw);
 }
 
 // Full transform with E values per thread (E a multiple of every radix of

@@ -93,6 +93,9 @@ struct Plan {
 
     int tile[MM_PASS_COUNT] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 
+    int tune_source = 0;          // 0 default / by hand, 1 timed, 2 tune cache
+    std::string arch;             // device architecture and compute units (tune cache key)
+
     bool timing = false;
     hipEvent_t tev[2] = {nullptr, nullptr};  // armed start/stop pair for the next launch
     TimingAcc acc[MM_PASS_COUNT];
@@ -108,6 +111,9 @@ struct Plan {
 Plan *plan_of(mm_plan h);
 // MM_OK if the plan has its workspace bound, else MM_EINVAL with a detail.
 int plan_ready(const Plan *p);
+// Persistent tuning results (file named by MM_TUNE_CACHE).
+bool tune_cache_read(Plan &p, const char *path);
+void tune_cache_write(const Plan &p, const char *path);
 // Carve (base != nullptr) or measure (base == nullptr) the plan workspace.
 size_t plan_layout(Plan &p, char *base);
 // FP64 scratch bytes of the spectrum set-up (tensor.hip).

@@ -34,6 +34,15 @@ template <int L> __host__ __device__ constexpr size_t xs_lds_bytes(int P)
     return xs_rows_offset<L>(P) + 3 * 2 * (size_t)P * (L / 2) * sizeof(float);
 }
 
+// Inputs of one stage task: W consecutive cells of a row, their stage
+// state, its four y/z neighbour rows and the two x neighbours outside the
+// group, the step's start state and the RK4 accumulator.
+template <int W> struct XsTask {
+    float m[3][W], y0[3][W], y1[3][W], z0[3][W], z1[3][W], mn[3][W], ka[3][W];
+    float left[3], right[3];
+    unsigned id, i;
+};
+
 // W: cells per thread task of the stage phase (nx % W == 0).
 template <int L, int STAGE, bool FWD, int W>
 __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float *S, const float *Mn,
@@ -58,6 +67,113 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
     float *rows = reinterpret_cast<float *>(reinterpret_cast<char *>(lds) + xs_rows_offset<L>(P));
     const int rstride = 2 * P * nx_;  // floats per component in `rows`
     const LdsView s{fbuf, 1, (g * P + p) * XS};
+
+    // stage tasks: cells [r0 nx, (r0 + 2P) nx), W consecutive cells of a row
+    // per task (as stage_body_vec, with the field from LDS)
+    const unsigned nx = (unsigned)nx_, nxy = (unsigned)nx_ * (unsigned)ny;
+    const unsigned n = nxy * (unsigned)nz;
+    const unsigned cbase = (unsigned)r0 * nx;
+    auto load_task = [&](unsigned e, XsTask<W> &T) -> bool {
+        const unsigned id = cbase + e;
+        if (e >= (unsigned)rstride || id >= n) return false;
+        const unsigned k = id / nxy;
+        const unsigned rem = id - k * nxy;
+        const unsigned j = rem / nx;
+        const unsigned i = rem - j * nx;
+        const unsigned ym = j > 0 ? id - nx : id, yp = j + 1 < (unsigned)ny ? id + nx : id;
+        const unsigned zm = k > 0 ? id - nxy : id, zp = k + 1 < (unsigned)nz ? id + nxy : id;
+        T.id = id;
+        T.i = i;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float *sc = S + (size_t)a * n;
+            const float *mc = Mn + (size_t)a * n;
+            const float *kc = kacc + (size_t)a * n;
+            if constexpr (W == 1) {
+                T.m[a][0] = ld32(sc, id);
+                T.y0[a][0] = ld32(sc, ym);
+                T.y1[a][0] = ld32(sc, yp);
+                T.z0[a][0] = ld32(sc, zm);
+                T.z1[a][0] = ld32(sc, zp);
+                T.mn[a][0] = ld32(mc, id);
+                T.ka[a][0] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? ld32(kc, id) : 0.f;
+            } else {
+                typedef typename VecOf<W>::T V;
+                const V vm = ldv32<V>(sc, id), vy0 = ldv32<V>(sc, ym), vy1 = ldv32<V>(sc, yp);
+                const V vz0 = ldv32<V>(sc, zm), vz1 = ldv32<V>(sc, zp), vmn = ldv32<V>(mc, id);
+                V vka;
+                if constexpr (STAGE == 2 || STAGE == 3 || STAGE == 4) vka = ldv32<V>(kc, id);
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    T.m[a][w] = lane_of<W>(vm, w);
+                    T.y0[a][w] = lane_of<W>(vy0, w);
+                    T.y1[a][w] = lane_of<W>(vy1, w);
+                    T.z0[a][w] = lane_of<W>(vz0, w);
+                    T.z1[a][w] = lane_of<W>(vz1, w);
+                    T.mn[a][w] = lane_of<W>(vmn, w);
+                    T.ka[a][w] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? lane_of<W>(vka, w) : 0.f;
+                }
+            }
+            T.left[a] = i > 0 ? ld32(sc, id - 1) : T.m[a][0];
+            T.right[a] = i + W < nx ? ld32(sc, id + W) : T.m[a][W - 1];
+        }
+        return true;
+    };
+    auto stage_task = [&](unsigned e, const XsTask<W> &T) {
+        if (e >= (unsigned)rstride || T.id >= n) return;
+        float o[3][W], kn[3][W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            float mm[3], xm[3], xp[3], a0[3], a1[3], b0[3], b1[3], h[3], mnn[3], kk[3], oo[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mm[a] = T.m[a][w];
+                xm[a] = w > 0 ? T.m[a][w - 1] : T.left[a];
+                xp[a] = w + 1 < W ? T.m[a][w + 1] : T.right[a];
+                a0[a] = T.y0[a][w];
+                a1[a] = T.y1[a][w];
+                b0[a] = T.z0[a][w];
+                b1[a] = T.z1[a][w];
+                h[a] = rows[a * rstride + e + w];
+                mnn[a] = T.mn[a][w];
+                kk[a] = T.ka[a][w];
+            }
+            stage_cell<STAGE>(mm, xm, xp, a0, a1, b0, b1, h, mnn, kk, oo, c);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                o[a][w] = oo[a];
+                kn[a][w] = kk[a];
+            }
+        }
+        const unsigned id = T.id;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float *oc = out + (size_t)a * n;
+            float *kc = kacc + (size_t)a * n;
+            float *hc = rows + a * rstride + e;
+            if constexpr (W == 1) {
+                if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) st32(kc, id, kn[a][0]);
+                st32(oc, id, o[a][0]);
+                if constexpr (FWD) hc[0] = o[a][0];
+            } else {
+                typedef typename VecOf<W>::T V;
+                V vo, vk;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    set_lane<W>(vo, w, o[a][w]);
+                    set_lane<W>(vk, w, kn[a][w]);
+                }
+                if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) stv32<V>(kc, id, vk);
+                stv32<V>(oc, id, vo);
+                if constexpr (FWD) *reinterpret_cast<V *>(hc) = vo;
+            }
+        }
+    };
+    // the first task's loads are in flight during the inverse transform
+    const unsigned e0 = (unsigned)t * W;
+    XsTask<W> T0;
+    T0.id = n;
+    (void)load_task(e0, T0);
 
     // 1. inverse C2R of rows ra, rb of component g (as xinv_body)
     {
@@ -101,107 +217,13 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
     }
     __syncthreads();
 
-    // 2. the stage on cells [r0 nx, (r0 + 2P) nx), W consecutive cells of a
-    // row per task (as stage_body_vec, with the field from LDS)
-    {
-        const unsigned nx = (unsigned)nx_, nxy = (unsigned)nx_ * (unsigned)ny;
-        const unsigned n = nxy * (unsigned)nz;
-        const unsigned base = (unsigned)r0 * nx;
-        for (unsigned e = (unsigned)t * W; e < (unsigned)rstride; e += blockDim.x * W) {
-            const unsigned id = base + e;
-            if (id >= n) break;
-            const unsigned k = id / nxy;
-            const unsigned rem = id - k * nxy;
-            const unsigned j = rem / nx;
-            const unsigned i = rem - j * nx;
-            const unsigned ym = j > 0 ? id - nx : id, yp = j + 1 < (unsigned)ny ? id + nx : id;
-            const unsigned zm = k > 0 ? id - nxy : id, zp = k + 1 < (unsigned)nz ? id + nxy : id;
-            float m[3][W], y0[3][W], y1[3][W], z0[3][W], z1[3][W], mn[3][W], ka[3][W], hd[3][W];
-            float left[3], right[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float *sc = S + (size_t)a * n;
-                const float *mc = Mn + (size_t)a * n;
-                const float *kc = kacc + (size_t)a * n;
-                const float *hc = rows + a * rstride + e;
-                if constexpr (W == 1) {
-                    m[a][0] = ld32(sc, id);
-                    y0[a][0] = ld32(sc, ym);
-                    y1[a][0] = ld32(sc, yp);
-                    z0[a][0] = ld32(sc, zm);
-                    z1[a][0] = ld32(sc, zp);
-                    mn[a][0] = ld32(mc, id);
-                    ka[a][0] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? ld32(kc, id) : 0.f;
-                    hd[a][0] = hc[0];
-                } else {
-                    typedef typename VecOf<W>::T V;
-                    const V vm = ldv32<V>(sc, id), vy0 = ldv32<V>(sc, ym), vy1 = ldv32<V>(sc, yp);
-                    const V vz0 = ldv32<V>(sc, zm), vz1 = ldv32<V>(sc, zp), vmn = ldv32<V>(mc, id);
-                    V vka;
-                    if constexpr (STAGE == 2 || STAGE == 3 || STAGE == 4) vka = ldv32<V>(kc, id);
-                    const V vh = *reinterpret_cast<const V *>(hc);
-#pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        m[a][w] = lane_of<W>(vm, w);
-                        y0[a][w] = lane_of<W>(vy0, w);
-                        y1[a][w] = lane_of<W>(vy1, w);
-                        z0[a][w] = lane_of<W>(vz0, w);
-                        z1[a][w] = lane_of<W>(vz1, w);
-                        mn[a][w] = lane_of<W>(vmn, w);
-                        ka[a][w] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? lane_of<W>(vka, w) : 0.f;
-                        hd[a][w] = lane_of<W>(vh, w);
-                    }
-                }
-                left[a] = i > 0 ? ld32(sc, id - 1) : m[a][0];
-                right[a] = i + W < nx ? ld32(sc, id + W) : m[a][W - 1];
-            }
-            float o[3][W], kn[3][W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                float mm[3], xm[3], xp[3], a0[3], a1[3], b0[3], b1[3], h[3], mnn[3], kk[3], oo[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    mm[a] = m[a][w];
-                    xm[a] = w > 0 ? m[a][w - 1] : left[a];
-                    xp[a] = w + 1 < W ? m[a][w + 1] : right[a];
-                    a0[a] = y0[a][w];
-                    a1[a] = y1[a][w];
-                    b0[a] = z0[a][w];
-                    b1[a] = z1[a][w];
-                    h[a] = hd[a][w];
-                    mnn[a] = mn[a][w];
-                    kk[a] = ka[a][w];
-                }
-                stage_cell<STAGE>(mm, xm, xp, a0, a1, b0, b1, h, mnn, kk, oo, c);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    o[a][w] = oo[a];
-                    kn[a][w] = kk[a];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                float *oc = out + (size_t)a * n;
-                float *kc = kacc + (size_t)a * n;
-                float *hc = rows + a * rstride + e;
-                if constexpr (W == 1) {
-                    if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) st32(kc, id, kn[a][0]);
-                    st32(oc, id, o[a][0]);
-                    if constexpr (FWD) hc[0] = o[a][0];
-                } else {
-                    typedef typename VecOf<W>::T V;
-                    V vo, vk;
-#pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        set_lane<W>(vo, w, o[a][w]);
-                        set_lane<W>(vk, w, kn[a][w]);
-                    }
-                    if constexpr (STAGE == 1 || STAGE == 2 || STAGE == 3) stv32<V>(kc, id, vk);
-                    stv32<V>(oc, id, vo);
-                    if constexpr (FWD) *reinterpret_cast<V *>(hc) = vo;
-                }
-            }
-        }
+    // 2. the stage on this thread's tasks; the first task's inputs were
+    // loaded before the inverse transform
+    stage_task(e0, T0);
+    for (unsigned e = e0 + blockDim.x * W; e < (unsigned)rstride; e += blockDim.x * W) {
+        XsTask<W> T;
+        if (!load_task(e, T)) break;
+        stage_task(e, T);
     }
     if constexpr (!FWD) return;
 

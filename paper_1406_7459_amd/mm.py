@@ -98,7 +98,7 @@ class SurStats(C.Structure):
 class PlanInfo(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("Lx", C.c_int),
                 ("Ly", C.c_int), ("Lz", C.c_int), ("spectrum_count", C.c_longlong),
-                ("workspace_bytes", C.c_longlong), ("cfg", C.c_int * 9)]
+                ("workspace_bytes", C.c_longlong), ("cfg", C.c_int * 9), ("tune_source", C.c_int)]
 
 
 _lib = None
@@ -285,7 +285,8 @@ class Plan:
         _check(lib().mm_plan_query(self._h, C.byref(inf)), "mm_plan_query")
         return dict(nx=inf.nx, ny=inf.ny, nz=inf.nz, Lx=inf.Lx, Ly=inf.Ly, Lz=inf.Lz,
                     spectrum_count=inf.spectrum_count, workspace_bytes=inf.workspace_bytes,
-                    tiles={PASSES[k]: inf.cfg[k] for k in range(NPASS)})
+                    tiles={PASSES[k]: inf.cfg[k] for k in range(NPASS)},
+                    tune_source=("default", "timed", "cache")[inf.tune_source])
 
     def spectrum(self, stream=None) -> torch.Tensor:
         """The stored K~ octant, float32 [nzK][Ly/2+1][Lx/2+1][6] (nzK = Lz/2+1,

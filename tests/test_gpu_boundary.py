@@ -171,3 +171,44 @@ def test_batch_workspace_binding():
     assert n.value == b.workspace.numel()
     ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
     assert mm.lib().mm_batch_bind_workspace(b._h, ws.data_ptr(), n.value - 256) == mm.MM_ENOMEM
+
+
+def test_tune_cache_hit_skips_timing(tmp_path, monkeypatch):
+    """With MM_TUNE_CACHE set, the first autotune of a grid times the
+    candidates and records them; a second plan of the same grid takes the
+    recorded tiles without timing; another grid is timed; an entry with a
+    tile the grid cannot launch is ignored."""
+    import json
+    import time
+    from paper_1406_7459_amd import mm
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("MM_TUNE_CACHE", str(path))
+    a = mm.Plan(32, 16, 8, 2e-9, 2e-9, 2e-9)
+    t0 = time.perf_counter()
+    ta = a.autotune(reps=2)
+    t_timed = time.perf_counter() - t0
+    assert a.info()["tune_source"] == "timed"
+    data = json.loads(path.read_text())
+    (key,) = [k for k in data if k.endswith("/32x16x8")]
+    assert data[key]["zconv"] == ta["zconv"] and data[key]["xstage"] == ta["xstage"]
+    b = mm.Plan(32, 16, 8, 2e-9, 2e-9, 2e-9)
+    t0 = time.perf_counter()
+    tb = b.autotune(reps=2)
+    t_cached = time.perf_counter() - t0
+    assert b.info()["tune_source"] == "cache"
+    assert tb == ta
+    say("tune timed %.3f s, cached %.4f s" % (t_timed, t_cached))
+    assert t_cached < 0.2 * t_timed
+    M = to_dev(8e5 * W.random_unit(32, 16, 8, seed=8))
+    assert np.array_equal(to_host(a.demag(M)), to_host(b.demag(M)))
+    c = mm.Plan(16, 16, 8, 2e-9, 2e-9, 2e-9)
+    c.autotune(reps=1)
+    assert c.info()["tune_source"] == "timed"
+    assert len(json.loads(path.read_text())) == 2
+    # an unlaunchable tile in the entry: ignored, the grid is timed again
+    data = json.loads(path.read_text())
+    data[key]["zconv"] = 4096
+    path.write_text("{\n" + ",\n".join('"%s": %s' % (k, json.dumps(v)) for k, v in data.items()) + "\n}\n")
+    d = mm.Plan(32, 16, 8, 2e-9, 2e-9, 2e-9)
+    d.autotune(reps=1)
+    assert d.info()["tune_source"] == "timed"

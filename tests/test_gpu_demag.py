@@ -59,27 +59,35 @@ def test_demag_film32_matches_direct_sum():
 
 def test_every_tile_gives_identical_field():
     """Launch tiles change only which workgroup does a transform, not its
-    arithmetic: all candidates must agree bitwise."""
+    arithmetic: all candidates of one radix order agree bitwise; the product
+    pass's alternative radix orders (tile variants 3 and 4) round
+    differently and agree with the default order within 1e-6."""
     from paper_1406_7459_amd import mm
-    for grid in [(24, 48, 6), (32, 16, 1)]:
+    for grid in [(24, 48, 6), (32, 16, 1), (16, 8, 32)]:
         nx, ny, nz = grid
         d = (2e-9, 2e-9, 2e-9)
         plan = mm.Plan(nx, ny, nz, *d)
         M = to_dev(8e5 * W.random_unit(nx, ny, nz, seed=7))
         ref = to_host(plan.demag(M))
-        import ctypes as C
         for pname in ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv"):
             default = plan.info()["tiles"][pname]
             if default == 0:
                 continue
-            for t in [P + 256 * var for var in (0, 1, 2) for P in (1, 2, 4, 8, 16, 32, 64, 128)]:
+            order_ref = {}
+            for t in [P + 256 * var for var in (0, 1, 2, 3, 4) for P in (1, 2, 4, 8, 16, 32, 64, 128)]:
                 try:
                     plan.set_tile(pname, t)
                 except mm.MMError:
                     continue
                 say("tile", grid, pname, t)
                 H = to_host(plan.demag(M))
-                assert np.array_equal(H, ref), (pname, t)
+                order = t >> 8 if pname in ("zconv", "yconv") and t >= 3 * 256 else 0
+                if order == 0:
+                    assert np.array_equal(H, ref), (pname, t)
+                else:
+                    assert rel_l2(H, ref) < 1e-6, (pname, t)
+                    order_ref.setdefault(order, H)
+                    assert np.array_equal(H, order_ref[order]), (pname, t)
             plan.set_tile(pname, default)
         plan.close()
 
