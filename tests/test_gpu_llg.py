@@ -227,7 +227,7 @@ def test_fused_stage_pass_is_bitwise_the_unfused_path(grid, integrator):
         plan.step(pg, M, n)
         ref[n] = to_host(M)
     tiles = []
-    for P in (1, 2, 4, 8, 16, 32, 64):
+    for P in [P + 256 * w for w in (0, 1, 2) for P in (1, 2, 4, 8, 16, 32, 64)]:
         try:
             plan.set_tile("xstage", P)
         except mm.MMError:
