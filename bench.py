@@ -340,14 +340,19 @@ def batch_measure(torch, mm, W, steps=10, warmup=2):
     M0 = [torch.from_numpy((w.mat.Ms * w.initial_unit()).astype("float32")).cuda() for w in wls]
     b = mm.Batch(shapes, [w.cell for w in wls])
     b.autotune(reps=3)
-    Mb = [m.clone() for m in M0]
-    b.step(params, Mb, warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(params, Mb, steps)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / steps
-    q = b.query()
+    modes = {}
+    for mode in ("grouped", "merged"):
+        b.set_mode(mode)
+        Mm = [m.clone() for m in M0]
+        b.step(params, Mm, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(params, Mm, steps)
+        torch.cuda.synchronize()
+        modes[mode] = dict(ms_per_step=(time.perf_counter() - t0) / steps * 1e3, query=b.query(), M=Mm)
+    tb = modes["merged"]["ms_per_step"] * 1e-3
+    Mb = modes["merged"]["M"]
+    q = modes["merged"]["query"]
     b.close()
     plans = [mm.Plan(*w.shape, *w.cell) for w in wls]
     for p in plans:
@@ -366,13 +371,17 @@ def batch_measure(torch, mm, W, steps=10, warmup=2):
     for p in plans:
         p.close()
     return {"workload": "sweep64 (64 films, nx,ny in {64..512}, nz in {1,2,4,8}, seed 4)",
-            "cells": cells, "groups": q["groups"], "launches_per_step": q["launches_per_step"],
+            "cells": cells, "mode": "merged (one launch per pass kind)",
+            "launch_kinds": q["groups"], "launches_per_step": q["launches_per_step"],
+            "grouped_mode": {"ms_per_step": modes["grouped"]["ms_per_step"],
+                             "groups": modes["grouped"]["query"]["groups"],
+                             "launches_per_step": modes["grouped"]["query"]["launches_per_step"]},
             "batched_ms_per_step": tb * 1e3, "looped_ms_per_step": tl * 1e3,
             "speedup_vs_looped_plain_fp32": tl / tb,
             "batched_cell_updates_per_s": cells / tb,
             "bitwise_equal_to_looped": same, "max_state_rel_l2_vs_looped": diff,
-            "note": "the batch runs the default radix orders; the looped plans' autotuner may pick "
-                    "other orders of the product pass, which round differently"}
+            "note": "the merged launches run radix order 1 for 3*2^a lengths; the looped plans' "
+                    "autotuner picks its own orders, which round differently"}
 
 
 def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):

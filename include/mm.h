@@ -227,18 +227,22 @@ int mm_plan_query(mm_plan plan, mm_plan_info *info);
 /* Set the launch configuration of one pass kind: tile = P + 256 * variant,
  * P = transforms per workgroup (x rows, or kx columns for y/z; a power of
  * two <= 128), variant = schedule: for the single-component passes 0 = the
- * default values per thread E, 1 = 2E; for the product passes (ZCONV, YCONV)
- * 0 = all three components in one thread's registers, 1 = one component per
- * thread group with the 3x3 product exchanged through LDS, 2 = as 1 with 2E.
+ * default values per thread E, 1 = 2E, 2 = radix order 1 (radix 16 first for
+ * lengths 2^a, radix 3 then 4s for 3*2^a), 3 = radix order 2 (radix 4 only,
+ * 2^a); for the product passes (ZCONV, YCONV) 0 = all three components in
+ * one thread's registers, 1 = one component per thread group with the 3x3
+ * product exchanged through LDS, 2 = as 1 with 2E, 3 and 4 = as 0 in radix
+ * orders 1 and 2.  Tiles of one radix order compute bitwise the same result;
+ * different orders agree to rounding.
  * For MM_PASS_STAGE the tile is the vector width W in {1, 2, 4}: W
  * consecutive cells of an x row per thread (nx % W == 0; default 4 when
  * nx % 4 == 0; a launch whose arrays are not aligned to 4W bytes falls back
- * to a narrower width).  For MM_PASS_XSTAGE the tile is P = 2^k pairs of
- * cell rows per workgroup of the fused pass that runs, per RK stage, the x
- * inverse of the field, the stage and the x forward of its result (the
- * field is never stored; the default), or 0 for the unfused path (XINV,
- * stage kernel, XFWD).  Every configuration computes bitwise the same
- * result.  Returns MM_EINVAL for a configuration the pass cannot launch.    */
+ * to a narrower width).  For MM_PASS_XSTAGE the tile is P + 256 w: P = 2^k
+ * pairs of cell rows per workgroup of the fused pass that runs, per RK
+ * stage, the x inverse of the field, the stage and the x forward of its
+ * result (the field is never stored; the default), with 2^w cells per stage
+ * task, or 0 for the unfused path (XINV, stage kernel, XFWD).  Returns
+ * MM_EINVAL for a configuration the pass cannot launch.                     */
 int mm_plan_set_tile(mm_plan plan, int pass, int tile);
 
 /* Time every candidate tile of every pass on this plan's buffers and keep
@@ -270,13 +274,18 @@ int mm_plan_timing(mm_plan plan, double *total_ms, long long *launches);
 
 /* ------------------------------------------------------------------------ *
  * Batches: many independent grids of uneven sizes (e.g. the points of a
- * field sweep) stepped together.  Each instance is a full plan; a batched
- * launch runs one pass kind for all instances sharing that pass's transform
- * length, its workgroups taking (instance, block) coordinates from a task
- * table; the whole step is replayed from one captured HIP graph.  Results
- * are bitwise those of the per-instance entry points.
+ * field sweep) stepped together.  Each instance is a full plan; the whole
+ * step is replayed from one captured HIP graph.  Two launch modes:
+ *   MM_BATCH_MERGED (default): one launch per pass kind over every instance
+ *     and transform length (a task table of (instance, block, length),
+ *     longest transform first; 3*2^a lengths in radix order 1): at most
+ *     4 x 7 launches per RK4 step.  Results are bitwise those of per-instance
+ *     plans whose tiles use the same radix orders.
+ *   MM_BATCH_GROUPED: one launch per (pass kind, transform length), each
+ *     group's tile tuned; bitwise the per-instance default results.
  * ------------------------------------------------------------------------ */
 typedef struct mm_batch_s *mm_batch;
+enum { MM_BATCH_GROUPED = 0, MM_BATCH_MERGED = 1 };
 
 /* Describe `count` plans (arrays of per-instance sizes and cells, host
  * memory; each instance as in mm_demag_setup) and their task tables.
@@ -305,14 +314,19 @@ int mm_batch_demag(mm_batch batch, const float *const *M_dev, float *const *H_de
  * instance table (synchronising) and re-captures the step graph.           */
 int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M_dev, int nsteps, void *stream);
 
-/* Tune the tile of every (pass, length) group on the batch's buffers: a
- * candidate is timed as `reps` complete batched demag evaluations (hipEvents
- * around the loop), the other groups keeping their tiles.  Overwrites the
- * instances' stage buffers.  Synchronises.                                  */
+/* Tune the tile of every (pass, length) group (the grouped mode's launches)
+ * on the batch's buffers: a candidate is timed as `reps` complete batched
+ * demag evaluations (hipEvents around the loop), the other groups keeping
+ * their tiles.  The mode is left as it was.  Overwrites the instances' stage
+ * buffers.  Synchronises.                                                   */
 int mm_batch_autotune(mm_batch batch, int reps, void *stream);
 
-/* Number of (pass, length) groups, kernel launches per RK4 step, total cells. */
+/* Number of launch groups of the current mode ((pass, length) groups, or
+ * pass kinds when merged), kernel launches per RK4 step, total cells.      */
 int mm_batch_query(mm_batch batch, int *groups, int *launches_per_step, long long *cells);
+
+/* Select the launch mode (MM_BATCH_MERGED or MM_BATCH_GROUPED).            */
+int mm_batch_set_mode(mm_batch batch, int mode);
 
 /* Pass kind (MM_PASS_*), transform length and tile of group `index`.       */
 int mm_batch_group_tile(mm_batch batch, int index, int *pass, int *length, int *tile);

@@ -705,8 +705,10 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
         }
     }
     // the fused pass's tiles and the unfused path (tile 0): each candidate
-    // timed as `reps` RK4 steps by direct launches on a zero state held in
-    // H (which the fused step never touches; the unfused one also writes its
+    // timed as `reps` replays of a captured one-step RK4 graph (the way
+    // mm_llg_step runs steps; the fused path has fewer launches, and only a
+    // replayed graph shows what that saves) on a zero state held in H
+    // (which the fused step never touches; the unfused one also writes its
     // field there, which changes the values but not the work)
     if (rc == MM_OK) {
         std::vector<int> cand = xstage_candidates(*p);
@@ -721,15 +723,27 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
         q.renorm = 1;
         const StageCoef c = stage_coef(*p, q);
         MMK_HIP(hipMemsetAsync(p->H, 0, sizeof(float) * 3 * (size_t)p->cells(), s));
+        MMK_HIP(hipStreamSynchronize(s));
         float best = 1e30f;
         int best_tile = p->tile[MM_PASS_XSTAGE];
         for (int t : cand) {
             if (cand.size() < 2) break;
             p->tile[MM_PASS_XSTAGE] = t;
-            if ((rc = llg_enqueue_step(*p, c, MM_RK4, p->H, s)) != MM_OK) break;  // warm-up
+            hipGraph_t g = nullptr;
+            hipGraphExec_t x = nullptr;
+            if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                rc = fail(MM_EHIP, "tune capture");
+                break;
+            }
+            rc = llg_enqueue_step(*p, c, MM_RK4, p->H, p->cap_stream);
+            hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+            if (rc == MM_OK && e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            if (rc == MM_OK && e != hipSuccess) rc = fail(MM_EHIP, std::string("tune graph: ") + hipGetErrorString(e));
+            if (rc == MM_OK && hipGraphLaunch(x, s) != hipSuccess) rc = fail(MM_EHIP, "tune graph launch");  // warm-up
             for (int rep = 0; rep < 3 && rc == MM_OK; ++rep) {
                 if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MM_EHIP, "event"); break; }
-                for (int r = 0; r < reps && rc == MM_OK; ++r) rc = llg_enqueue_step(*p, c, MM_RK4, p->H, s);
+                for (int r = 0; r < reps && rc == MM_OK; ++r)
+                    if (hipGraphLaunch(x, s) != hipSuccess) rc = fail(MM_EHIP, "tune graph launch");
                 if (rc != MM_OK) break;
                 if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     rc = fail(MM_EHIP, "event");
@@ -742,6 +756,9 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
                     best_tile = t;
                 }
             }
+            (void)hipStreamSynchronize(s);  // no replay in flight when its graph goes
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
             if (rc != MM_OK) break;
             ++tuned;
         }

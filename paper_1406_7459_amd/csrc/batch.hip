@@ -8,10 +8,16 @@
 // L2).  A whole RK4 step is a
 // fixed sequence of such launches and is captured once into a HIP graph.
 //
-// Grouping by length keeps each launch's register and LDS budget that of its
-// own length (a single launch over every length would size both for the
-// largest).  The launch tile of every (pass, length) group is tuned on the
-// batch's own buffers.
+// Two launch modes.  Merged: one launch per pass kind over every instance
+// and every transform length, 128 threads a workgroup, a task naming its
+// instance, block and length; each length runs in the radix order of at most
+// 12 values per thread (order 1 for 3 2^a lengths); the product passes (z,
+// and y for nz = 1) share one launch per register class of their schedules
+// (at most 8 values per thread, 12), so the z passes of most instances are
+// not sized for the 12-value schedules; tasks are ordered longest transform
+// first.  At most 7 launches per stage.  Grouped: one launch
+// per (pass kind, transform length), each group with its own tuned tile in
+// the default radix orders.
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -101,6 +107,96 @@ __global__ __launch_bounds__(256) void kb_copy(const BInst *__restrict__ B, cons
     for (size_t i = (size_t)t.y * 768 + threadIdx.x; i < n3 && i < (size_t)(t.y + 1) * 768; i += 256) I.M[i] = I.Sa[i];
 }
 
+// ------------------------------------------------------------- merged ---
+// (a power of two no larger than the largest tile P, 128, so that a length
+// with one thread per transform still fits the tile encoding)
+constexpr int BM_THREADS = 128;
+
+// schedule variant of length L in the merged launches: radix order 1 (radix
+// 3 then 4s, 12 values per thread) for 3 2^a lengths, the default otherwise
+template <int L> constexpr bool bm_alt() { return L >= 24 && L % 3 == 0; }
+template <int L> constexpr int bm_var() { return bm_alt<L>() ? 2 : 0; }     // single-component passes
+template <int L> constexpr int bm_cvar() { return bm_alt<L>() ? 3 : 0; }    // product passes
+template <int L> constexpr int bm_e()
+{
+    if constexpr (bm_alt<L>()) return Factors<L, 1>::E;
+    else return Factors<L>::E;
+}
+template <int L> constexpr int bm_lp2()
+{
+    int lp = 0;
+    while ((1 << lp) * (L / bm_e<L>()) < BM_THREADS) ++lp;
+    return lp;
+}
+
+// Launch slots of the merged mode: the x and y passes one launch each; the
+// product passes (z for nz > 1, y for nz = 1) one launch per register class
+// of their schedules (at most 8 values per thread, and 12), so the smaller
+// lengths' launch is not sized for the larger schedules' registers.
+enum { MS_XFWD = 0, MS_YFWD = 1, MS_CONV_A = 2, MS_CONV_B = 3, MS_YINV = 4, MS_XINV = 5, MS_COUNT = 6 };
+template <int L> constexpr int bm_class() { return bm_e<L>() > 8 ? 1 : 0; }
+constexpr int BM_YCONV = 1 << 16;  // task flag: product along y (nz = 1)
+
+// t = (instance, block, plane or ky, transform length [| BM_YCONV])
+template <int SLOT, int L>
+__device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
+{
+    constexpr int V = bm_var<L>(), lp2 = bm_lp2<L>();
+    if constexpr (SLOT == MS_XFWD) xfwd_body<L, V>(bsel(I, sel), I.X1, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
+    else if constexpr (SLOT == MS_YFWD) yfwd_body<L, V>(I.X1, I.X2, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z);
+    else if constexpr (SLOT == MS_YINV) yinv_body<L, V>(I.X2, I.X1, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z);
+    else if constexpr (SLOT == MS_XINV) xinv_body<L, V>(I.X1, I.Hout, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
+    else if constexpr (bm_class<L>() == SLOT - MS_CONV_A) {
+        constexpr int O = bm_alt<L>() ? 1 : 0;
+        if (t.w & BM_YCONV)
+            conv_reg3_body<L, false, O>(I.X1, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.ny, lp2, I.tw1, t.y, 0);
+        else
+            conv_reg3_body<L, true, O>(I.X2, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.nz, lp2, I.tw2, t.y, t.z);
+    }
+}
+
+#define MMK_BM_LENGTHS(X)                                                                                \
+    X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) \
+        X(768) X(1024)
+
+template <int SLOT>
+__global__ __launch_bounds__(BM_THREADS) void kb_merged(const BInst *__restrict__ B, const int4 *__restrict__ T,
+                                                         int sel)
+{
+    const bool rows = SLOT == MS_XFWD || SLOT == MS_XINV;
+    const int4 t = T[rows ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x)];
+    const BInst &I = B[t.x];
+    switch (t.w & (BM_YCONV - 1)) {
+#define MMK_CASE(LEN) case LEN: bm_run<SLOT, LEN>(I, t, sel); break;
+        MMK_BM_LENGTHS(MMK_CASE)
+#undef MMK_CASE
+    default: break;
+    }
+}
+
+// P, variant and tile of length L in the merged launches (host side)
+static int bm_tile(int pass, int L)
+{
+    switch (L) {
+#define MMK_CASE(LEN) \
+    case LEN: return (1 << bm_lp2<LEN>()) + 256 * (pass == MM_PASS_ZCONV || pass == MM_PASS_YCONV ? bm_cvar<LEN>() : bm_var<LEN>());
+        MMK_BM_LENGTHS(MMK_CASE)
+#undef MMK_CASE
+    default: return 0;
+    }
+}
+
+// register class (merged product launch) of length L
+static int bm_class_of(int L)
+{
+    switch (L) {
+#define MMK_CASE(LEN) case LEN: return bm_class<LEN>();
+        MMK_BM_LENGTHS(MMK_CASE)
+#undef MMK_CASE
+    default: return 0;
+    }
+}
+
 // ---------------------------------------------------------------- host ---
 struct BGroup {
     int pass = 0, L = 0, tile = 0;
@@ -129,6 +225,8 @@ struct BatchImpl {
     size_t bytes = 0;                // workspace bytes
     std::vector<size_t> plan_bytes;  // per-instance plan workspace
     char *ws = nullptr;              // bound workspace (nullptr: unbound)
+    bool merged = true;              // launch mode
+    BGroup mg[MS_COUNT];             // merged launch per slot (tile unused)
 };
 
 static int pass_len_of(const BInst &I, int pass)
@@ -145,6 +243,14 @@ static int pass_len_of(const BInst &I, int pass)
 }
 
 static int launch_group(const BGroup &g, const BInst *table, int sel, hipStream_t s, bool raise_only);
+
+// tile variants in the default radix order: single-component passes 0, 1;
+// product passes 0, 1, 2
+static bool default_order(int pass, int tile)
+{
+    const int var = tile >> 8;
+    return (pass == MM_PASS_ZCONV || pass == MM_PASS_YCONV) ? var <= 2 : var <= 1;
+}
 
 static void make_tasks(const BatchImpl &b, const BGroup &g, int tile, std::vector<int4> &tasks)
 {
@@ -190,6 +296,72 @@ static int build_tasks(BatchImpl &b, BGroup &g)
     int maxt;
     shape_for(g.pass, g.L, g.tile, g.threads, g.lds, maxt);
     return launch_group(g, nullptr, 0, nullptr, true);  // raise the LDS limit if this tile needs it
+}
+
+// Task table of merged launch slot `slot`: every instance with the pass
+// active (and, for a product slot, its length in the slot's register class),
+// longest transform first, each with its length's tile; the launch's LDS is
+// the largest any of its lengths needs.
+static void make_merged(BatchImpl &b, int slot)
+{
+    BGroup &g = b.mg[slot];
+    g.tasks.clear();
+    g.lds = 0;
+    const bool conv = slot == MS_CONV_A || slot == MS_CONV_B;
+    auto pass_of = [&](const BInst &I) {
+        switch (slot) {
+        case MS_XFWD: return (int)MM_PASS_XFWD;
+        case MS_YFWD: return (int)MM_PASS_YFWD;
+        case MS_YINV: return (int)MM_PASS_YINV;
+        case MS_XINV: return (int)MM_PASS_XINV;
+        default: return I.nz > 1 ? (int)MM_PASS_ZCONV : (int)MM_PASS_YCONV;
+        }
+    };
+    auto len_of = [&](const BInst &I) {
+        const int L = pass_len_of(I, pass_of(I));
+        if (conv && L && bm_class_of(L) != slot - MS_CONV_A) return 0;
+        return L;
+    };
+    std::vector<int> order;
+    for (int i = 0; i < b.count; ++i)
+        if (len_of(b.inst[i])) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return len_of(b.inst[a]) > len_of(b.inst[c]); });
+    for (int i : order) {
+        const BInst &I = b.inst[i];
+        const int pass = pass_of(I);
+        const int L = len_of(I);
+        const int tile = bm_tile(pass, L), P = tile & 255;
+        int threads = 0, maxt = 0;
+        size_t lds = 0;
+        shape_for(pass, L, tile, threads, lds, maxt);
+        g.lds = std::max(g.lds, lds);
+        const int nxc = I.Lx / 2 + 1, ncr = I.nz * I.ny;
+        switch (pass) {
+        case MM_PASS_XFWD:
+        case MM_PASS_XINV: {
+            const int pairs = 3 * ((ncr + 1) / 2);
+            for (int bx = 0; bx < (pairs + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, L));
+            break;
+        }
+        case MM_PASS_YFWD:
+        case MM_PASS_YINV:
+            for (int pl = 0; pl < 3 * I.nz; ++pl)
+                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, pl, L));
+            break;
+        case MM_PASS_ZCONV:
+            for (int m = 0; m < I.Ly / 2; ++m)
+                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx)
+                    for (int h = 0; h < 2; ++h)
+                        g.tasks.push_back(make_int4(i, bx, ky_of_slot(2 * m + h, I.Ly / 2), L));
+            break;
+        case MM_PASS_YCONV:
+            for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, 0, L | BM_YCONV));
+            break;
+        default: break;
+        }
+    }
+    g.cap = g.tasks.size();
 }
 
 static int ilog2i(int v)
@@ -268,8 +440,34 @@ static int launch_group(const BGroup &g, const BInst *table, int sel, hipStream_
 static const int DEMAG_ORDER[6] = {MM_PASS_XFWD, MM_PASS_YFWD, MM_PASS_ZCONV, MM_PASS_YCONV, MM_PASS_YINV,
                                    MM_PASS_XINV};
 
+static int merged_launch(const BatchImpl &b, int slot, const BInst *table, int sel, hipStream_t s)
+{
+    const BGroup &g = b.mg[slot];
+    if (g.tasks.empty()) return MM_OK;
+    const dim3 grid((unsigned)g.tasks.size()), block(BM_THREADS);
+    switch (slot) {
+    case MS_XFWD: hipLaunchKernelGGL(kb_merged<MS_XFWD>, grid, block, g.lds, s, table, g.d, sel); break;
+    case MS_YFWD: hipLaunchKernelGGL(kb_merged<MS_YFWD>, grid, block, g.lds, s, table, g.d, sel); break;
+    case MS_CONV_A: hipLaunchKernelGGL(kb_merged<MS_CONV_A>, grid, block, g.lds, s, table, g.d, sel); break;
+    case MS_CONV_B: hipLaunchKernelGGL(kb_merged<MS_CONV_B>, grid, block, g.lds, s, table, g.d, sel); break;
+    case MS_YINV: hipLaunchKernelGGL(kb_merged<MS_YINV>, grid, block, g.lds, s, table, g.d, sel); break;
+    case MS_XINV: hipLaunchKernelGGL(kb_merged<MS_XINV>, grid, block, g.lds, s, table, g.d, sel); break;
+    default: break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MM_EHIP, std::string("batch merged launch: ") + hipGetErrorString(e));
+    return MM_OK;
+}
+
 static int batch_demag_enqueue(BatchImpl &b, const BInst *table, int sel, hipStream_t s)
 {
+    if (b.merged) {
+        for (int slot = 0; slot < MS_COUNT; ++slot) {
+            int rc = merged_launch(b, slot, table, sel, s);
+            if (rc != MM_OK) return rc;
+        }
+        return MM_OK;
+    }
     for (int pass : DEMAG_ORDER)
         for (const BGroup &g : b.groups)
             if (g.pass == pass) {
@@ -328,6 +526,16 @@ static void free_batch(BatchImpl *b)
     delete b;
 }
 
+static void raise_merged_lds(BatchImpl &b)
+{
+    const void *k[MS_COUNT] = {(const void *)kb_merged<MS_XFWD>,   (const void *)kb_merged<MS_YFWD>,
+                               (const void *)kb_merged<MS_CONV_A>, (const void *)kb_merged<MS_CONV_B>,
+                               (const void *)kb_merged<MS_YINV>,   (const void *)kb_merged<MS_XINV>};
+    for (int slot = 0; slot < MS_COUNT; ++slot)
+        if (b.mg[slot].lds > 65536)
+            (void)hipFuncSetAttribute(k[slot], hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.mg[slot].lds);
+}
+
 }  // namespace mmk
 
 using namespace mmk;
@@ -384,7 +592,7 @@ int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const
             g.L = L;
             g.tile = default_tile_for(pass, L, b->lds_limit);
             for (int t : tile_candidates_for(pass, L, b->lds_limit)) {
-                if ((t >> 8) > 2) continue;  // the batch runs the default radix orders
+                if (!default_order(pass, t)) continue;  // the groups run the default radix orders
                 make_tasks(*b, g, t, scratch);
                 g.cap = std::max(g.cap, scratch.size());
             }
@@ -393,8 +601,10 @@ int mm_batch_setup(int count, const int *nx, const int *ny, const int *nz, const
             b->groups.push_back(g);
         }
     }
+    for (int slot = 0; slot < MS_COUNT; ++slot) make_merged(*b, slot);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t total = 0;
+    for (int slot = 0; slot < MS_COUNT; ++slot) total += al(sizeof(int4) * b->mg[slot].tasks.size());
     for (int i = 0; i < count; ++i) {
         size_t pb = 0;
         mm_plan_workspace_bytes(b->plans[i], &pb);
@@ -450,6 +660,15 @@ int mm_batch_bind_workspace(mm_batch batch, void *ws, size_t bytes)
         cur += al(sizeof(int4) * g.cap);
         if ((rc = build_tasks(b, g)) != MM_OK) return rc;
     }
+    for (int slot = 0; slot < MS_COUNT; ++slot) {
+        BGroup &g = b.mg[slot];
+        g.d = (int4 *)cur;
+        cur += al(sizeof(int4) * g.tasks.size());
+        if (!g.tasks.empty())
+            MMK_HIP(hipMemcpy(g.d, g.tasks.data(), sizeof(int4) * g.tasks.size(), hipMemcpyHostToDevice));
+        if (g.lds > b.lds_limit) return fail(MM_EINVAL, "batch: merged launch needs more LDS than the device has");
+    }
+    raise_merged_lds(b);
     b.d_inst = (BInst *)cur; cur += al(sizeof(BInst) * b.count);
     b.d_io = (BInst *)cur; cur += al(sizeof(BInst) * b.count);
     b.d_stage = (int2 *)cur; cur += al(sizeof(int2) * b.stage_tasks.size());
@@ -527,7 +746,7 @@ int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M, 
         b.bound_params = pkey;
         drop_graph(b);
     }
-    std::string key = std::to_string(integrator);
+    std::string key = std::to_string(integrator) + (b.merged ? "m" : "g");
     for (const BGroup &g : b.groups) key += "," + std::to_string(g.tile);
     if (!b.exec || b.key != key) {
         drop_graph(b);
@@ -571,6 +790,8 @@ int mm_batch_autotune(mm_batch batch, int reps, void *stream)
     MMK_HIP(hipEventCreate(&e0));
     MMK_HIP(hipEventCreate(&e1));
     int rc = MM_OK, tuned = 0;
+    const bool was_merged = b.merged;
+    b.merged = false;  // the groups' tiles are what there is to tune
     // a candidate is timed as `reps` complete batched demag evaluations
     // (every group launched in step order, events only around the loop), so
     // it is judged in the cache state and launch overlap of a real step
@@ -579,7 +800,7 @@ int mm_batch_autotune(mm_batch batch, int reps, void *stream)
         float best = 1e30f;
         int best_tile = keep;
         for (int t : tile_candidates_for(g.pass, g.L, b.lds_limit)) {
-            if ((t >> 8) > 2) continue;  // the batch runs the default radix orders
+            if (!default_order(g.pass, t)) continue;  // the groups run the default radix orders
             g.tile = t;
             if ((rc = build_tasks(b, g)) != MM_OK) break;
             if ((rc = batch_demag_enqueue(b, b.d_inst, 1, s)) != MM_OK) break;
@@ -604,6 +825,7 @@ int mm_batch_autotune(mm_batch batch, int reps, void *stream)
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    b.merged = was_merged;
     drop_graph(b);
     if (rc != MM_OK) return rc;
     return tuned ? MM_OK : fail(MM_ETUNE, "batch: no candidate ran");
@@ -613,13 +835,24 @@ int mm_batch_query(mm_batch batch, int *groups, int *launches_per_step, long lon
 {
     if (!batch || !batch->impl) return fail(MM_EINVAL, "NULL batch");
     BatchImpl &b = *batch->impl;
-    if (groups) *groups = (int)b.groups.size();
-    if (launches_per_step) *launches_per_step = 4 * ((int)b.groups.size() + 1);
+    int kinds = 0;
+    for (int slot = 0; slot < MS_COUNT; ++slot) kinds += b.mg[slot].tasks.empty() ? 0 : 1;
+    if (groups) *groups = b.merged ? kinds : (int)b.groups.size();
+    if (launches_per_step) *launches_per_step = 4 * ((b.merged ? kinds : (int)b.groups.size()) + 1);
     if (cells) {
         long long c = 0;
         for (const BInst &I : b.inst) c += (long long)I.nx * I.ny * I.nz;
         *cells = c;
     }
+    return MM_OK;
+}
+
+int mm_batch_set_mode(mm_batch batch, int mode)
+{
+    if (!batch || !batch->impl) return fail(MM_EINVAL, "NULL batch");
+    if (mode != MM_BATCH_GROUPED && mode != MM_BATCH_MERGED) return fail(MM_EINVAL, "unknown batch mode");
+    batch->impl->merged = mode == MM_BATCH_MERGED;
+    drop_graph(*batch->impl);
     return MM_OK;
 }
 

@@ -81,8 +81,9 @@ __global__ __launch_bounds__(1024) void k_xinv(const float2 *__restrict__ X1, fl
 // A launch configuration ("tile") is P + 256 * variant: P transforms (rows
 // for x, kx columns for y/z) per workgroup, a power of two, and a schedule
 // variant: for the single-component passes 0 = default values per thread E,
-// 1 = 2E; for the product passes 0 = reg3, 1 = split (E), 2 = split (2E),
-// 3 = reg3 in radix order 1, 4 = reg3 in radix order 2 (fft_engine.hpp).
+// 1 = 2E, 2 = radix order 1, 3 = radix order 2; for the product passes 0 =
+// reg3, 1 = split (E), 2 = split (2E), 3 = reg3 in radix order 1, 4 = reg3 in
+// radix order 2 (fft_engine.hpp).
 
 static int ilog2(int v)
 {
@@ -190,9 +191,10 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
             return false;
         }
     } else {
-        if (var != 0 && var != 1) return false;
+        if (var < 0 || var > 3) return false;
         if (var == 1 && k.E1 == k.E0) return false;
-        const int E = var == 0 ? k.E0 : k.E1;
+        if (var >= 2 && !k.Eo[var - 1]) return false;
+        const int E = var == 0 ? k.E0 : (var == 1 ? k.E1 : k.Eo[var - 1]);
         threads = P * (L / E);
         // the x forward separates its packed rows through LDS even for one stage
         const bool needs = k.nstage > 1 || pass == MM_PASS_XFWD;
@@ -216,7 +218,7 @@ bool tile_valid_for(int pass, int L, int tile, size_t lds_limit)
 std::vector<int> tile_candidates_for(int pass, int L, size_t lds_limit)
 {
     std::vector<int> out;
-    for (int var = 0; var < 5; ++var)
+    for (int var = 0; var < (is_conv(pass) ? 5 : 4); ++var)
         for (int P = 1; P <= 128; P *= 2) {
             const int tile = P + 256 * var;
             if (!tile_valid_for(pass, L, tile, lds_limit)) continue;
@@ -321,9 +323,24 @@ int prepare_kernels(Plan &p)
     return MM_OK;
 }
 
+template <typename K>
+static void raise_for(K kern, size_t lds)
+{
+    if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <int L, int V>
 static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, float *H, hipStream_t s)
 {
+    if constexpr (V >= 2) {
+        switch (pass) {
+        case MM_PASS_XFWD: raise_for(k_xfwd<L, V>, lds); break;
+        case MM_PASS_YFWD: raise_for(k_yfwd<L, V>, lds); break;
+        case MM_PASS_YINV: raise_for(k_yinv<L, V>, lds); break;
+        case MM_PASS_XINV: raise_for(k_xinv<L, V>, lds); break;
+        default: break;
+        }
+    }
     constexpr int Q = L / ept<L, V>();
     const int lp2 = ilog2(P);
     const dim3 block(P * Q);
@@ -402,7 +419,9 @@ static void launch_len(Plan &p, int pass, int tile, size_t lds, const float *M, 
     const int P = tile & 255, var = tile >> 8;
     if (is_conv(pass)) launch_conv<L>(p, pass, P, var, lds, s);
     else if (var == 0) launch_single<L, 0>(p, pass, P, lds, M, H, s);
-    else launch_single<L, 1>(p, pass, P, lds, M, H, s);
+    else if (var == 1) launch_single<L, 1>(p, pass, P, lds, M, H, s);
+    else if (var == 2) { if constexpr (variant_valid<L, 2>()) launch_single<L, 2>(p, pass, P, lds, M, H, s); }
+    else if (var == 3) { if constexpr (variant_valid<L, 3>()) launch_single<L, 3>(p, pass, P, lds, M, H, s); }
 }
 
 int launch_pass(Plan &p, int pass, const float *M, float *H, hipStream_t s)

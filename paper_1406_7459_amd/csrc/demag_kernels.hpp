@@ -74,6 +74,7 @@ template <int L, int V>
 __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *__restrict__ X1, int ncr, int nx,
                                           int lp2, const float2 *__restrict__ tw, int bx)
 {
+    constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
@@ -87,7 +88,7 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
     float2 *col = lds + tw_slots<L>() + p * XS;
     const LdsView s{lds + tw_slots<L>(), 1, p * XS};
     float2 v[E];
-    constexpr int R0 = first_radix<L, false>();
+    constexpr int R0 = first_radix<L, false, OV>();
     const float *sa = M + (size_t)ra * nx;
     const float *sb = M + (size_t)rb * nx;
 #pragma unroll
@@ -99,8 +100,8 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
             const bool in = !upper && i < nx;
             v[b * R0 + r] = make_float2(in && oka ? sa[i] : 0.f, in && okb ? sb[i] : 0.f);
         }
-    fft_e<L, E, -1, false>(v, s, q, twl);
-    constexpr int RL = last_radix<L, false>();
+    fft_e<L, E, -1, false, OV>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false, OV>();
     // the last exchange ended with a barrier: the column is free for Z
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
@@ -130,6 +131,7 @@ template <int L, int V>
 __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc, int ny,
                                           int lp2, const float2 *__restrict__ tw, int bx, int plane)
 {
+    constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
@@ -141,7 +143,7 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
     const int xp = x_pitch(nxc);
     const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
-    constexpr int R0 = first_radix<L, false>();
+    constexpr int R0 = first_radix<L, false, OV>();
     // this thread's row q; the other rows are compile-time multiples of the
     // (uniform) row pitch away
     const float2 *src = X1 + ((size_t)plane * ny + q) * xp + kx;
@@ -154,8 +156,8 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
             v[b * R0 + r] = (!upper && ok && j < ny) ? float2(src[(size_t)(Q * b + r * (L / R0)) * xp])
                                                      : make_float2(0.f, 0.f);
         }
-    fft_e<L, E, -1, false>(v, s, q, twl);
-    constexpr int RL = last_radix<L, false>();
+    fft_e<L, E, -1, false, OV>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false, OV>();
     float2 *dst = X2 + ((size_t)plane * L + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
@@ -404,6 +406,7 @@ template <int L, int V>
 __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc, int ny,
                                           int lp2, const float2 *__restrict__ tw, int bx, int plane)
 {
+    constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
@@ -415,15 +418,15 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
     const int xp = x_pitch(nxc);
     const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
-    constexpr int R0 = first_radix<L, false>();
+    constexpr int R0 = first_radix<L, false, OV>();
     const float2 *src = X2 + ((size_t)plane * L + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
         for (int r = 0; r < R0; ++r)
             v[b * R0 + r] = ok ? float2(src[(size_t)(Q * b + r * (L / R0)) * xp]) : make_float2(0.f, 0.f);
-    fft_e<L, E, +1, false>(v, s, q, twl);
-    constexpr int RL = last_radix<L, false>();
+    fft_e<L, E, +1, false, OV>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false, OV>();
     float2 *dst = X1 + ((size_t)plane * ny + q) * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
@@ -442,6 +445,7 @@ template <int L, int V>
 __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *__restrict__ H, int ncr, int nx,
                                           int lp2, const float2 *__restrict__ tw, int bx)
 {
+    constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
@@ -455,7 +459,7 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
     const float2 *sa = X1 + (size_t)ra * XP;
     const float2 *sb = X1 + (size_t)rb * XP;
     float2 v[E];
-    constexpr int R0 = first_radix<L, false>();
+    constexpr int R0 = first_radix<L, false, OV>();
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -475,8 +479,8 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
             }
             v[b * R0 + r] = make_float2(A.x - B.y, A.y + B.x);
         }
-    fft_e<L, E, +1, false>(v, s, q, twl);
-    constexpr int RL = last_radix<L, false>();
+    fft_e<L, E, +1, false, OV>(v, s, q, twl);
+    constexpr int RL = last_radix<L, false, OV>();
     float *da = H + (size_t)ra * nx;
     float *db = H + (size_t)rb * nx;
 #pragma unroll

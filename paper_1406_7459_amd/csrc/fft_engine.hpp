@@ -344,10 +344,10 @@ __device__ __forceinline__ void fft_pp(float2 (&v)[E], const LdsView &s0, const 
 // row q + Q*b + r*L/RL with RL = last_radix<L,REV>.  Every thread of the
 // workgroup must call it (it contains barriers when the transform has more
 // than one stage).
-template <int L, int E, int DIR, bool REV>
+template <int L, int E, int DIR, bool REV, int O = 0>
 __device__ __forceinline__ void fft_e(float2 (&v)[E], const LdsView &s, int q, const float2 *__restrict__ tw)
 {
-    run_stages<L, E, DIR, REV, 0>(v, s, q, tw);
+    run_stages<L, E, DIR, REV, 0, O>(v, s, q, tw);
 }
 
 template <int L, int DIR, bool REV>
@@ -359,9 +359,22 @@ __device__ __forceinline__ void fft(float2 (&v)[Factors<L>::E], const LdsView &s
 
 // Values per thread of variant V of length L: V = 0 the default E, V = 1
 // twice as many (half the threads per transform, wider tiles per workgroup).
+// Schedule variant V of a single-component pass: 0 = order 0 with E values
+// per thread, 1 = order 0 with 2E, 2 = order 1, 3 = order 2 (each with its
+// own E).  order_of_v gives the radix order, ept the values per thread.
+template <int V> constexpr int order_of_v() { return V == 2 ? 1 : (V == 3 ? 2 : 0); }
 template <int L, int V> constexpr int ept()
 {
-    return (V == 1 && 2 * Factors<L>::E <= L) ? 2 * Factors<L>::E : Factors<L>::E;
+    if constexpr (V == 2 && Factors<L, 1>::valid) return Factors<L, 1>::E;
+    else if constexpr (V == 3 && Factors<L, 2>::valid) return Factors<L, 2>::E;
+    else return (V == 1 && 2 * Factors<L>::E <= L) ? 2 * Factors<L>::E : Factors<L>::E;
+}
+template <int L, int V> constexpr bool variant_valid()
+{
+    if constexpr (V == 2) return Factors<L, 1>::valid;
+    else if constexpr (V == 3) return Factors<L, 2>::valid;
+    else if constexpr (V == 1) return 2 * Factors<L>::E <= L;
+    else return true;
 }
 
 }  // namespace mmk

@@ -31,7 +31,7 @@ SYMBOLS = ("mm_demag_setup", "mm_plan_workspace_bytes", "mm_plan_bind_workspace"
            "mm_plan_set_timing", "mm_plan_timing", "mm_destroy", "mm_status_string",
            "mm_last_error", "mm_batch_setup", "mm_batch_workspace_bytes",
            "mm_batch_bind_workspace", "mm_batch_demag", "mm_batch_step",
-           "mm_batch_autotune", "mm_batch_query", "mm_batch_group_tile", "mm_batch_destroy",
+           "mm_batch_autotune", "mm_batch_query", "mm_batch_set_mode", "mm_batch_group_tile", "mm_batch_destroy",
            "mm_sur_create", "mm_sur_workspace_bytes", "mm_sur_bind_workspace", "mm_sur_attach",
            "mm_sur_param_count", "mm_sur_set_params", "mm_sur_get_params",
            "mm_sur_zero", "mm_sur_forward", "mm_sur_gradients", "mm_sur_train_step",
@@ -142,6 +142,7 @@ def lib():
     L.mm_batch_step.argtypes = [vp, C.POINTER(LLGParams), C.POINTER(vp), i, vp]
     L.mm_batch_autotune.argtypes = [vp, i, vp]
     L.mm_batch_query.argtypes = [vp, ip, ip, C.POINTER(C.c_longlong)]
+    L.mm_batch_set_mode.argtypes = [vp, i]
     L.mm_batch_group_tile.argtypes = [vp, i, ip, ip, ip]
     L.mm_batch_destroy.argtypes = [vp]
     L.mm_batch_destroy.restype = None
@@ -378,6 +379,10 @@ class Batch:
     def autotune(self, reps=5, stream=None):
         _check(lib().mm_batch_autotune(self._h, int(reps), _stream(stream)), "mm_batch_autotune")
         return self.groups()
+
+    def set_mode(self, mode: str):
+        """'merged' (one launch per pass kind) or 'grouped' (per pass and length)."""
+        _check(lib().mm_batch_set_mode(self._h, 1 if mode == "merged" else 0), "mm_batch_set_mode")
 
     def query(self):
         g, n, c = C.c_int(), C.c_int(), C.c_longlong()

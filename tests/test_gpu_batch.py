@@ -1,5 +1,7 @@
-"""Batched form: many grids of uneven sizes stepped by grouped launches must
-give bitwise the per-instance results (same kernel bodies, same arithmetic)."""
+"""Batched form: many grids of uneven sizes stepped by merged launches (one
+per pass kind) or grouped launches (one per pass kind and length) must give
+bitwise the per-instance results when the per-instance plans run the same
+radix orders (same kernel bodies, same arithmetic)."""
 import numpy as np
 import pytest
 
@@ -12,7 +14,7 @@ SMALL = [((16, 24, 1), (4e-9, 4e-9, 2e-9)), ((32, 16, 2), (4e-9, 4e-9, 2e-9)),
          ((24, 48, 4), (4e-9, 4e-9, 2e-9)), ((16, 16, 8), (4e-9, 4e-9, 2e-9)),
          ((48, 32, 1), (4e-9, 4e-9, 2e-9)), ((32, 32, 2), (2e-9, 2e-9, 2e-9)),
          ((12, 6, 3), (1e-9, 1.3e-9, 0.7e-9)), ((64, 8, 1), (4e-9, 4e-9, 2e-9)),
-         ((1, 1, 1), (2e-9, 2e-9, 2e-9))]
+         ((1, 1, 1), (2e-9, 2e-9, 2e-9)), ((96, 12, 12), (2e-9, 2e-9, 2e-9))]
 
 
 def _params(mm, i, integrator="rk4"):
@@ -20,15 +22,52 @@ def _params(mm, i, integrator="rk4"):
                              Hext=(1e4 * (i - 4), 2e3 * i, -5e3), dt=1e-14, integrator=integrator)
 
 
-def test_batched_demag_is_bitwise_per_instance():
+def _alt(L):
+    return L >= 24 and L % 3 == 0
+
+
+def _set_variant(mm, plan, pname, var):
+    for P in (16, 8, 4, 2, 1, 32, 64, 128):
+        try:
+            plan.set_tile(pname, P + 256 * var)
+            return
+        except mm.MMError:
+            continue
+    raise AssertionError("no tile of variant %d for %s" % (var, pname))
+
+
+def _plan(mm, s, d, mode):
+    """A per-instance plan running the radix orders the batch's mode runs:
+    merged launches take order 1 for transform lengths 3 * 2^a >= 24."""
+    plan = mm.Plan(*s, *d)
+    if mode == "merged":
+        inf = plan.info()
+        if _alt(inf["Lx"]):
+            plan.set_tile("xstage", 0)
+            _set_variant(mm, plan, "xfwd", 2)
+            _set_variant(mm, plan, "xinv", 2)
+        if _alt(inf["Ly"]):
+            if s[2] > 1:
+                _set_variant(mm, plan, "yfwd", 2)
+                _set_variant(mm, plan, "yinv", 2)
+            else:
+                _set_variant(mm, plan, "yconv", 3)
+        if s[2] > 1 and _alt(inf["Lz"]):
+            _set_variant(mm, plan, "zconv", 3)
+    return plan
+
+
+@pytest.mark.parametrize("mode", ["merged", "grouped"])
+def test_batched_demag_is_bitwise_per_instance(mode):
     from paper_1406_7459_amd import mm
     b = mm.Batch([s for s, _ in SMALL], [d for _, d in SMALL])
+    b.set_mode(mode)
     Ms = [to_dev(8e5 * W.random_unit(*s, seed=i)) for i, (s, _) in enumerate(SMALL)]
     Hb = [to_host(h) for h in b.demag(Ms)]
     for i, (s, d) in enumerate(SMALL):
-        plan = mm.Plan(*s, *d)
+        plan = _plan(mm, s, d, mode)
         Hp = to_host(plan.demag(Ms[i]))
-        assert np.array_equal(Hb[i], Hp), s
+        assert np.array_equal(Hb[i], Hp), (s, mode)
         plan.close()
     b.autotune(reps=2)
     Hb2 = [to_host(h) for h in b.demag(Ms)]
@@ -37,38 +76,57 @@ def test_batched_demag_is_bitwise_per_instance():
     b.close()
 
 
+@pytest.mark.parametrize("mode", ["merged", "grouped"])
 @pytest.mark.parametrize("integrator", ["rk4", "euler"])
-def test_batched_steps_are_bitwise_per_instance(integrator):
+def test_batched_steps_are_bitwise_per_instance(integrator, mode):
     from paper_1406_7459_amd import mm
     b = mm.Batch([s for s, _ in SMALL], [d for _, d in SMALL])
+    b.set_mode(mode)
     M0 = [8e5 * W.random_unit(*s, seed=10 + i) for i, (s, _) in enumerate(SMALL)]
     Mb = [to_dev(m) for m in M0]
     params = [_params(mm, i, integrator) for i in range(len(SMALL))]
     b.step(params, Mb, 7)
     for i, (s, d) in enumerate(SMALL):
-        plan = mm.Plan(*s, *d)
+        plan = _plan(mm, s, d, mode)
         Mp = to_dev(M0[i])
         plan.step(params[i], Mp, 7)
-        assert np.array_equal(to_host(Mb[i]), to_host(Mp)), (s, integrator)
+        assert np.array_equal(to_host(Mb[i]), to_host(Mp)), (s, integrator, mode)
         plan.close()
     b.close()
 
 
+def test_merged_and_grouped_modes_agree():
+    """The two launch modes differ only in the radix orders of 3 * 2^a
+    lengths: their fields agree to rounding."""
+    from paper_1406_7459_amd import mm
+    b = mm.Batch([s for s, _ in SMALL], [d for _, d in SMALL])
+    Ms = [to_dev(8e5 * W.random_unit(*s, seed=20 + i)) for i, (s, _) in enumerate(SMALL)]
+    b.set_mode("merged")
+    Hm = [to_host(h) for h in b.demag(Ms)]
+    b.set_mode("grouped")
+    Hg = [to_host(h) for h in b.demag(Ms)]
+    for a, c in zip(Hm, Hg):
+        assert np.linalg.norm(a - c) <= 1e-6 * np.linalg.norm(c)
+    b.close()
+
+
 def test_sweep_batch_full_size_matches_per_instance():
-    """The 64-film field sweep at full size: a few instances checked bitwise
-    after two batched steps (autotuned groups)."""
+    """The 64-film field sweep at full size: at most one launch per pass kind
+    and stage (4 x 7 per RK4 step) in the merged mode, and a few instances
+    checked bitwise after two batched steps."""
     from paper_1406_7459_amd import mm
     wls = W.sweep64()
     b = mm.Batch([w.shape for w in wls], [w.cell for w in wls])
-    say("sweep64 groups", b.query())
-    b.autotune(reps=2)
+    q = b.query()
+    say("sweep64 merged", q)
+    assert q["launches_per_step"] <= 4 * (6 + 1)
     Ms = [to_dev(w.mat.Ms * w.initial_unit()) for w in wls]
     M0 = [m.clone() for m in Ms]
     params = [mm.LLGParams.make(Ms=w.mat.Ms, A=w.mat.A, alpha=w.mat.alpha, Hext=w.mat.Hext, dt=w.mat.dt)
               for w in wls]
     b.step(params, Ms, 2)
     for i in (0, 17, 40, 63):
-        plan = mm.Plan(*wls[i].shape, *wls[i].cell)
+        plan = _plan(mm, wls[i].shape, wls[i].cell, "merged")
         m = M0[i].clone()
         plan.step(params[i], m, 2)
         assert np.array_equal(to_host(Ms[i]), to_host(m)), wls[i].shape

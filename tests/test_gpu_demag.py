@@ -59,9 +59,10 @@ def test_demag_film32_matches_direct_sum():
 
 def test_every_tile_gives_identical_field():
     """Launch tiles change only which workgroup does a transform, not its
-    arithmetic: all candidates of one radix order agree bitwise; the product
-    pass's alternative radix orders (tile variants 3 and 4) round
-    differently and agree with the default order within 1e-6."""
+    arithmetic: all candidates of one radix order agree bitwise; the
+    alternative radix orders (variants 2 and 3 of the single-component
+    passes, 3 and 4 of the product passes) round differently and agree with
+    the default order within 1e-6."""
     from paper_1406_7459_amd import mm
     for grid in [(24, 48, 6), (32, 16, 1), (16, 8, 32)]:
         nx, ny, nz = grid
@@ -75,13 +76,17 @@ def test_every_tile_gives_identical_field():
                 continue
             order_ref = {}
             for t in [P + 256 * var for var in (0, 1, 2, 3, 4) for P in (1, 2, 4, 8, 16, 32, 64, 128)]:
+                if t >> 8 == 4 and pname not in ("zconv", "yconv"):
+                    continue
                 try:
                     plan.set_tile(pname, t)
                 except mm.MMError:
                     continue
                 say("tile", grid, pname, t)
                 H = to_host(plan.demag(M))
-                order = t >> 8 if pname in ("zconv", "yconv") and t >= 3 * 256 else 0
+                var = t >> 8
+                conv = pname in ("zconv", "yconv")
+                order = (var - 2 if var >= 3 else 0) if conv else (var - 1 if var >= 2 else 0)
                 if order == 0:
                     assert np.array_equal(H, ref), (pname, t)
                 else:
