@@ -105,10 +105,11 @@ def _workload(name):
 
 def pass_tile_of(kname, blocks, threads, shape):
     """(pass, tile, sub) of a dispatch of this library on a grid of `shape`
-    from its kernel name, its number of workgroups along x and its total
-    threads: sub is the RK4 stage (0 = Euler) for the stage kernel, whose tile
-    is its vector width, and 0 otherwise; None for anything else (other
-    transform lengths, set-up kernels)."""
+    from its kernel name, its number of workgroups (every launch of the
+    library is one-dimensional) and its total threads: sub is the RK4 stage
+    (0 = Euler) for the stage kernel, whose tile is its vector width, and 0
+    otherwise; None for anything else (other transform lengths, set-up
+    kernels)."""
     import re
     nx, ny, nz = shape
     nxc, pairs = nx + 1, (3 * nz * ny + 1) // 2
@@ -121,25 +122,42 @@ def pass_tile_of(kname, blocks, threads, shape):
         return p
 
     lens = {"xfwd": 2 * nx, "xinv": 2 * nx, "yfwd": 2 * ny, "yinv": 2 * ny, "yconv": 2 * ny, "zconv": 2 * nz}
+
+    def col_P(nrows, edge):
+        # the column passes' workgroup count for P: tiles over the nx columns
+        # below the last plus edge workgroups for the last when P divides nx
+        # (and edge launches are used), else tiles over all nx + 1 columns
+        for P in (1, 2, 4, 8, 16, 32, 64, 128):
+            if edge and P > 1 and nx % P == 0:
+                n = nx // P * nrows + -(-nrows // P)
+            else:
+                n = -(-nxc // P) * nrows
+            if n == blocks:
+                return P
+        return p2(-(-nxc * nrows // blocks))
+
     m = re.search(r"mmk::k_(xfwd|yfwd|yinv|xinv)<(\d+), (\d+)>", kname)
     if m:
         if int(m.group(2)) != lens[m.group(1)]:
             return None
         rows = m.group(1) in ("xfwd", "xinv")
-        P = p2(-(-pairs // blocks)) if rows else p2(-(-nxc // blocks))
+        P = p2(-(-pairs // blocks)) if rows else col_P(3 * nz, True)
         return m.group(1), P + 256 * int(m.group(3)), 0
     m = re.search(r"mmk::k_conv_reg3<(\d+), (true|false), (\d)>", kname)
     if m:
-        pname = "zconv" if m.group(2) == "true" else "yconv"
+        z = m.group(2) == "true"
+        pname = "zconv" if z else "yconv"
         order = int(m.group(3))
         var = 0 if order == 0 else 2 + order
-        return (pname, p2(-(-nxc // blocks)) + 256 * var, 0) if int(m.group(1)) == lens[pname] else None
+        P = col_P(2 * ny, True) if z else col_P(1, False)
+        return (pname, P + 256 * var, 0) if int(m.group(1)) == lens[pname] else None
     m = re.search(r"mmk::k_conv_split<(\d+), (\d+), (true|false)>", kname)
     if m:
-        pname = "zconv" if m.group(3) == "true" else "yconv"
+        z = m.group(3) == "true"
+        pname = "zconv" if z else "yconv"
         if int(m.group(1)) != lens[pname]:
             return None
-        return pname, p2(-(-nxc // blocks)) + 256 * (1 + int(m.group(2))), 0
+        return pname, col_P(2 * ny if z else 1, False) + 256 * (1 + int(m.group(2))), 0
     m = re.search(r"mmk::k_xstage<(\d+), ([0-4]), (true|false), (\d)>", kname)
     if m:
         if int(m.group(1)) != lens["xfwd"]:
@@ -172,10 +190,14 @@ def summarize_trace(workload, db):
             other.setdefault(name.split("(")[0].replace("void ", ""), []).append(dur / 1e3)
     alg = pass_bytes(*shape)
     out = ["# kernel trace, %s (%dx%dx%d cells), rocprofv3 --kernel-trace" % ((workload,) + tuple(shape)),
-           "# command (from /tmp on the GPU, REPO = repository root, OUT = an output folder):",
-           "#   rocprofv3 --kernel-trace --stats -d $OUT/prof_%s -o %s -- python3 $REPO/bench.py "
-           "--workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs --no-surrogate"
-           % (workload, workload, workload),
+           "# commands (from /tmp on the GPU, REPO = repository root, OUT = an output folder; the first, a",
+           "# full bench run, tunes and writes the tune cache, so the traced run launches the tuned tiles",
+           "# without re-tuning):",
+           "#   MM_TUNE_CACHE=$OUT/tune.json python3 $REPO/bench.py --workload %s --no-cpu-baseline "
+           "--no-batch --no-surrogate" % workload,
+           "#   MM_TUNE_CACHE=$OUT/tune.json rocprofv3 --kernel-trace --stats -d $OUT/prof_%s -o %s -- python3 "
+           "$REPO/bench.py --workload %s --steps 10 --warmup 2 --no-cpu-baseline --no-batch --no-other-configs "
+           "--no-surrogate" % (workload, workload, workload),
            "#   python3 bench.py --summarize-trace %s $OUT/prof_%s/%s_results.db" % (workload, workload, workload),
            "# durations in microseconds; tile = P + 256 * variant, for the stage kernel its vector width, for",
            "# the fused xstage pass its row pairs per workgroup, with the RK4 stage (1-4, 0 = Euler) in column s;",
@@ -198,6 +220,84 @@ def summarize_trace(workload, db):
     for name in sorted(other, key=lambda n: -sum(other[n])):
         d = other[name]
         out.append("#   %-56s calls %6d mean %9.2f total %10.1f" % (name[:56], len(d), statistics.mean(d), sum(d)))
+    return "\n".join(out) + "\n"
+
+
+SQ_SETS = {
+    "sq_A": ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+             "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"),
+    "sq_B": ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY",
+             "SQ_ACTIVE_INST_ANY", "SQ_WAVE_CYCLES", "SQ_WAVES"),
+}
+
+
+def summarize_counters(workload, pmc_dir, trace_db):
+    """Text of profiles/sq_<workload>.txt from the rocprofv3 --pmc databases
+    sq_A and sq_B under pmc_dir (the counter sets of SQ_SETS, one run each)
+    and a --kernel-trace database of the same tiles for durations: per (pass,
+    tile, stage) the median per dispatch of each counter, summed over the
+    chip, and ratios of counters in the same units."""
+    import glob
+    import sqlite3
+    import statistics
+    shape = _workload(workload).shape
+    vals = {}
+    for kind, names in SQ_SETS.items():
+        db = glob.glob(os.path.join(pmc_dir, kind, "*.db"))[0]
+        con = sqlite3.connect(db)
+        per = {}
+        for disp, kname, gx, wx, gt, cname, v in con.execute(
+                "select dispatch_id, kernel_name, grid_size_x, workgroup_size_x, grid_size, counter_name, value "
+                "from counters_collection"):
+            key = pass_tile_of(kname, gx // max(1, wx), gt, shape)
+            if key is None:
+                continue
+            e = per.setdefault(disp, (key, {}))
+            e[1][cname] = e[1].get(cname, 0.0) + v
+        for key, cv in per.values():
+            for c, v in cv.items():
+                vals.setdefault(key, {}).setdefault(c, []).append(v)
+    dur = {}
+    con = sqlite3.connect(trace_db)
+    for name, gx, gy, gz, wx, d in con.execute(
+            "select name, grid_x, grid_y, grid_z, workgroup_x, duration from kernels"):
+        key = pass_tile_of(name, gx // max(1, wx), gx * gy * gz, shape)
+        if key:
+            dur.setdefault(key, []).append(d / 1e3)
+    out = ["# SQ counters per launch, %s (%dx%dx%d cells), rocprofv3 --pmc" % ((workload,) + tuple(shape)),
+           "# commands (from /tmp on the GPU, REPO = repository root, OUT = an output folder; the tune cache",
+           "# written by a full bench run, so these runs launch the tuned tiles without re-tuning):",
+           "#   MM_TUNE_CACHE=$OUT/tune.json python3 $REPO/bench.py --workload %s --no-cpu-baseline --no-batch "
+           "--no-surrogate" % workload]
+    for kind, names in SQ_SETS.items():
+        out.append("#   MM_TUNE_CACHE=$OUT/tune.json rocprofv3 --pmc %s -d $OUT/sq/%s -o %s -- python3 $REPO/bench.py "
+                   "--workload %s --steps 3 --warmup 1 --no-cpu-baseline --no-batch --no-other-configs "
+                   "--no-surrogate" % (" ".join(names), kind, kind, workload))
+    out += ["#   python3 bench.py --summarize-counters %s $OUT/sq $OUT/prof_%s/%s_results.db"
+            % (workload, workload, workload),
+            "# columns: waves; VALU, LDS, SALU, VMEM instructions per wave; valu_floor_us = SQ_INSTS_VALU x 4",
+            "# cycles (a wave64 FP32 VALU op without packed math) / (1024 SIMDs x 2.4 GHz); the trace median",
+            "# duration; valu_frac = floor / median; lds_conf = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS;",
+            "# wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (share of wave time waiting on a dependency);",
+            "# valu_act = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES",
+            "%-7s %5s %2s %7s %6s %6s %5s %6s %7s %8s %7s %6s %6s %6s %6s" % (
+                "pass", "tile", "s", "waves", "valu", "lds", "salu", "vmem", "floor", "median", "v_frac",
+                "ldsc", "wait", "v_act", "n")]
+    for key in sorted(vals):
+        c = {k: statistics.median(v) for k, v in vals[key].items()}
+        w = c.get("SQ_WAVES", 0.0)
+        if not w:
+            continue
+        floor = c.get("SQ_INSTS_VALU", 0.0) * 4 / (1024 * 2.4e3)
+        med = statistics.median(dur[key]) if key in dur else float("nan")
+        wc = c.get("SQ_WAVE_CYCLES", 0.0) or float("nan")
+        lds_act = c.get("SQ_ACTIVE_INST_LDS", 0.0) or float("nan")
+        out.append("%-7s %5d %2d %7d %6.0f %6.0f %5.0f %6.1f %7.2f %8.2f %7.2f %6.3f %6.3f %6.3f %6d" % (
+            key[0], key[1], key[2], w, c.get("SQ_INSTS_VALU", 0) / w, c.get("SQ_INSTS_LDS", 0) / w,
+            c.get("SQ_INSTS_SALU", 0) / w, (c.get("SQ_INSTS_VMEM_RD", 0) + c.get("SQ_INSTS_VMEM_WR", 0)) / w,
+            floor, med, floor / med, c.get("SQ_LDS_BANK_CONFLICT", 0) / lds_act,
+            c.get("SQ_WAIT_INST_ANY", 0) / wc, c.get("SQ_ACTIVE_INST_VALU", 0) / wc,
+            len(vals[key].get("SQ_WAVES", []))))
     return "\n".join(out) + "\n"
 
 
@@ -631,6 +731,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("WORKLOAD", "PMC_DIR"),
                     help="print the traffic summary of rocprofv3 counter databases and exit")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("WORKLOAD", "PMC_DIR", "TRACE_DB"),
+                    help="print the SQ counter summary of two rocprofv3 --pmc databases (SQ_SETS) and exit")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("WORKLOAD", "DB"),
                     help="print the per-(pass, tile) summary of a rocprofv3 kernel-trace database and exit")
     ap.add_argument("--surrogate-profile", action="store_true",
@@ -652,6 +754,9 @@ def main():
         return
     if args.summarize_trace:
         sys.stdout.write(summarize_trace(*args.summarize_trace))
+        return
+    if args.summarize_counters:
+        sys.stdout.write(summarize_counters(*args.summarize_counters))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU; the library has no multi-GPU path (got --gpus %d)"

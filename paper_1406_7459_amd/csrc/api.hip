@@ -673,35 +673,45 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
     MMK_HIP(hipEventCreate(&e1));
     int rc = MM_OK;
     int tuned = 0;
+    // time of `reps` runs of `run` (two events around the loop)
+    auto time_it = [&](auto &&run, float &ms) -> int {
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(MM_EHIP, "event");
+        for (int r = 0; r < reps; ++r) {
+            const int rc2 = run();
+            if (rc2 != MM_OK) return rc2;
+        }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return fail(MM_EHIP, "event");
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return MM_OK;
+    };
+    // Candidates are timed in three interleaved rounds and each keeps its
+    // best round (one run is noisy to a few per cent, and clocks drift over
+    // a tuning run: timing each candidate's repeats back to back would
+    // favour whichever runs last).
+    constexpr int ROUNDS = 3;
     for (int sweep = 0; sweep < 2 && rc == MM_OK; ++sweep) {
         for (int pass = 0; pass <= MM_PASS_YCONV && rc == MM_OK; ++pass) {
             std::vector<int> cand = pass_tile_candidates(*p, pass);
             if (cand.size() < (sweep == 0 ? 1u : 2u)) continue;
-            float best = 1e30f;
-            int best_tile = p->tile[pass];
-            for (int t : cand) {
-                p->tile[pass] = t;
-                if ((rc = demag_enqueue(*p, p->Sa, p->H, s)) != MM_OK) break;  // warm-up
-                // the best of three timed runs (one run is noisy to a few per cent)
-                for (int rep = 0; rep < 3 && rc == MM_OK; ++rep) {
-                    if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MM_EHIP, "event"); break; }
-                    for (int r = 0; r < reps && rc == MM_OK; ++r) rc = demag_enqueue(*p, p->Sa, p->H, s);
-                    if (rc != MM_OK) break;
-                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                        rc = fail(MM_EHIP, "event");
-                        break;
-                    }
-                    float ms = 0.f;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    if (ms < best) {
-                        best = ms;
-                        best_tile = t;
-                    }
-                }
-                if (rc != MM_OK) break;
-                ++tuned;
+            std::vector<float> best(cand.size(), 1e30f);
+            auto run = [&]() { return demag_enqueue(*p, p->Sa, p->H, s); };
+            for (size_t i = 0; i < cand.size() && rc == MM_OK; ++i) {  // warm-up
+                p->tile[pass] = cand[i];
+                rc = run();
             }
-            p->tile[pass] = best_tile;
+            for (int round = 0; round < ROUNDS && rc == MM_OK; ++round)
+                for (size_t i = 0; i < cand.size() && rc == MM_OK; ++i) {
+                    p->tile[pass] = cand[i];
+                    float ms = 0.f;
+                    if ((rc = time_it(run, ms)) == MM_OK) best[i] = std::min(best[i], ms);
+                }
+            if (rc != MM_OK) break;
+            size_t bi = 0;
+            for (size_t i = 1; i < cand.size(); ++i)
+                if (best[i] < best[bi]) bi = i;
+            p->tile[pass] = cand[bi];
+            tuned += (int)cand.size();
         }
     }
     // the fused pass's tiles and the unfused path (tile 0): each candidate
@@ -724,45 +734,43 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
         const StageCoef c = stage_coef(*p, q);
         MMK_HIP(hipMemsetAsync(p->H, 0, sizeof(float) * 3 * (size_t)p->cells(), s));
         MMK_HIP(hipStreamSynchronize(s));
-        float best = 1e30f;
-        int best_tile = p->tile[MM_PASS_XSTAGE];
-        for (int t : cand) {
-            if (cand.size() < 2) break;
-            p->tile[MM_PASS_XSTAGE] = t;
-            hipGraph_t g = nullptr;
-            hipGraphExec_t x = nullptr;
+        std::vector<hipGraph_t> gs(cand.size(), nullptr);
+        std::vector<hipGraphExec_t> xs(cand.size(), nullptr);
+        std::vector<float> best(cand.size(), 1e30f);
+        const int keep = p->tile[MM_PASS_XSTAGE];
+        for (size_t i = 0; i < cand.size() && cand.size() > 1 && rc == MM_OK; ++i) {
+            p->tile[MM_PASS_XSTAGE] = cand[i];
             if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
                 rc = fail(MM_EHIP, "tune capture");
                 break;
             }
             rc = llg_enqueue_step(*p, c, MM_RK4, p->H, p->cap_stream);
-            hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
-            if (rc == MM_OK && e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            hipError_t e = hipStreamEndCapture(p->cap_stream, &gs[i]);
+            if (rc == MM_OK && e == hipSuccess) e = hipGraphInstantiate(&xs[i], gs[i], nullptr, nullptr, 0);
             if (rc == MM_OK && e != hipSuccess) rc = fail(MM_EHIP, std::string("tune graph: ") + hipGetErrorString(e));
-            if (rc == MM_OK && hipGraphLaunch(x, s) != hipSuccess) rc = fail(MM_EHIP, "tune graph launch");  // warm-up
-            for (int rep = 0; rep < 3 && rc == MM_OK; ++rep) {
-                if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(MM_EHIP, "event"); break; }
-                for (int r = 0; r < reps && rc == MM_OK; ++r)
-                    if (hipGraphLaunch(x, s) != hipSuccess) rc = fail(MM_EHIP, "tune graph launch");
-                if (rc != MM_OK) break;
-                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = fail(MM_EHIP, "event");
-                    break;
-                }
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best) {
-                    best = ms;
-                    best_tile = t;
-                }
-            }
-            (void)hipStreamSynchronize(s);  // no replay in flight when its graph goes
-            if (x) (void)hipGraphExecDestroy(x);
-            if (g) (void)hipGraphDestroy(g);
-            if (rc != MM_OK) break;
-            ++tuned;
+            if (rc == MM_OK && hipGraphLaunch(xs[i], s) != hipSuccess) rc = fail(MM_EHIP, "tune graph launch");  // warm-up
         }
-        p->tile[MM_PASS_XSTAGE] = best_tile;
+        for (int round = 0; round < ROUNDS && cand.size() > 1 && rc == MM_OK; ++round)
+            for (size_t i = 0; i < cand.size() && rc == MM_OK; ++i) {
+                float ms = 0.f;
+                auto run = [&]() {
+                    return hipGraphLaunch(xs[i], s) == hipSuccess ? MM_OK : fail(MM_EHIP, "tune graph launch");
+                };
+                if ((rc = time_it(run, ms)) == MM_OK) best[i] = std::min(best[i], ms);
+            }
+        (void)hipStreamSynchronize(s);  // no replay in flight when its graph goes
+        for (size_t i = 0; i < cand.size(); ++i) {
+            if (xs[i]) (void)hipGraphExecDestroy(xs[i]);
+            if (gs[i]) (void)hipGraphDestroy(gs[i]);
+        }
+        p->tile[MM_PASS_XSTAGE] = keep;
+        if (rc == MM_OK && cand.size() > 1) {
+            size_t bi = 0;
+            for (size_t i = 1; i < cand.size(); ++i)
+                if (best[i] < best[bi]) bi = i;
+            p->tile[MM_PASS_XSTAGE] = cand[bi];
+            tuned += (int)cand.size();
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

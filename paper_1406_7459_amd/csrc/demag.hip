@@ -7,24 +7,40 @@
 
 namespace mmk {
 
-// Tile and plane (or mirror-paired ky row) of this workgroup for the column
-// passes, through the XCD mapping: logical order is kx tile fastest, so
-// neighbouring tiles of one row share their L2; in the z pass the two ky
+// Coordinates of this workgroup in a column pass over `nrows` planes (ky
+// rows in the z pass).  The grid holds ntm * nrows tiles and, first, any
+// edge workgroups (the last kx column at P rows each, column_of; their
+// strided accesses take longest, so they are dispatched first, one to each
+// XCD in turn): for those the return value is nrows (the body's nedge),
+// else 0.  Tiles go through the XCD mapping, logical order kx tile fastest,
+// so neighbouring tiles of one row share their L2; in the z pass the two ky
 // rows of a mirror pair (one K~ octant row) come first, then the tile.
-__device__ __forceinline__ void column_coords(int &bx, int &plane)
+__device__ __forceinline__ int column_coords(int ntm, int nrows, int &bx, int &plane)
 {
-    const unsigned nt = gridDim.x, nb = nt * gridDim.y;
-    const unsigned l = xcd_block(blockIdx.y * nt + blockIdx.x, nb);
-    bx = (int)(l % nt);
-    plane = (int)(l / nt);
+    const unsigned nmain = (unsigned)ntm * (unsigned)nrows, ne = gridDim.x - nmain;
+    if (blockIdx.x < ne) {
+        bx = 0;
+        plane = (int)blockIdx.x;
+        return nrows;
+    }
+    const unsigned l = xcd_block(blockIdx.x - ne, nmain);
+    bx = (int)(l % (unsigned)ntm);
+    plane = (int)(l / (unsigned)ntm);
+    return 0;
 }
-__device__ __forceinline__ void conv_coords(int hy, int &bx, int &ky)
+__device__ __forceinline__ int conv_coords(int ntm, int hy, int &bx, int &ky)
 {
-    const unsigned nt = gridDim.x, nb = nt * gridDim.y;  // gridDim.y = Ly = 2 hy slots
-    const unsigned l = xcd_block(blockIdx.y * nt + blockIdx.x, nb);
+    const unsigned nmain = (unsigned)ntm * 2u * (unsigned)hy, ne = gridDim.x - nmain;
+    if (blockIdx.x < ne) {
+        bx = 0;
+        ky = (int)blockIdx.x;
+        return 2 * hy;
+    }
+    const unsigned l = xcd_block(blockIdx.x - ne, nmain);
     const unsigned r = l >> 1;
-    bx = (int)(r % nt);
-    ky = ky_of_slot((int)(2 * (r / nt) + (l & 1)), hy);
+    bx = (int)(r % (unsigned)ntm);
+    ky = ky_of_slot((int)(2 * (r / (unsigned)ntm) + (l & 1)), hy);
+    return 0;
 }
 
 // Per-plan kernels: one launch covers one pass of one grid.
@@ -36,39 +52,40 @@ __global__ __launch_bounds__(1024) void k_xfwd(const float *__restrict__ M, floa
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yfwd(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc,
-                                               int ny, int lp2, const float2 *__restrict__ tw)
+                                               int ny, int lp2, const float2 *__restrict__ tw, int ntm, int nrows)
 {
     int bx, plane;
-    column_coords(bx, plane);
-    yfwd_body<L, V>(X1, X2, nxc, ny, lp2, tw, bx, plane);
+    const int ne = column_coords(ntm, nrows, bx, plane);
+    yfwd_body<L, V>(X1, X2, nxc, ny, lp2, tw, bx, plane, ne);
 }
 template <int L, bool ZAXIS, int O>
 __global__ __launch_bounds__((conv_max_threads<L, O>())) void k_conv_reg3(float2 *__restrict__ X,
                                                                          const float *__restrict__ Kt, int nxc,
                                                                          int hy, int nlive, int lp2,
-                                                                         const float2 *__restrict__ tw)
+                                                                         const float2 *__restrict__ tw, int ntm)
 {
-    int bx, ky = 0;
-    if constexpr (ZAXIS) conv_coords(hy, bx, ky);
+    int bx, ky = 0, ne = 0;
+    if constexpr (ZAXIS) ne = conv_coords(ntm, hy, bx, ky);
     else bx = (int)xcd_block(blockIdx.x, gridDim.x);
-    conv_reg3_body<L, ZAXIS, O>(X, Kt, nxc, hy, nlive, lp2, tw, bx, ky);
+    conv_reg3_body<L, ZAXIS, O>(X, Kt, nxc, hy, nlive, lp2, tw, bx, ky, ne);
 }
 template <int L, int V, bool ZAXIS>
 __global__ __launch_bounds__(1024) void k_conv_split(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc,
-                                                      int hy, int nlive, int lp2, const float2 *__restrict__ tw)
+                                                      int hy, int nlive, int lp2, const float2 *__restrict__ tw,
+                                                      int ntm)
 {
     int bx, ky = 0;
-    if constexpr (ZAXIS) conv_coords(hy, bx, ky);
+    if constexpr (ZAXIS) (void)conv_coords(ntm, hy, bx, ky);  // launched without edge workgroups
     else bx = (int)xcd_block(blockIdx.x, gridDim.x);
     conv_split_body<L, V, ZAXIS>(X, Kt, nxc, hy, nlive, lp2, tw, bx, ky);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_yinv(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc,
-                                               int ny, int lp2, const float2 *__restrict__ tw)
+                                               int ny, int lp2, const float2 *__restrict__ tw, int ntm, int nrows)
 {
     int bx, plane;
-    column_coords(bx, plane);
-    yinv_body<L, V>(X2, X1, nxc, ny, lp2, tw, bx, plane);
+    const int ne = column_coords(ntm, nrows, bx, plane);
+    yinv_body<L, V>(X2, X1, nxc, ny, lp2, tw, bx, plane, ne);
 }
 template <int L, int V>
 __global__ __launch_bounds__(1024) void k_xinv(const float2 *__restrict__ X1, float *__restrict__ H, int ncr,
@@ -329,6 +346,22 @@ static void raise_for(K kern, size_t lds)
     if (lds > 65536) (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// Tiles of a column pass over nrows planes (ky rows): when P (> 1) divides
+// the Lx/2 columns below the last, ntm = Lx/2 / P tiles and ne edge
+// workgroups for the last column (P rows each); else ntm tiles over every
+// column and none.
+static void column_grid(const Plan &p, int P, int nrows, int &ntm, int &ne)
+{
+    const int half = p.Lx / 2;
+    if (P > 1 && half % P == 0) {
+        ntm = half / P;
+        ne = (nrows + P - 1) / P;
+    } else {
+        ntm = (p.nxc + P - 1) / P;
+        ne = 0;
+    }
+}
+
 template <int L, int V>
 static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, float *H, hipStream_t s)
 {
@@ -353,13 +386,17 @@ static void launch_single(Plan &p, int pass, int P, size_t lds, const float *M, 
         break;
     }
     case MM_PASS_YFWD:
-        MMK_LAUNCH(p, (k_yfwd<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X1, p.X2, nxc, p.ny, lp2,
-                           p.tw[1]);
+    case MM_PASS_YINV: {
+        const int nrows = 3 * p.nz;
+        int ntm, ne;
+        column_grid(p, P, nrows, ntm, ne);
+        const dim3 grid((unsigned)(ntm * nrows + ne));
+        if (pass == MM_PASS_YFWD)
+            MMK_LAUNCH(p, (k_yfwd<L, V>), grid, block, lds, s, p.X1, p.X2, nxc, p.ny, lp2, p.tw[1], ntm, nrows);
+        else
+            MMK_LAUNCH(p, (k_yinv<L, V>), grid, block, lds, s, p.X2, p.X1, nxc, p.ny, lp2, p.tw[1], ntm, nrows);
         break;
-    case MM_PASS_YINV:
-        MMK_LAUNCH(p, (k_yinv<L, V>), dim3((nxc + P - 1) / P, 3 * p.nz), block, lds, s, p.X2, p.X1, nxc, p.ny, lp2,
-                           p.tw[1]);
-        break;
+    }
     case MM_PASS_XINV: {
         MMK_LAUNCH(p, (k_xinv<L, V>), dim3((pairs + P - 1) / P), block, lds, s, p.X1, H, ncr, p.nx, lp2, p.tw[0]);
         break;
@@ -376,18 +413,23 @@ static void launch_conv(Plan &p, int pass, int P, int var, size_t lds, hipStream
     const bool z = pass == MM_PASS_ZCONV;
     float2 *X = z ? p.X2 : p.X1;
     const float2 *tw = z ? p.tw[2] : p.tw[1];
-    const dim3 grid((nxc + P - 1) / P, z ? p.Ly : 1);
     const int hy = p.Ly / 2, nl = z ? p.nz : p.ny;
+    // reg3 z passes take edge workgroups (column_grid); the split schedule
+    // and the y product tile every column
+    const bool reg3z = z && (var == 0 || var == 3 || var == 4);
+    int ntm = (nxc + P - 1) / P, ne = 0;
+    if (reg3z) column_grid(p, P, p.Ly, ntm, ne);
+    const dim3 grid((unsigned)(z ? ntm * p.Ly + ne : ntm));
     if (var == 0) {
         const dim3 block(P * (L / Factors<L>::E));
-        if (z) MMK_LAUNCH(p, (k_conv_reg3<L, true, 0>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
-        else MMK_LAUNCH(p, (k_conv_reg3<L, false, 0>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_reg3<L, true, 0>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw, ntm);
+        else MMK_LAUNCH(p, (k_conv_reg3<L, false, 0>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw, ntm);
     } else if (var == 3 || var == 4) {
         if constexpr (Factors<L, 1>::valid || Factors<L, 2>::valid) {
             auto go = [&](auto kern, int E) {
                 if (lds > 65536)
                     (void)hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                MMK_LAUNCH(p, kern, grid, dim3(P * (L / E)), lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+                MMK_LAUNCH(p, kern, grid, dim3(P * (L / E)), lds, s, X, p.Kt, nxc, hy, nl, lp2, tw, ntm);
             };
             if constexpr (Factors<L, 1>::valid) {
                 if (var == 3) {
@@ -404,12 +446,12 @@ static void launch_conv(Plan &p, int pass, int P, int var, size_t lds, hipStream
         }
     } else if (var == 1) {
         const dim3 block(3 * P * (L / ept<L, 0>()));
-        if (z) MMK_LAUNCH(p, (k_conv_split<L, 0, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
-        else MMK_LAUNCH(p, (k_conv_split<L, 0, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_split<L, 0, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw, ntm);
+        else MMK_LAUNCH(p, (k_conv_split<L, 0, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw, ntm);
     } else {
         const dim3 block(3 * P * (L / ept<L, 1>()));
-        if (z) MMK_LAUNCH(p, (k_conv_split<L, 1, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
-        else MMK_LAUNCH(p, (k_conv_split<L, 1, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw);
+        if (z) MMK_LAUNCH(p, (k_conv_split<L, 1, true>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw, ntm);
+        else MMK_LAUNCH(p, (k_conv_split<L, 1, false>), grid, block, lds, s, X, p.Kt, nxc, hy, nl, lp2, tw, ntm);
     }
 }
 

@@ -126,10 +126,31 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
         }
 }
 
-// y forward on a tile of P kx columns of one (component, z) plane.
+// Column of thread p of a column-pass workgroup.  A tile (nedge = 0): kx
+// columns bx P .. bx P + P - 1 of one plane (or ky row) `slot`.  An edge
+// workgroup (nedge > 0): the half spectrum's last column kx = nxc - 1 of the
+// P planes (ky rows) slot P .. slot P + P - 1 of nedge.  When P divides the
+// Lx/2 columns below it, edge workgroups spare the tiles a last tile with a
+// single live column.
+__device__ __forceinline__ bool column_of(int nxc, int P, int p, int bx, int slot, int nedge, int &kx, int &row)
+{
+    if (nedge > 0) {
+        kx = nxc - 1;
+        row = slot * P + p;
+        if (row < nedge) return true;
+        row = nedge - 1;  // an idle lane keeps in-range addresses
+        return false;
+    }
+    kx = bx * P + p;
+    row = slot;
+    return kx < nxc;
+}
+
+// y forward on a tile of P kx columns of one (component, z) plane, or an
+// edge workgroup (column_of).
 template <int L, int V>
 __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 *__restrict__ X2, int nxc, int ny,
-                                          int lp2, const float2 *__restrict__ tw, int bx, int plane)
+                                          int lp2, const float2 *__restrict__ tw, int bx, int slot, int nedge = 0)
 {
     constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
@@ -138,8 +159,8 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
     const int P = 1 << lp2;
     const int t = threadIdx.x;
     const int p = t & (P - 1), q = t >> lp2;
-    const int kx = bx * P + p;
-    const bool ok = kx < nxc;
+    int kx, plane;
+    const bool ok = column_of(nxc, P, p, bx, slot, nedge, kx, plane);
     const int xp = x_pitch(nxc);
     const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
@@ -205,11 +226,13 @@ template <int L, int O = 0> constexpr int conv_max_threads()
 
 // Schedule "reg3" of the product pass in radix order O.  ZAXIS: z forward
 // -> product -> z inverse for P kx columns at one ky, in place on X2 (rows
-// k < nz).  Else (nz = 1): the same along y on X1 (rows j < ny), with
+// k < nz), or (nedge = 2 hy) for the last kx column at P ky rows
+// (column_of).  Else (nz = 1): the same along y on X1 (rows j < ny), with
 // xz = yz = 0.
 template <int L, bool ZAXIS, int O = 0>
 __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const float *__restrict__ Kt, int nxc, int hy,
-                                               int nlive, int lp2, const float2 *__restrict__ tw, int bx, int ky)
+                                               int nlive, int lp2, const float2 *__restrict__ tw, int bx, int slot,
+                                               int nedge = 0)
 {
     constexpr int E = Factors<L, O>::E, Q = L / E, NH = L / 2;
     extern __shared__ float2 lds[];
@@ -217,8 +240,8 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     const int P = 1 << lp2;
     const int t = threadIdx.x;
     const int p = t & (P - 1), q = t >> lp2;
-    const int kx = bx * P + p;
-    const bool ok = kx < nxc;
+    int kx, ky;
+    const bool ok = column_of(nxc, P, p, bx, slot, nedge, kx, ky);
     const int xp = x_pitch(nxc);
     // two exchange buffers (ping-pong transforms: one barrier per exchange)
     const LdsView s{lds + tw_slots<L>(), P, p};
@@ -401,10 +424,11 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
         }
 }
 
-// y inverse on a tile of P kx columns of one (component, z) plane, keep j < ny.
+// y inverse on a tile of P kx columns of one (component, z) plane, or an
+// edge workgroup (column_of); keep j < ny.
 template <int L, int V>
 __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 *__restrict__ X1, int nxc, int ny,
-                                          int lp2, const float2 *__restrict__ tw, int bx, int plane)
+                                          int lp2, const float2 *__restrict__ tw, int bx, int slot, int nedge = 0)
 {
     constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
@@ -413,8 +437,8 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
     const int P = 1 << lp2;
     const int t = threadIdx.x;
     const int p = t & (P - 1), q = t >> lp2;
-    const int kx = bx * P + p;
-    const bool ok = kx < nxc;
+    int kx, plane;
+    const bool ok = column_of(nxc, P, p, bx, slot, nedge, kx, plane);
     const int xp = x_pitch(nxc);
     const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
