@@ -722,7 +722,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="cube128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -856,6 +856,28 @@ def main():
     plan.set_timing(False)
     st = plan.reduce(params, M)
 
+    # the fused stage pass against the unfused path (x inverse, stage kernel,
+    # x forward), both from graph replays, in interleaved rounds
+    schedules = {}
+    for t in (tiles.get("xstage", 0), 0, 2, 1):
+        try:
+            plan.set_tile("xstage", t)
+        except mm.MMError:
+            continue
+        schedules.setdefault(t, 1e30)
+    Ms = M.clone()
+    for _ in range(3):
+        for t in schedules:
+            plan.set_tile("xstage", t)
+            plan.step(params, Ms, 2)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan.step(params, Ms, args.steps)
+            torch.cuda.synchronize()
+            schedules[t] = min(schedules[t], (time.perf_counter() - t1) / args.steps * 1e3)
+    plan.set_tile("xstage", tiles.get("xstage", 0))
+    del Ms
+
     # isolated demag evaluations, graph-free, events around the loop
     H = torch.empty_like(M)
     for _ in range(5):
@@ -934,6 +956,7 @@ def main():
             "achieved_GBs": sbytes / (el / args.steps) / 1e9,
             "unfused_schedule_bytes_per_step": step_bytes(nx, ny, nz, fused=False),
         },
+        "stage_schedules_ms_per_step": {("fused tile %d" % t if t else "unfused"): v for t, v in schedules.items()},
         "paper_context": {"table1_128cube_euler_ms_HD7970_fp32": 26.34,
                           "note": "paper Table 1, Euler, AMD HD 7970, other hardware: context only"},
     }

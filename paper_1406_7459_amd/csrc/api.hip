@@ -151,7 +151,7 @@ size_t plan_layout(Plan &p, char *base)
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     const size_t szK = sizeof(float) * 6 * (size_t)p.nzK * (p.Ly / 2 + 1) * p.xp;
     const size_t szX1 = sizeof(float2) * 3 * (size_t)nz * ny * p.xp;
-    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * p.Ly * p.xp : 0;
+    const size_t szX2 = nz > 1 ? sizeof(float2) * 3 * (size_t)nz * x2_plane_stride(p.Ly, p.xp) : 0;
     const size_t szF = sizeof(float) * 3 * N;
     const size_t szPart = sizeof(double) * 9 * (size_t)p.red_blocks;
     const size_t szRed = sizeof(double) * 16 * (size_t)RED_LOG;
@@ -690,6 +690,8 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
     // a tuning run: timing each candidate's repeats back to back would
     // favour whichever runs last).
     constexpr int ROUNDS = 3;
+    // MM_TUNE_LOG set: every candidate's best time to stderr
+    const bool tune_log = std::getenv("MM_TUNE_LOG") != nullptr;
     for (int sweep = 0; sweep < 2 && rc == MM_OK; ++sweep) {
         for (int pass = 0; pass <= MM_PASS_YCONV && rc == MM_OK; ++pass) {
             std::vector<int> cand = pass_tile_candidates(*p, pass);
@@ -708,8 +710,10 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
                 }
             if (rc != MM_OK) break;
             size_t bi = 0;
-            for (size_t i = 1; i < cand.size(); ++i)
+            for (size_t i = 0; i < cand.size(); ++i) {
                 if (best[i] < best[bi]) bi = i;
+                if (tune_log) std::fprintf(stderr, "mm tune: pass %d tile %d: %.4f ms / %d runs\n", pass, cand[i], best[i], reps);
+            }
             p->tile[pass] = cand[bi];
             tuned += (int)cand.size();
         }
@@ -766,8 +770,11 @@ int mm_plan_autotune(mm_plan plan, int reps, void *stream)
         p->tile[MM_PASS_XSTAGE] = keep;
         if (rc == MM_OK && cand.size() > 1) {
             size_t bi = 0;
-            for (size_t i = 1; i < cand.size(); ++i)
+            for (size_t i = 0; i < cand.size(); ++i) {
                 if (best[i] < best[bi]) bi = i;
+                if (tune_log)
+                    std::fprintf(stderr, "mm tune: stage pass tile %d: %.4f ms / %d RK4 steps\n", cand[i], best[i], reps);
+            }
             p->tile[MM_PASS_XSTAGE] = cand[bi];
             tuned += (int)cand.size();
         }

@@ -50,6 +50,19 @@ __device__ __forceinline__ const float2 *stage_twiddles(float2 *lds, const float
     }
 }
 
+// The row passes' twiddles in the staged layout of radix order O
+// (fft_engine.hpp, stage_compute): L - R0 <= L entries, in the same slots.
+template <int L, int O>
+__device__ __forceinline__ const float2 *row_twiddles(float2 *lds, const float2 *__restrict__ tw)
+{
+    if constexpr (tw_slots<L>() == 0) {
+        return tw;  // one stage: no twiddles read
+    } else {
+        fill_staged_twiddles<L, O>(lds, tw);
+        return lds;
+    }
+}
+
 // ----------------------------------------------------------------- kernels ---
 
 // Rows of the x passes are paired within a component: pair m of the
@@ -77,7 +90,7 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
     constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
-    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const float2 *twl = row_twiddles<L, OV>(lds, tw);
     const int t = threadIdx.x;
     const int q = t % Q, p = t / Q;
     int ra;
@@ -100,7 +113,7 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ M, float2 *_
             const bool in = !upper && i < nx;
             v[b * R0 + r] = make_float2(in && oka ? sa[i] : 0.f, in && okb ? sb[i] : 0.f);
         }
-    fft_e<L, E, -1, false, OV>(v, s, q, twl);
+    fft_e<L, E, -1, false, OV, true>(v, s, q, twl);
     constexpr int RL = last_radix<L, false, OV>();
     // the last exchange ended with a barrier: the column is free for Z
 #pragma unroll
@@ -168,6 +181,7 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
     // this thread's row q; the other rows are compile-time multiples of the
     // (uniform) row pitch away
     const float2 *src = X1 + ((size_t)plane * ny + q) * xp + kx;
+    const size_t zs = x2_plane_stride(L, xp);
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -179,7 +193,7 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
         }
     fft_e<L, E, -1, false, OV>(v, s, q, twl);
     constexpr int RL = last_radix<L, false, OV>();
-    float2 *dst = X2 + ((size_t)plane * L + q) * xp + kx;
+    float2 *dst = X2 + (size_t)plane * zs + (size_t)q * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / RL; ++b)
 #pragma unroll
@@ -246,7 +260,7 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
     // two exchange buffers (ping-pong transforms: one barrier per exchange)
     const LdsView s{lds + tw_slots<L>(), P, p};
     const LdsView s1{lds + tw_slots<L>() + lds_rows(L) * P, P, p};
-    const size_t rs = ZAXIS ? (size_t)2 * hy * xp : (size_t)xp;  // stride along the transform
+    const size_t rs = ZAXIS ? (size_t)x2_plane_stride(2 * hy, xp) : (size_t)xp;  // stride along the transform
     const size_t cs = (size_t)nlive * rs;                         // component stride
     float2 *base = X + (size_t)ky * xp + kx + (size_t)q * rs;  // this thread's row q
     float2 va[E], vb[E], vc[E];
@@ -340,7 +354,7 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
     constexpr int GS = lds_rows(L);  // slots per component group
     float2 *buf = lds + tw_slots<L>();
     const LdsView s{buf + (size_t)g * GS * P, P, p};
-    const size_t rs = ZAXIS ? (size_t)2 * hy * xp : (size_t)xp;
+    const size_t rs = ZAXIS ? (size_t)x2_plane_stride(2 * hy, xp) : (size_t)xp;
     const size_t cs = (size_t)nlive * rs;
     float2 *base = X + (size_t)g * cs + (size_t)ky * xp + kx + (size_t)q * rs;
     float2 v[E];
@@ -443,7 +457,7 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
     const LdsView s{lds + tw_slots<L>(), P, p};
     float2 v[E];
     constexpr int R0 = first_radix<L, false, OV>();
-    const float2 *src = X2 + ((size_t)plane * L + q) * xp + kx;
+    const float2 *src = X2 + (size_t)plane * x2_plane_stride(L, xp) + (size_t)q * xp + kx;
 #pragma unroll
     for (int b = 0; b < E / R0; ++b)
 #pragma unroll
@@ -472,7 +486,7 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
     constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
-    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const float2 *twl = row_twiddles<L, OV>(lds, tw);
     const int t = threadIdx.x;
     const int q = t % Q, p = t / Q;
     int ra;
@@ -503,7 +517,7 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
             }
             v[b * R0 + r] = make_float2(A.x - B.y, A.y + B.x);
         }
-    fft_e<L, E, +1, false, OV>(v, s, q, twl);
+    fft_e<L, E, +1, false, OV, true>(v, s, q, twl);
     constexpr int RL = last_radix<L, false, OV>();
     float *da = H + (size_t)ra * nx;
     float *db = H + (size_t)rb * nx;

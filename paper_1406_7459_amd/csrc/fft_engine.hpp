@@ -230,7 +230,16 @@ struct LdsView {
 };
 
 // -------------------------------------------------------------- stages ---
-template <int L, int E, int R, int NS, int DIR>
+// Twiddles of a stage with radix R after NS points: w^(r k L/(NS R)) for
+// k < NS, 1 <= r < R, with w = exp(-2 pi i / L).  Flat layout: tw[m] = w^m
+// (m < L).  Staged layout (STW): the entries of each stage in the order
+// [r - 1][k], stage after stage; stage S (NS > 1) starts at NS - R0 (the
+// stages before it hold NS - R0 entries, R0 the first radix), L - R0 in all.
+// In a row pass the lanes of a wave are consecutive k of one transform, so
+// flat reads stride by r L/(NS R) slots and fall into a few LDS banks; the
+// staged reads are consecutive.  Both hold the same values (staged entries
+// are copies of flat ones), so the transforms agree bitwise.
+template <int L, int E, int R, int NS, int DIR, bool STW = false, int R0 = 1>
 __device__ __forceinline__ void stage_compute(float2 (&v)[E], int q, const float2 *__restrict__ tw)
 {
     constexpr int Q = L / E;
@@ -242,7 +251,7 @@ __device__ __forceinline__ void stage_compute(float2 (&v)[E], int q, const float
             const int k = (q + Q * b) % NS;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = tw[r * k * (L / (NS * R))];
+                float2 w = STW ? tw[(NS - R0) + (r - 1) * NS + k] : tw[r * k * (L / (NS * R))];
                 if constexpr (DIR > 0) w.y = -w.y;
                 x[r] = cmul(x[r], w);
             }
@@ -293,18 +302,42 @@ __device__ __forceinline__ void exchange(float2 (&v)[E], const LdsView &s, int q
     if constexpr (TRAIL) __syncthreads();
 }
 
-template <int L, int E, int DIR, bool REV, int S, int O = 0>
+template <int L, int E, int DIR, bool REV, int S, int O = 0, bool STW = false>
 __device__ __forceinline__ void run_stages(float2 (&v)[E], const LdsView &s, int q,
                                            const float2 *__restrict__ tw)
 {
     constexpr int R = radix_at<L, REV, O>(S);
     constexpr int NS = ns_before<L, REV, O>(S);
-    stage_compute<L, E, R, NS, DIR>(v, q, tw);
+    stage_compute<L, E, R, NS, DIR, STW, first_radix<L, REV, O>()>(v, q, tw);
     if constexpr (S + 1 < Factors<L, O>::N) {
         constexpr int R2 = radix_at<L, REV, O>(S + 1);
         exchange<L, E, R, NS, R2>(v, s, q);
-        run_stages<L, E, DIR, REV, S + 1, O>(v, s, q, tw);
+        run_stages<L, E, DIR, REV, S + 1, O, STW>(v, s, q, tw);
     }
+}
+
+// Fill the staged twiddle table (stage_compute) of length L in radix order
+// O (stages in forward order) into `out` from the flat table `tw`: every
+// thread of the workgroup takes entries threadIdx.x, + blockDim.x, ...
+template <int L, int O, int S = 1>
+__device__ __forceinline__ void fill_staged_one(float2 *out, const float2 *__restrict__ tw, int i)
+{
+    if constexpr (S < Factors<L, O>::N) {
+        constexpr int R = radix_at<L, false, O>(S), NS = ns_before<L, false, O>(S);
+        constexpr int lo = NS - first_radix<L, false, O>(), hi = lo + NS * (R - 1);
+        if (i < hi) {
+            const int loc = i - lo;
+            const int r = 1 + loc / NS, k = loc % NS;
+            out[i] = tw[r * k * (L / (NS * R))];
+        } else {
+            fill_staged_one<L, O, S + 1>(out, tw, i);
+        }
+    }
+}
+template <int L, int O>
+__device__ __forceinline__ void fill_staged_twiddles(float2 *out, const float2 *__restrict__ tw)
+{
+    for (int i = threadIdx.x; i < L - first_radix<L, false, O>(); i += blockDim.x) fill_staged_one<L, O>(out, tw, i);
 }
 
 // Ping-pong form: exchange S uses buffer S mod 2, so only one barrier per
@@ -344,10 +377,11 @@ __device__ __forceinline__ void fft_pp(float2 (&v)[E], const LdsView &s0, const 
 // row q + Q*b + r*L/RL with RL = last_radix<L,REV>.  Every thread of the
 // workgroup must call it (it contains barriers when the transform has more
 // than one stage).
-template <int L, int E, int DIR, bool REV, int O = 0>
+template <int L, int E, int DIR, bool REV, int O = 0, bool STW = false>
 __device__ __forceinline__ void fft_e(float2 (&v)[E], const LdsView &s, int q, const float2 *__restrict__ tw)
 {
-    run_stages<L, E, DIR, REV, 0, O>(v, s, q, tw);
+    static_assert(!STW || !REV, "the staged twiddle table holds the forward stage order");
+    run_stages<L, E, DIR, REV, 0, O, STW>(v, s, q, tw);
 }
 
 template <int L, int DIR, bool REV>

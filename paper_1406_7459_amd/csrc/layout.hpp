@@ -19,6 +19,13 @@ __host__ __device__ constexpr int x_pitch(int nxc) { return (nxc + 15) & ~15; }
 // logical neighbours (tiles sharing 128-byte lines, mirror rows sharing a K~
 // row, neighbour cell planes) meet in one L2 at nearly the same time.  Ids
 // past the last multiple of 8 keep their place.
+// Stride between the (component, z) planes of the y-transformed spectrum
+// X2, in complex elements: Ly rows of xp plus 128 bytes.  Without the pad
+// the z pass's rows of one column sit a multiple of 16 KiB apart (256 rows
+// of 1088 bytes at Ly = 256), so one workgroup's loads share their low
+// address bits and crowd into few HBM channels.
+__host__ __device__ constexpr int x2_plane_stride(int Ly, int xp) { return Ly * xp + 16; }
+
 __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
 {
     const unsigned per = nb / 8u;

@@ -76,7 +76,7 @@ struct Plan {
     float *Kt = nullptr;         // [nzK][Ly/2+1][xp][6], kx < nxc used
     long long nK = 0;            // 6 nzK (Ly/2+1) nxc: the exported (unpadded) count
     float2 *X1 = nullptr;        // [3][nz][ny][xp]
-    float2 *X2 = nullptr;        // [3][nz][Ly][xp] (nz > 1 only)
+    float2 *X2 = nullptr;        // [3][nz] planes of Ly rows of xp, x2_plane_stride apart (nz > 1 only)
     float *H = nullptr;          // [3][N] demag field scratch for the step driver
     float *Sa = nullptr, *Sb = nullptr, *kacc = nullptr;  // stage states and RK4 accumulator
     double *part = nullptr;      // reduction partials

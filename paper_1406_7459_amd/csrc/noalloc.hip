@@ -48,7 +48,7 @@ static size_t static_need(const Plan &p)
 {
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t x1 = sizeof(float2) * 3 * (size_t)p.nz * p.ny * p.xp;
-    const size_t x2 = p.nz > 1 ? sizeof(float2) * 3 * (size_t)p.nz * p.Ly * p.xp : 0;
+    const size_t x2 = p.nz > 1 ? sizeof(float2) * 3 * (size_t)p.nz * x2_plane_stride(p.Ly, p.xp) : 0;
     return al(x1) + al(x2);
 }
 

@@ -22,16 +22,20 @@
 
 namespace mmk {
 
-// LDS layout: twiddles | 3P transforms of XS slots (float2) | H/S' rows
-// [3][2P][nx] (float, 16-byte aligned; sized for nx = L/2, the largest).
+// LDS layout: twiddles | 3P transforms of XS slots (float2).  The H/S' rows
+// [3][2P][nx] (float) share the transforms' space: they are written after
+// the inverse transforms' last exchange (whose trailing barrier every thread
+// has passed) and read into registers, behind a barrier, before the forward
+// transforms' first exchange; 3 2P nx floats never exceed the 6P XS floats.
+// Sharing leaves room for more resident workgroups per CU.
 template <int L> constexpr int xs_slots() { return lds_rows(L) + 1; }
-template <int L> __host__ __device__ constexpr size_t xs_rows_offset(int P)
+template <int L> __host__ __device__ constexpr size_t xs_rows_offset(int)
 {
-    return (((size_t)tw_slots<L>() + 3 * (size_t)P * xs_slots<L>()) * sizeof(float2) + 15) & ~(size_t)15;
+    return (size_t)tw_slots<L>() * sizeof(float2);  // 16-byte aligned: L is even
 }
 template <int L> __host__ __device__ constexpr size_t xs_lds_bytes(int P)
 {
-    return xs_rows_offset<L>(P) + 3 * 2 * (size_t)P * (L / 2) * sizeof(float);
+    return ((size_t)tw_slots<L>() + 3 * (size_t)P * xs_slots<L>()) * sizeof(float2);
 }
 
 // Inputs of one stage task: W consecutive cells of a row, their stage
@@ -51,7 +55,7 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
 {
     constexpr int E = Factors<L>::E, Q = L / E, NX = L / 2, XP = x_pitch(NX + 1);
     extern __shared__ float2 lds[];
-    const float2 *twl = stage_twiddles<L>(lds, tw);
+    const float2 *twl = row_twiddles<L, 0>(lds, tw);
     const int P = 1 << lp2;
     const int PQ = P * Q;
     const int t = threadIdx.x;
@@ -200,7 +204,7 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
                 }
                 v[b * R0 + r] = make_float2(A.x - B.y, A.y + B.x);
             }
-        fft_e<L, E, +1, false>(v, s, q, twl);
+        fft_e<L, E, +1, false, 0, true>(v, s, q, twl);
         constexpr int RL = last_radix<L, false>();
         float *ha = rows + g * rstride + 2 * p * nx_;
 #pragma unroll
@@ -244,7 +248,8 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
                 const bool in = !upper && i < nx_;
                 v[b * R0 + r] = make_float2(in && oka ? za[i] : 0.f, in && okb ? zb[i] : 0.f);
             }
-        fft_e<L, E, -1, false>(v, s, q, twl);
+        __syncthreads();  // every row read before the transforms reuse the space
+        fft_e<L, E, -1, false, 0, true>(v, s, q, twl);
         constexpr int RL = last_radix<L, false>();
         float2 *col = fbuf + (g * P + p) * XS;
 #pragma unroll
