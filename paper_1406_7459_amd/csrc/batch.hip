@@ -9,13 +9,15 @@
 // fixed sequence of such launches and is captured once into a HIP graph.
 //
 // Two launch modes.  Merged: one launch per pass kind over every instance
-// and every transform length, 128 threads a workgroup, a task naming its
-// instance, block and length; each length runs in the radix order of at most
-// 12 values per thread (order 1 for 3 2^a lengths); the product passes (z,
-// and y for nz = 1) share one launch per register class of their schedules
-// (at most 8 values per thread, 12), so the z passes of most instances are
-// not sized for the 12-value schedules; tasks are ordered longest transform
-// first.  At most 7 launches per stage.  Grouped: one launch
+// and every transform length (512 threads a workgroup for the row and
+// column passes, 256 for the products), a task naming its instance, block
+// and length; each length runs in the radix order of at most 12 values per
+// thread (order 1 for 3 2^a lengths); the product passes take two launches
+// (the z products of at most 8 values per thread; the y products of nz = 1
+// instances and the 12-value z products), so the many short z products of
+// thin films are sized for neither the larger schedules' registers nor the
+// long y products' LDS; tasks are ordered longest transform first.  At
+// most 7 launches per stage.  Grouped: one launch
 // per (pass kind, transform length), each group with its own tuned tile in
 // the default radix orders.
 #include <algorithm>
@@ -108,50 +110,75 @@ __global__ __launch_bounds__(256) void kb_copy(const BInst *__restrict__ B, cons
 }
 
 // ------------------------------------------------------------- merged ---
-// (a power of two no larger than the largest tile P, 128, so that a length
-// with one thread per transform still fits the tile encoding)
-constexpr int BM_THREADS = 128;
+// Threads of a merged launch: the row and column passes 512, so a long
+// transform still gets several columns (rows) per workgroup for coalesced
+// access; the products 256 (long y products, 12-value z products), which
+// bounds their ping-pong LDS (proportional to values per thread x threads),
+// and 128 for the short z products, whose P = 128 / Q columns per task stay
+// within the half spectra of small films.  Every length of a launch runs P
+// = threads / Q transforms of Q = L / E threads each.
 
-// schedule variant of length L in the merged launches: radix order 1 (radix
-// 3 then 4s, 12 values per thread) for 3 2^a lengths, the default otherwise
+// Schedule variant of length L in the merged launches: radix order 1 (radix
+// 3 then 4s, 12 values per thread) for 3 2^a lengths, the default otherwise.
 template <int L> constexpr bool bm_alt() { return L >= 24 && L % 3 == 0; }
+template <int L> constexpr bool bm_calt() { return bm_alt<L>(); }
 template <int L> constexpr int bm_var() { return bm_alt<L>() ? 2 : 0; }     // single-component passes
-template <int L> constexpr int bm_cvar() { return bm_alt<L>() ? 3 : 0; }    // product passes
-template <int L> constexpr int bm_e()
+template <int L> constexpr int bm_cvar() { return bm_calt<L>() ? 3 : 0; }   // product passes
+template <int L, bool CONV> constexpr int bm_e()
 {
-    if constexpr (bm_alt<L>()) return Factors<L, 1>::E;
+    if constexpr (CONV ? bm_calt<L>() : bm_alt<L>()) return Factors<L, 1>::E;
     else return Factors<L>::E;
 }
-template <int L> constexpr int bm_lp2()
+template <int T, int L, bool CONV> constexpr int bm_lp2()
 {
     int lp = 0;
-    while ((1 << lp) * (L / bm_e<L>()) < BM_THREADS) ++lp;
+    while ((1 << lp) * (L / bm_e<L, CONV>()) < T) ++lp;
     return lp;
 }
 
 // Launch slots of the merged mode: the x and y passes one launch each; the
-// product passes (z for nz > 1, y for nz = 1) one launch per register class
-// of their schedules (at most 8 values per thread, and 12), so the smaller
-// lengths' launch is not sized for the larger schedules' registers.
+// product passes two: A the z products of schedules with at most 8 values
+// per thread, B the y products (nz = 1) and the z products of 12 values per
+// thread.  Small-length z products (the bulk of the tasks of thin films)
+// then share neither the larger schedules' registers nor the long y
+// products' LDS.
 enum { MS_XFWD = 0, MS_YFWD = 1, MS_CONV_A = 2, MS_CONV_B = 3, MS_YINV = 4, MS_XINV = 5, MS_COUNT = 6 };
-template <int L> constexpr int bm_class() { return bm_e<L>() > 8 ? 1 : 0; }
+template <int L> constexpr int bm_class() { return bm_alt<L>() ? 1 : 0; }  // 12 values per thread
+__host__ __device__ constexpr int bm_threads(int slot)
+{
+    return slot == MS_CONV_A ? 128 : (slot == MS_CONV_B ? 256 : 512);
+}
 constexpr int BM_YCONV = 1 << 16;  // task flag: product along y (nz = 1)
+constexpr int BM_EDGE = 1 << 17;   // task flag: edge workgroup (the last kx column, column_of)
+constexpr int BM_LEN = (1 << 16) - 1;
 
-// t = (instance, block, plane or ky, transform length [| BM_YCONV])
+// t = (instance, block, plane or ky (an edge task: row group), transform
+// length [| BM_YCONV] [| BM_EDGE])
 template <int SLOT, int L>
 __device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
 {
-    constexpr int V = bm_var<L>(), lp2 = bm_lp2<L>();
+    constexpr bool CONV = SLOT == MS_CONV_A || SLOT == MS_CONV_B;
+    constexpr int V = bm_var<L>(), lp2 = bm_lp2<bm_threads(SLOT), L, CONV>();
+    static_assert((1 << lp2) * (L / bm_e<L, CONV>()) == bm_threads(SLOT), "P transforms fill the workgroup exactly");
     if constexpr (SLOT == MS_XFWD) xfwd_body<L, V>(bsel(I, sel), I.X1, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
-    else if constexpr (SLOT == MS_YFWD) yfwd_body<L, V>(I.X1, I.X2, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z);
-    else if constexpr (SLOT == MS_YINV) yinv_body<L, V>(I.X2, I.X1, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z);
+    else if constexpr (SLOT == MS_YFWD)
+        yfwd_body<L, V>(I.X1, I.X2, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z, (t.w & BM_EDGE) ? 3 * I.nz : 0);
+    else if constexpr (SLOT == MS_YINV)
+        yinv_body<L, V>(I.X2, I.X1, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z, (t.w & BM_EDGE) ? 3 * I.nz : 0);
     else if constexpr (SLOT == MS_XINV) xinv_body<L, V>(I.X1, I.Hout, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
-    else if constexpr (bm_class<L>() == SLOT - MS_CONV_A) {
-        constexpr int O = bm_alt<L>() ? 1 : 0;
-        if (t.w & BM_YCONV)
-            conv_reg3_body<L, false, O>(I.X1, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.ny, lp2, I.tw1, t.y, 0);
-        else
-            conv_reg3_body<L, true, O>(I.X2, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.nz, lp2, I.tw2, t.y, t.z);
+    else {
+        // product slots: A the z products of the smaller schedules, B the
+        // y products (nz = 1) and the z products of 12 values per thread
+        constexpr int O = bm_calt<L>() ? 1 : 0;
+        const bool y = (t.w & BM_YCONV) != 0;
+        if constexpr (SLOT == MS_CONV_B) {
+            if (y) conv_reg3_body<L, false, O>(I.X1, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.ny, lp2, I.tw1, t.y, 0);
+        }
+        if constexpr (bm_class<L>() == SLOT - MS_CONV_A) {
+            if (!y)
+                conv_reg3_body<L, true, O>(I.X2, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.nz, lp2, I.tw2, t.y, t.z,
+                                           (t.w & BM_EDGE) ? I.Ly : 0);
+        }
     }
 }
 
@@ -160,13 +187,13 @@ __device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
         X(768) X(1024)
 
 template <int SLOT>
-__global__ __launch_bounds__(BM_THREADS) void kb_merged(const BInst *__restrict__ B, const int4 *__restrict__ T,
+__global__ __launch_bounds__(bm_threads(SLOT)) void kb_merged(const BInst *__restrict__ B, const int4 *__restrict__ T,
                                                          int sel)
 {
     const bool rows = SLOT == MS_XFWD || SLOT == MS_XINV;
     const int4 t = T[rows ? blockIdx.x : xcd_block(blockIdx.x, gridDim.x)];
     const BInst &I = B[t.x];
-    switch (t.w & (BM_YCONV - 1)) {
+    switch (t.w & BM_LEN) {
 #define MMK_CASE(LEN) case LEN: bm_run<SLOT, LEN>(I, t, sel); break;
         MMK_BM_LENGTHS(MMK_CASE)
 #undef MMK_CASE
@@ -175,18 +202,43 @@ __global__ __launch_bounds__(BM_THREADS) void kb_merged(const BInst *__restrict_
 }
 
 // P, variant and tile of length L in the merged launches (host side)
-static int bm_tile(int pass, int L)
+// P (transforms per workgroup) of length L in merged slot `slot`, and the
+// schedule variant of `pass` there
+static int bm_P(int slot, int L)
 {
     switch (L) {
 #define MMK_CASE(LEN) \
-    case LEN: return (1 << bm_lp2<LEN>()) + 256 * (pass == MM_PASS_ZCONV || pass == MM_PASS_YCONV ? bm_cvar<LEN>() : bm_var<LEN>());
+    case LEN:                                                                  \
+        return slot == MS_CONV_A   ? (1 << bm_lp2<bm_threads(MS_CONV_A), LEN, true>())  \
+               : slot == MS_CONV_B ? (1 << bm_lp2<bm_threads(MS_CONV_B), LEN, true>())  \
+                                   : (1 << bm_lp2<bm_threads(MS_XFWD), LEN, false>());
         MMK_BM_LENGTHS(MMK_CASE)
 #undef MMK_CASE
     default: return 0;
     }
 }
+static int bm_variant(int pass, int L)
+{
+    switch (L) {
+#define MMK_CASE(LEN) \
+    case LEN: return pass == MM_PASS_ZCONV || pass == MM_PASS_YCONV ? bm_cvar<LEN>() : bm_var<LEN>();
+        MMK_BM_LENGTHS(MMK_CASE)
+#undef MMK_CASE
+    default: return 0;
+    }
+}
+// LDS bytes of P transforms of length L for `pass` in variant var: linear in
+// P (twiddles plus P transforms' slots), taken from the shapes at P = 1, 2
+static size_t bm_lds(int pass, int L, int var, int P)
+{
+    int t1, t2, m;
+    size_t l1 = 0, l2 = 0;
+    shape_for(pass, L, 1 + 256 * var, t1, l1, m);
+    shape_for(pass, L, 2 + 256 * var, t2, l2, m);
+    return l1 + (size_t)(P - 1) * (l2 - l1);
+}
 
-// register class (merged product launch) of length L
+// register class of length L (0: at most 8 values per thread, 1: 12)
 static int bm_class_of(int L)
 {
     switch (L) {
@@ -299,7 +351,7 @@ static int build_tasks(BatchImpl &b, BGroup &g)
 }
 
 // Task table of merged launch slot `slot`: every instance with the pass
-// active (and, for a product slot, its length in the slot's register class),
+// active (and, for a product slot, its product in that slot),
 // longest transform first, each with its length's tile; the launch's LDS is
 // the largest any of its lengths needs.
 static void make_merged(BatchImpl &b, int slot)
@@ -319,7 +371,8 @@ static void make_merged(BatchImpl &b, int slot)
     };
     auto len_of = [&](const BInst &I) {
         const int L = pass_len_of(I, pass_of(I));
-        if (conv && L && bm_class_of(L) != slot - MS_CONV_A) return 0;
+        // z products by register class; every y product in slot B
+        if (conv && L && (I.nz > 1 ? bm_class_of(L) : 1) != slot - MS_CONV_A) return 0;
         return L;
     };
     std::vector<int> order;
@@ -331,12 +384,17 @@ static void make_merged(BatchImpl &b, int slot)
         const BInst &I = b.inst[i];
         const int pass = pass_of(I);
         const int L = len_of(I);
-        const int tile = bm_tile(pass, L), P = tile & 255;
-        int threads = 0, maxt = 0;
-        size_t lds = 0;
-        shape_for(pass, L, tile, threads, lds, maxt);
-        g.lds = std::max(g.lds, lds);
+        const int P = bm_P(slot, L);
+        g.lds = std::max(g.lds, bm_lds(pass, L, bm_variant(pass, L), P));
         const int nxc = I.Lx / 2 + 1, ncr = I.nz * I.ny;
+        // column passes: when P divides the Lx/2 columns below the last,
+        // tiles over those and edge tasks (dispatched first) for the last
+        const bool edge = P > 1 && (I.Lx / 2) % P == 0;
+        const int ntm = edge ? (I.Lx / 2) / P : (nxc + P - 1) / P;
+        auto edges = [&](int nrows) {
+            if (edge)
+                for (int e = 0; e < (nrows + P - 1) / P; ++e) g.tasks.push_back(make_int4(i, 0, e, L | BM_EDGE));
+        };
         switch (pass) {
         case MM_PASS_XFWD:
         case MM_PASS_XINV: {
@@ -346,12 +404,14 @@ static void make_merged(BatchImpl &b, int slot)
         }
         case MM_PASS_YFWD:
         case MM_PASS_YINV:
+            edges(3 * I.nz);
             for (int pl = 0; pl < 3 * I.nz; ++pl)
-                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx) g.tasks.push_back(make_int4(i, bx, pl, L));
+                for (int bx = 0; bx < ntm; ++bx) g.tasks.push_back(make_int4(i, bx, pl, L));
             break;
         case MM_PASS_ZCONV:
+            edges(I.Ly);
             for (int m = 0; m < I.Ly / 2; ++m)
-                for (int bx = 0; bx < (nxc + P - 1) / P; ++bx)
+                for (int bx = 0; bx < ntm; ++bx)
                     for (int h = 0; h < 2; ++h)
                         g.tasks.push_back(make_int4(i, bx, ky_of_slot(2 * m + h, I.Ly / 2), L));
             break;
@@ -444,7 +504,7 @@ static int merged_launch(const BatchImpl &b, int slot, const BInst *table, int s
 {
     const BGroup &g = b.mg[slot];
     if (g.tasks.empty()) return MM_OK;
-    const dim3 grid((unsigned)g.tasks.size()), block(BM_THREADS);
+    const dim3 grid((unsigned)g.tasks.size()), block((unsigned)bm_threads(slot));
     switch (slot) {
     case MS_XFWD: hipLaunchKernelGGL(kb_merged<MS_XFWD>, grid, block, g.lds, s, table, g.d, sel); break;
     case MS_YFWD: hipLaunchKernelGGL(kb_merged<MS_YFWD>, grid, block, g.lds, s, table, g.d, sel); break;

@@ -116,16 +116,19 @@ struct KInfo {
     int conv_max;  // launch bound of the reg3 product kernel
     int Eo[3];     // values per thread of radix orders 0, 1, 2 (0: no such order)
     int maxo[3];   // launch bound of the reg3 kernel in each order
+    int No[3];     // stages of each order (exchange buffers only when > 1)
 };
 
 template <int L, int O> static constexpr int order_e() { if constexpr (Factors<L, O>::valid) return Factors<L, O>::E; else return 0; }
 template <int L, int O> static constexpr int order_max() { if constexpr (Factors<L, O>::valid) return conv_max_threads<L, O>(); else return 0; }
+template <int L, int O> static constexpr int order_n() { if constexpr (Factors<L, O>::valid) return Factors<L, O>::N; else return 0; }
 
 template <int L> static KInfo kinfo()
 {
     return {Factors<L>::E, ept<L, 1>(), Factors<L>::N, conv_max_threads<L>(),
             {order_e<L, 0>(), order_e<L, 1>(), order_e<L, 2>()},
-            {order_max<L, 0>(), order_max<L, 1>(), order_max<L, 2>()}};
+            {order_max<L, 0>(), order_max<L, 1>(), order_max<L, 2>()},
+            {order_n<L, 0>(), order_n<L, 1>(), order_n<L, 2>()}};
 }
 
 #define MMK_ALL_LENGTHS(X)                                                                               \
@@ -189,6 +192,8 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
     KInfo k{};
     if (!kinfo_for(L, k)) return false;
     const int P = tile & 255, var = tile >> 8;
+    // twiddles are copied to LDS whenever the default order has several
+    // stages (tw_slots); exchange buffers when the schedule's own order has
     const size_t tws = k.nstage > 1 ? (size_t)L : 0;
     maxt = 1024;
     if (is_conv(pass)) {
@@ -198,7 +203,7 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
             threads = P * (L / k.Eo[o]);
             maxt = k.maxo[o];
             // two exchange buffers (ping-pong transforms)
-            lds = (tws + (k.nstage > 1 ? 2 * (size_t)lds_rows(L) * P : 0)) * sizeof(float2);
+            lds = (tws + (k.No[o] > 1 ? 2 * (size_t)lds_rows(L) * P : 0)) * sizeof(float2);
         } else if (var == 1 || var == 2) {
             const int E = var == 1 ? k.E0 : k.E1;
             if (var == 2 && k.E1 == k.E0) return false;
@@ -214,7 +219,7 @@ bool shape_for(int pass, int L, int tile, int &threads, size_t &lds, int &maxt)
         const int E = var == 0 ? k.E0 : (var == 1 ? k.E1 : k.Eo[var - 1]);
         threads = P * (L / E);
         // the x forward separates its packed rows through LDS even for one stage
-        const bool needs = k.nstage > 1 || pass == MM_PASS_XFWD;
+        const bool needs = (var >= 2 ? k.No[var - 1] : k.nstage) > 1 || pass == MM_PASS_XFWD;
         lds = (tws + (needs ? (is_rows(pass) ? (size_t)P * (lds_rows(L) + 1) : (size_t)lds_rows(L) * P) : 0)) *
               sizeof(float2);
     }

@@ -46,14 +46,14 @@ def _plan(mm, s, d, mode):
             plan.set_tile("xstage", 0)
             _set_variant(mm, plan, "xfwd", 2)
             _set_variant(mm, plan, "xinv", 2)
-        if _alt(inf["Ly"]):
-            if s[2] > 1:
+        if s[2] > 1:
+            if _alt(inf["Ly"]):
                 _set_variant(mm, plan, "yfwd", 2)
                 _set_variant(mm, plan, "yinv", 2)
-            else:
-                _set_variant(mm, plan, "yconv", 3)
-        if s[2] > 1 and _alt(inf["Lz"]):
-            _set_variant(mm, plan, "zconv", 3)
+            if _alt(inf["Lz"]):
+                _set_variant(mm, plan, "zconv", 3)
+        elif _alt(inf["Ly"]):
+            _set_variant(mm, plan, "yconv", 3)
     return plan
 
 
