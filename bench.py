@@ -279,10 +279,11 @@ def summarize_counters(workload, pmc_dir, trace_db):
             "# cycles (a wave64 FP32 VALU op without packed math) / (1024 SIMDs x 2.4 GHz); the trace median",
             "# duration; valu_frac = floor / median; lds_conf = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS;",
             "# wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (share of wave time waiting on a dependency);",
+            "# w_any = SQ_WAIT_ANY / SQ_WAVE_CYCLES (waiting on anything, barriers included);",
             "# valu_act = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES",
-            "%-7s %5s %2s %7s %6s %6s %5s %6s %7s %8s %7s %6s %6s %6s %6s" % (
+            "%-7s %5s %2s %7s %6s %6s %5s %6s %7s %8s %7s %6s %6s %6s %6s %6s" % (
                 "pass", "tile", "s", "waves", "valu", "lds", "salu", "vmem", "floor", "median", "v_frac",
-                "ldsc", "wait", "v_act", "n")]
+                "ldsc", "wait", "w_any", "v_act", "n")]
     for key in sorted(vals):
         c = {k: statistics.median(v) for k, v in vals[key].items()}
         w = c.get("SQ_WAVES", 0.0)
@@ -292,11 +293,11 @@ def summarize_counters(workload, pmc_dir, trace_db):
         med = statistics.median(dur[key]) if key in dur else float("nan")
         wc = c.get("SQ_WAVE_CYCLES", 0.0) or float("nan")
         lds_act = c.get("SQ_ACTIVE_INST_LDS", 0.0) or float("nan")
-        out.append("%-7s %5d %2d %7d %6.0f %6.0f %5.0f %6.1f %7.2f %8.2f %7.2f %6.3f %6.3f %6.3f %6d" % (
+        out.append("%-7s %5d %2d %7d %6.0f %6.0f %5.0f %6.1f %7.2f %8.2f %7.2f %6.3f %6.3f %6.3f %6.3f %6d" % (
             key[0], key[1], key[2], w, c.get("SQ_INSTS_VALU", 0) / w, c.get("SQ_INSTS_LDS", 0) / w,
             c.get("SQ_INSTS_SALU", 0) / w, (c.get("SQ_INSTS_VMEM_RD", 0) + c.get("SQ_INSTS_VMEM_WR", 0)) / w,
             floor, med, floor / med, c.get("SQ_LDS_BANK_CONFLICT", 0) / lds_act,
-            c.get("SQ_WAIT_INST_ANY", 0) / wc, c.get("SQ_ACTIVE_INST_VALU", 0) / wc,
+            c.get("SQ_WAIT_INST_ANY", 0) / wc, c.get("SQ_WAIT_ANY", 0) / wc, c.get("SQ_ACTIVE_INST_VALU", 0) / wc,
             len(vals[key].get("SQ_WAVES", []))))
     return "\n".join(out) + "\n"
 
@@ -647,7 +648,7 @@ def table1_euler(torch, mm, W):
     return out
 
 
-def relax_sweep(torch, mm, W, sizes=(8, 16, 32, 64), tol=1e3, max_steps=40000, check_every=250, dt=5e-14):
+def relax_sweep(torch, mm, W, sizes=(8, 16, 32, 64), tol=1e3, max_steps=120000, check_every=250, dt=5e-14):
     """The structure of the paper's cube benchmark (relaxation of N^3 cubes
     with uniaxial anisotropy to the minimum-energy state): mm_llg_relax on
     cubes of the cube workload's material with alpha 1, from a state along
