@@ -119,20 +119,29 @@ __global__ __launch_bounds__(256) void kb_copy(const BInst *__restrict__ B, cons
 // = threads / Q transforms of Q = L / E threads each.
 
 // Schedule variant of length L in the merged launches: radix order 1 (radix
-// 3 then 4s, 12 values per thread) for 3 2^a lengths, the default otherwise.
+// 3 then 4s, 12 values per thread) for 3 2^a lengths, the default otherwise;
+// the y passes also take order 1 (radix 16 first, 16 values per thread) for
+// 2^a lengths >= 512, which halves their threads per column and doubles
+// the columns (contiguous bytes of each row) a 512-thread task covers.
+// KIND: 0 x passes, 1 y passes, 2 products.
 template <int L> constexpr bool bm_alt() { return L >= 24 && L % 3 == 0; }
-template <int L> constexpr bool bm_calt() { return bm_alt<L>(); }
-template <int L> constexpr int bm_var() { return bm_alt<L>() ? 2 : 0; }     // single-component passes
-template <int L> constexpr int bm_cvar() { return bm_calt<L>() ? 3 : 0; }   // product passes
-template <int L, bool CONV> constexpr int bm_e()
+template <int L, int KIND> constexpr bool bm_o1()
 {
-    if constexpr (CONV ? bm_calt<L>() : bm_alt<L>()) return Factors<L, 1>::E;
+    return bm_alt<L>() || (KIND == 1 && L >= 512 && L % 3 != 0);
+}
+template <int L, int KIND> constexpr int bm_v()
+{
+    return bm_o1<L, KIND>() ? (KIND == 2 ? 3 : 2) : 0;  // tile variant of radix order 1
+}
+template <int L, int KIND> constexpr int bm_e()
+{
+    if constexpr (bm_o1<L, KIND>()) return Factors<L, 1>::E;
     else return Factors<L>::E;
 }
-template <int T, int L, bool CONV> constexpr int bm_lp2()
+template <int T, int L, int KIND> constexpr int bm_lp2()
 {
     int lp = 0;
-    while ((1 << lp) * (L / bm_e<L, CONV>()) < T) ++lp;
+    while ((1 << lp) * (L / bm_e<L, KIND>()) < T) ++lp;
     return lp;
 }
 
@@ -157,9 +166,9 @@ constexpr int BM_LEN = (1 << 16) - 1;
 template <int SLOT, int L>
 __device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
 {
-    constexpr bool CONV = SLOT == MS_CONV_A || SLOT == MS_CONV_B;
-    constexpr int V = bm_var<L>(), lp2 = bm_lp2<bm_threads(SLOT), L, CONV>();
-    static_assert((1 << lp2) * (L / bm_e<L, CONV>()) == bm_threads(SLOT), "P transforms fill the workgroup exactly");
+    constexpr int KIND = (SLOT == MS_CONV_A || SLOT == MS_CONV_B) ? 2 : ((SLOT == MS_YFWD || SLOT == MS_YINV) ? 1 : 0);
+    constexpr int V = bm_v<L, KIND>(), lp2 = bm_lp2<bm_threads(SLOT), L, KIND>();
+    static_assert((1 << lp2) * (L / bm_e<L, KIND>()) == bm_threads(SLOT), "P transforms fill the workgroup exactly");
     if constexpr (SLOT == MS_XFWD) xfwd_body<L, V>(bsel(I, sel), I.X1, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
     else if constexpr (SLOT == MS_YFWD)
         yfwd_body<L, V>(I.X1, I.X2, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z, (t.w & BM_EDGE) ? 3 * I.nz : 0);
@@ -169,7 +178,7 @@ __device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
     else {
         // product slots: A the z products of the smaller schedules, B the
         // y products (nz = 1) and the z products of 12 values per thread
-        constexpr int O = bm_calt<L>() ? 1 : 0;
+        constexpr int O = bm_o1<L, 2>() ? 1 : 0;
         const bool y = (t.w & BM_YCONV) != 0;
         if constexpr (SLOT == MS_CONV_B) {
             if (y) conv_reg3_body<L, false, O>(I.X1, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.ny, lp2, I.tw1, t.y, 0);
@@ -209,9 +218,10 @@ static int bm_P(int slot, int L)
     switch (L) {
 #define MMK_CASE(LEN) \
     case LEN:                                                                  \
-        return slot == MS_CONV_A   ? (1 << bm_lp2<bm_threads(MS_CONV_A), LEN, true>())  \
-               : slot == MS_CONV_B ? (1 << bm_lp2<bm_threads(MS_CONV_B), LEN, true>())  \
-                                   : (1 << bm_lp2<bm_threads(MS_XFWD), LEN, false>());
+        return slot == MS_CONV_A   ? (1 << bm_lp2<bm_threads(MS_CONV_A), LEN, 2>())                   \
+               : slot == MS_CONV_B ? (1 << bm_lp2<bm_threads(MS_CONV_B), LEN, 2>())                   \
+               : (slot == MS_YFWD || slot == MS_YINV) ? (1 << bm_lp2<bm_threads(MS_YFWD), LEN, 1>()) \
+                                   : (1 << bm_lp2<bm_threads(MS_XFWD), LEN, 0>());
         MMK_BM_LENGTHS(MMK_CASE)
 #undef MMK_CASE
     default: return 0;
@@ -221,7 +231,9 @@ static int bm_variant(int pass, int L)
 {
     switch (L) {
 #define MMK_CASE(LEN) \
-    case LEN: return pass == MM_PASS_ZCONV || pass == MM_PASS_YCONV ? bm_cvar<LEN>() : bm_var<LEN>();
+    case LEN:                                                            \
+        return pass == MM_PASS_ZCONV || pass == MM_PASS_YCONV ? bm_v<LEN, 2>() \
+               : (pass == MM_PASS_YFWD || pass == MM_PASS_YINV) ? bm_v<LEN, 1>() : bm_v<LEN, 0>();
         MMK_BM_LENGTHS(MMK_CASE)
 #undef MMK_CASE
     default: return 0;

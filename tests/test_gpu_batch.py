@@ -38,7 +38,8 @@ def _set_variant(mm, plan, pname, var):
 
 def _plan(mm, s, d, mode):
     """A per-instance plan running the radix orders the batch's mode runs:
-    merged launches take order 1 for transform lengths 3 * 2^a >= 24."""
+    merged launches take order 1 for transform lengths 3 * 2^a >= 24, and
+    in the y passes also for 2^a lengths >= 512."""
     plan = mm.Plan(*s, *d)
     if mode == "merged":
         inf = plan.info()
@@ -47,7 +48,7 @@ def _plan(mm, s, d, mode):
             _set_variant(mm, plan, "xfwd", 2)
             _set_variant(mm, plan, "xinv", 2)
         if s[2] > 1:
-            if _alt(inf["Ly"]):
+            if _alt(inf["Ly"]) or (inf["Ly"] >= 512 and inf["Ly"] % 3):
                 _set_variant(mm, plan, "yfwd", 2)
                 _set_variant(mm, plan, "yinv", 2)
             if _alt(inf["Lz"]):
