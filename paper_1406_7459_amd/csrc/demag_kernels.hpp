@@ -476,6 +476,49 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
         }
 }
 
+// Input of the packed x inverse at this thread's rows k = q + Q b + r L/R0:
+// z_k = A_k + i B_k for the half spectra A (row a, at sa) and B (row b, at
+// sb), extended Hermitian-wise (A_{L-k} = conj A_k) and with the imaginary
+// parts of the k = 0 and k = L/2 bins dropped (the bins of a real row are
+// real there); an absent row (ok false) enters as zeros.  Every load is
+// issued before any value is used, from rows clamped into the grid and
+// masked afterwards: with the loads in branches, each conjugation waited
+// for its own load, so a thread's loads ran one after another.
+template <int L, int E, int R0, int Q>
+__device__ __forceinline__ void x_inverse_gather(const float2 *sa, const float2 *sb, bool oka, bool okb, int q,
+                                                 float2 (&v)[E])
+{
+    constexpr int NX = L / 2;
+    float2 la[E], lb[E];
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int k = q + Q * b + r * (L / R0);
+            const int kk = k <= NX ? k : L - k;
+            la[b * R0 + r] = sa[kk];
+            lb[b * R0 + r] = sb[kk];
+        }
+#pragma unroll
+    for (int b = 0; b < E / R0; ++b)
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int i = b * R0 + r;
+            const int k = q + Q * b + r * (L / R0);
+            float2 A = la[i], B = lb[i];
+            if (k > NX) {
+                A.y = -A.y;
+                B.y = -B.y;
+            } else if (k == 0 || k == NX) {
+                A.y = 0.f;
+                B.y = 0.f;
+            }
+            if (!oka) A = make_float2(0.f, 0.f);
+            if (!okb) B = make_float2(0.f, 0.f);
+            v[i] = make_float2(A.x - B.y, A.y + B.x);
+        }
+}
+
 // x inverse, complex-to-real, two rows per transform: Z = A + iB with A, B
 // the Hermitian half-spectra of rows 2m and 2m+1; Re/Im of the inverse are
 // the two real rows.  Keep i < nx.
@@ -494,29 +537,12 @@ __device__ __forceinline__ void xinv_body(const float2 *__restrict__ X1, float *
     x_pair_rows((bx << lp2) + p, ncr, ra, oka, okb);
     const int rb = ra + 1;
     const LdsView s{lds + tw_slots<L>(), 1, p * (lds_rows(L) + 1)};
-    const float2 *sa = X1 + (size_t)ra * XP;
-    const float2 *sb = X1 + (size_t)rb * XP;
+    const int ca = oka ? ra : 0;  // rows clamped into the grid (masked in the gather)
+    const float2 *sa = X1 + (size_t)ca * XP;
+    const float2 *sb = X1 + (size_t)(okb ? rb : ca) * XP;
     float2 v[E];
     constexpr int R0 = first_radix<L, false, OV>();
-#pragma unroll
-    for (int b = 0; b < E / R0; ++b)
-#pragma unroll
-        for (int r = 0; r < R0; ++r) {
-            const int k = q + Q * b + r * (L / R0);
-            float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-            if (k <= NX) {
-                if (oka) A = sa[k];
-                if (okb) B = sb[k];
-                if (k == 0 || k == NX) {  // bins of a real row are real there
-                    A.y = 0.f;
-                    B.y = 0.f;
-                }
-            } else {
-                if (oka) A = cconj(sa[L - k]);
-                if (okb) B = cconj(sb[L - k]);
-            }
-            v[b * R0 + r] = make_float2(A.x - B.y, A.y + B.x);
-        }
+    x_inverse_gather<L, E, R0, Q>(sa, sb, oka, okb, q, v);
     fft_e<L, E, +1, false, OV, true>(v, s, q, twl);
     constexpr int RL = last_radix<L, false, OV>();
     float *da = H + (size_t)ra * nx;

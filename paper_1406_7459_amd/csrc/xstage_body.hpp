@@ -181,29 +181,12 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
 
     // 1. inverse C2R of rows ra, rb of component g (as xinv_body)
     {
-        const float2 *sa = X1 + ((size_t)g * ncr + ra) * XP;
-        const float2 *sb = sa + XP;
+        const size_t ca = (size_t)g * ncr + (oka ? ra : 0);  // rows clamped into the grid (masked in the gather)
+        const float2 *sa = X1 + ca * XP;
+        const float2 *sb = X1 + (okb ? ca + 1 : ca) * XP;
         float2 v[E];
         constexpr int R0 = first_radix<L, false>();
-#pragma unroll
-        for (int b = 0; b < E / R0; ++b)
-#pragma unroll
-            for (int r = 0; r < R0; ++r) {
-                const int k = q + Q * b + r * (L / R0);
-                float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-                if (k <= NX) {
-                    if (oka) A = sa[k];
-                    if (okb) B = sb[k];
-                    if (k == 0 || k == NX) {
-                        A.y = 0.f;
-                        B.y = 0.f;
-                    }
-                } else {
-                    if (oka) A = cconj(sa[L - k]);
-                    if (okb) B = cconj(sb[L - k]);
-                }
-                v[b * R0 + r] = make_float2(A.x - B.y, A.y + B.x);
-            }
+        x_inverse_gather<L, E, R0, Q>(sa, sb, oka, okb, q, v);
         fft_e<L, E, +1, false, 0, true>(v, s, q, twl);
         constexpr int RL = last_radix<L, false>();
         float *ha = rows + g * rstride + 2 * p * nx_;
