@@ -204,9 +204,11 @@ __global__ __launch_bounds__(256) void k_reduce_cells(const float *__restrict__ 
             const float v = s[id];
             finite = finite && isfinite(v);
             m[a] = v;
-            const double xm = i > 0 ? s[id - 1] : v, xp = i < nx - 1 ? s[id + 1] : v;
-            const double ym = j > 0 ? s[id - sy] : v, yp = j < ny - 1 ? s[id + sy] : v;
-            const double zm = k > 0 ? s[id - sz] : v, zp = k < nz - 1 ? s[id + sz] : v;
+            // a missing neighbour reads the cell itself (clamped index: every
+            // load is issued unconditionally)
+            const double xm = s[i > 0 ? id - 1 : id], xp = s[i < nx - 1 ? id + 1 : id];
+            const double ym = s[j > 0 ? id - sy : id], yp = s[j < ny - 1 ? id + sy : id];
+            const double zm = s[k > 0 ? id - sz : id], zp = s[k < nz - 1 ? id + sz : id];
             mxp[a] = xp;
             myp[a] = yp;
             mzp[a] = zp;

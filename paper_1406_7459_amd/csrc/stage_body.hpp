@@ -183,8 +183,11 @@ __device__ __forceinline__ void stage_body_vec(const float *S, const float *__re
         vyp[a] = ldv32<V>(s, yp);
         vzm[a] = ldv32<V>(s, zm);
         vzp[a] = ldv32<V>(s, zp);
-        left[a] = i > 0 ? ld32(s, id - 1) : lane_of<W>(vs[a], 0);
-        right[a] = i + W < (unsigned)nx ? ld32(s, id + W) : lane_of<W>(vs[a], W - 1);
+        // x neighbours outside the group: at a free edge the group's own end
+        // cell, read again (not selected from vs, so the load is issued
+        // unconditionally and never waits on vs)
+        left[a] = ld32(s, i > 0 ? id - 1 : id);
+        right[a] = ld32(s, i + W < (unsigned)nx ? id + W : id + W - 1);
         vhd[a] = ldv32<V>(Hd + (size_t)a * n, id);
         vmn[a] = ldv32<V>(Mn + (size_t)a * n, id);
         if constexpr (STAGE == 2 || STAGE == 3 || STAGE == 4) vka[a] = ldv32<V>(kacc + (size_t)a * n, id);

@@ -118,8 +118,10 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
                     T.ka[a][w] = (STAGE == 2 || STAGE == 3 || STAGE == 4) ? lane_of<W>(vka, w) : 0.f;
                 }
             }
-            T.left[a] = i > 0 ? ld32(sc, id - 1) : T.m[a][0];
-            T.right[a] = i + W < nx ? ld32(sc, id + W) : T.m[a][W - 1];
+            // at a free edge the task's own end cell, read again: no load
+            // waits on another
+            T.left[a] = ld32(sc, i > 0 ? id - 1 : id);
+            T.right[a] = ld32(sc, i + W < nx ? id + W : id + W - 1);
         }
         return true;
     };
