@@ -250,7 +250,6 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
 {
     constexpr int E = Factors<L, O>::E, Q = L / E, NH = L / 2;
     extern __shared__ float2 lds[];
-    const float2 *twl = stage_twiddles<L>(lds, tw);
     const int P = 1 << lp2;
     const int t = threadIdx.x;
     const int p = t & (P - 1), q = t >> lp2;
@@ -280,6 +279,9 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
             vb[b * R0 + r] = ld ? float2(base[cs + o]) : make_float2(0.f, 0.f);
             vc[b * R0 + r] = ld ? float2(base[2 * cs + o]) : make_float2(0.f, 0.f);
         }
+    // twiddles staged after this thread's loads are issued (the table's
+    // load latency overlaps them)
+    const float2 *twl = stage_twiddles<L>(lds, tw);
     fft_pp<L, -1, false, O>(va, s, s1, q, twl);
     fft_pp<L, -1, false, O>(vb, s, s1, q, twl);
     fft_pp<L, -1, false, O>(vc, s, s1, q, twl);
@@ -342,7 +344,6 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
 {
     constexpr int E = ept<L, V>(), Q = L / E, NH = L / 2;
     extern __shared__ float2 lds[];
-    const float2 *twl = stage_twiddles<L>(lds, tw);
     const int P = 1 << lp2;
     const int PQ = P * Q;
     const int g = threadIdx.x / PQ;
@@ -396,6 +397,9 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
             }
     };
     if constexpr (PRE) load_k();
+    // twiddles staged after this thread's loads are issued (the table's
+    // load latency overlaps them)
+    const float2 *twl = stage_twiddles<L>(lds, tw);
     fft_e<L, E, -1, false>(v, s, q, twl);
     if constexpr (!PRE) load_k();
 
