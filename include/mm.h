@@ -129,10 +129,11 @@ enum {
  * configuration and the workspace it needs.  Allocates no device memory;
  * the plan computes nothing until a workspace is bound.
  * Any 1 <= n <= 512 per axis: each axis is padded to the smallest transform
- * length L >= 2n of 2, 4, 6, 8, 12, 16, 24, ..., 512, 768, 1024 (radices 2,
- * 3, 4, 8); the zero-padded convolution needs L >= 2n - 1 (Sec. 2 zero
- * padding), so L = 2n exactly when n is 2^a or 3*2^a and the result is the
- * same convolution for any L (mm_plan_info reports Lx, Ly, Lz).
+ * length L >= 2n of 2, 4, 6, 8, 10, 12, 16, 20, 24, ..., 512, 640, 768, 1024
+ * (2^a, 3*2^a and 5*2^a; radices 2, 3, 4, 5, 8, 16); the zero-padded
+ * convolution needs L >= 2n - 1 (Sec. 2 zero padding), so L = 2n exactly
+ * when n is 2^a, 3*2^a or 5*2^a and the result is the same convolution for
+ * any L (mm_plan_info reports Lx, Ly, Lz).
  * Errors: MM_EINVAL (bad sizes), MM_ENODEV, MM_EHIP.                        */
 int mm_demag_setup(int nx, int ny, int nz, double dx, double dy, double dz, mm_plan *out);
 

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(256) void kb_copy(const BInst *__restrict__ B, cons
 template <int L> constexpr bool bm_alt() { return L >= 24 && L % 3 == 0; }
 template <int L, int KIND> constexpr bool bm_o1()
 {
-    return bm_alt<L>() || (KIND == 1 && L >= 512 && L % 3 != 0);
+    return bm_alt<L>() || (KIND == 1 && L >= 512 && (L & (L - 1)) == 0);
 }
 template <int L, int KIND> constexpr int bm_v()
 {
@@ -192,8 +192,8 @@ __device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
 }
 
 #define MMK_BM_LENGTHS(X)                                                                                \
-    X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) \
-        X(768) X(1024)
+    X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) \
+        X(160) X(192) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
 
 template <int SLOT>
 __global__ __launch_bounds__(bm_threads(SLOT)) void kb_merged(const BInst *__restrict__ B, const int4 *__restrict__ T,
@@ -492,8 +492,8 @@ static void launch_group_len(const BGroup &g, const BInst *table, int sel, hipSt
 }
 
 #define MMK_BATCH_LENGTHS(X)                                                                             \
-    X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) \
-        X(768) X(1024)
+    X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) \
+        X(160) X(192) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
 
 static int launch_group(const BGroup &g, const BInst *table, int sel, hipStream_t s, bool raise_only)
 {

@@ -132,8 +132,8 @@ template <int L> static KInfo kinfo()
 }
 
 #define MMK_ALL_LENGTHS(X)                                                                               \
-    X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) \
-        X(768) X(1024)
+    X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) \
+        X(160) X(192) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
 
 bool kinfo_for(int L, KInfo &out)
 {
@@ -156,7 +156,8 @@ bool length_supported(int L)
 // none (n > 512).
 int padded_length(int n)
 {
-    static const int lens[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+    static const int lens[] = {2,  4,   6,   8,   10,  12,  16,  20,  24,  32,  40,  48,  64,
+                               80, 96,  128, 160, 192, 256, 320, 384, 512, 640, 768, 1024};
     for (int L : lens)
         if (L >= 2 * n) return L;
     return 0;

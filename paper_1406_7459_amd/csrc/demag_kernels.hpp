@@ -17,7 +17,7 @@
 //   XINV   X1 -> H [3][nz][ny][nx] f32                            x: C2R, keep i < nx
 // (xp = x_pitch(Lx/2 + 1): rows of Lx/2 + 1 values padded to 128 bytes; the
 // padding is never read or written.)  An axis of n cells is padded to a
-// supported transform length L >= 2n (L = 2n when n is 2^a or 3 2^a): the
+// supported transform length L >= 2n (L = 2n when n is 2^a, 3 2^a or 5 2^a): the
 // zero-padded convolution only needs L >= 2n - 1, so the live count n is a
 // run-time argument of every body and L a template parameter.
 // For nz = 1 the padded z axis has length 2 with the second slot zero, so the

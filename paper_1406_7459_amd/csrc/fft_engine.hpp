@@ -63,6 +63,28 @@ __device__ __forceinline__ void bfly3(float2 *x)
     x[2] = csub(t2, t3);
 }
 
+// 5-point DFT: with t1 = x1 + x4, t2 = x2 + x3, t3 = x1 - x4, t4 = x2 - x3
+// and w = exp(DIR 2 pi i / 5), X1,4 = x0 + c1 t1 + c2 t2 +- DIR i (s1 t3 + s2 t4),
+// X2,3 = x0 + c2 t1 + c1 t2 +- DIR i (s2 t3 - s1 t4), where c1, s1 = cos, sin
+// of 2 pi/5 and c2, s2 = cos, sin of 4 pi/5 (pairing w^k with w^-k).
+template <int DIR>
+__device__ __forceinline__ void bfly5(float2 *x)
+{
+    const float c1 = 0.30901699437494742410f, s1 = 0.95105651629515357212f;
+    const float c2 = -0.80901699437494742410f, s2 = 0.58778525229247312917f;
+    const float2 t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]);
+    const float2 t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    const float2 a1 = make_float2(fmaf(c2, t2.x, fmaf(c1, t1.x, x[0].x)), fmaf(c2, t2.y, fmaf(c1, t1.y, x[0].y)));
+    const float2 a2 = make_float2(fmaf(c1, t2.x, fmaf(c2, t1.x, x[0].x)), fmaf(c1, t2.y, fmaf(c2, t1.y, x[0].y)));
+    const float2 b1 = mul_mi<DIR>(make_float2(fmaf(s2, t4.x, s1 * t3.x), fmaf(s2, t4.y, s1 * t3.y)));
+    const float2 b2 = mul_mi<DIR>(make_float2(fmaf(-s1, t4.x, s2 * t3.x), fmaf(-s1, t4.y, s2 * t3.y)));
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+}
+
 template <int DIR>
 __device__ __forceinline__ void bfly4(float2 *x)
 {
@@ -134,9 +156,10 @@ __device__ __forceinline__ void bfly(float2 *x)
     if constexpr (R == 2) bfly2<DIR>(x);
     else if constexpr (R == 3) bfly3<DIR>(x);
     else if constexpr (R == 4) bfly4<DIR>(x);
+    else if constexpr (R == 5) bfly5<DIR>(x);
     else if constexpr (R == 8) bfly8<DIR>(x);
     else if constexpr (R == 16) bfly16<DIR>(x);
-    else static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "radix");
+    else static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 8 || R == 16, "radix");
 }
 
 // ------------------------------------------------- factorisation tables ---
@@ -172,6 +195,14 @@ MMK_FACTORS(384, 0, 24, 3, 8, 4, 4)
 MMK_FACTORS(512, 0, 8, 8, 8, 8)
 MMK_FACTORS(768, 0, 24, 3, 8, 8, 4)
 MMK_FACTORS(1024, 0, 8, 8, 8, 4, 4)
+// 5 2^a: radix 5 then 4s (and a final 2), E = 20
+MMK_FACTORS(10, 0, 10, 5, 2)
+MMK_FACTORS(20, 0, 20, 5, 4)
+MMK_FACTORS(40, 0, 20, 5, 4, 2)
+MMK_FACTORS(80, 0, 20, 5, 4, 4)
+MMK_FACTORS(160, 0, 20, 5, 4, 4, 2)
+MMK_FACTORS(320, 0, 20, 5, 4, 4, 4)
+MMK_FACTORS(640, 0, 20, 5, 4, 4, 4, 2)
 // radix 16 first (2^a), radix 3 then 4s (3 2^a)
 MMK_FACTORS(16, 1, 16, 16)
 MMK_FACTORS(24, 1, 12, 3, 4, 2)

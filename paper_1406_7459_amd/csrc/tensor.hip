@@ -9,7 +9,7 @@
 //     kernel (tent weight, 4 Gauss-Legendre nodes per half-axis), where the
 //     closed form loses digits to cancellation.
 //  2. The transform of the padded, wrapped K over Lx x Ly x Lz (each L >= 2n;
-//     L = 2n when n is 2^a or 3 2^a): every component is even or odd in each
+//     L = 2n when n is 2^a, 3 2^a or 5 2^a): every component is even or odd in each
 //     axis (N(-r) = N(r) componentwise up to the sign of the odd axes), so it
 //     is real and equals separable cosine sums (even axes) and sine sums (odd
 //     axes) over the octant of offsets X < n:

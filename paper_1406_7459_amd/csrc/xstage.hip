@@ -17,8 +17,8 @@ __global__ __launch_bounds__(1024) void k_xstage(float2 *__restrict__ X1, const 
 }
 
 #define MMK_XS_LENGTHS(X)                                                                                \
-    X(2) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) \
-        X(768) X(1024)
+    X(2) X(4) X(6) X(8) X(10) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) \
+        X(160) X(192) X(256) X(320) X(384) X(512) X(640) X(768) X(1024)
 
 // threads and LDS of tile P (row pairs per workgroup) on x length L
 static bool xs_shape(int L, int P, int &threads, size_t &lds)

@@ -48,7 +48,7 @@ def _plan(mm, s, d, mode):
             _set_variant(mm, plan, "xfwd", 2)
             _set_variant(mm, plan, "xinv", 2)
         if s[2] > 1:
-            if _alt(inf["Ly"]) or (inf["Ly"] >= 512 and inf["Ly"] % 3):
+            if _alt(inf["Ly"]) or (inf["Ly"] >= 512 and (inf["Ly"] & (inf["Ly"] - 1)) == 0):
                 _set_variant(mm, plan, "yfwd", 2)
                 _set_variant(mm, plan, "yinv", 2)
             if _alt(inf["Lz"]):

@@ -14,14 +14,15 @@ from gpucommon import rel_l2, say, to_dev, to_host
 from paper_1406_7459_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-LENGTHS = [2, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+LENGTHS = [2, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512, 640, 768,
+           1024]
 
 
 def _padded(n):
     return min(L for L in LENGTHS if L >= 2 * n)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 9, 10, 13, 20, 50, 100, 125, 129, 257, 500, 512])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 9, 10, 13, 20, 40, 50, 80, 100, 125, 129, 160, 257, 300, 320, 500, 512])
 def test_padded_lengths(n):
     from paper_1406_7459_amd import mm
     plan = mm.Plan(n, 1, 1, 1e-9, 1e-9, 1e-9)
@@ -46,6 +47,10 @@ GRIDS = [
     ((1, 1, 7), (1e-9, 2e-9, 1.5e-9)),
     ((7, 9, 5), (1e-9, 1e-9, 1e-9)),
     ((33, 17, 2), (2e-9, 2e-9, 2e-9)),
+    # radix-5 lengths 10, 20, 40, 80 (n = 5 2^a pads to exactly 2n)
+    ((5, 10, 20), (2e-9, 2e-9, 2e-9)),
+    ((40, 20, 1), (3e-9, 3e-9, 2e-9)),
+    ((20, 5, 10), (1e-9, 2e-9, 1e-9)),
 ]
 
 
