@@ -10,14 +10,16 @@
 //
 // Two launch modes.  Merged: one launch per pass kind over every instance
 // and every transform length (512 threads a workgroup for the row and
-// column passes, 256 for the products), a task naming its instance, block
-// and length; each length runs in the radix order of at most 12 values per
-// thread (order 1 for 3 2^a lengths); the product passes take two launches
-// (the z products of at most 8 values per thread; the y products of nz = 1
-// instances and the 12-value z products), so the many short z products of
-// thin films are sized for neither the larger schedules' registers nor the
-// long y products' LDS; tasks are ordered longest transform first.  At
-// most 7 launches per stage.  Grouped: one launch
+// column passes, 128 or 256 for the products), a task naming its instance,
+// block and length; each length runs in the radix order of at most 12
+// values per thread (order 1 for 3 2^a lengths; 5 2^a lengths take 20); the
+// product passes take one launch per register class (the z products of at
+// most 8 values per thread; the y products of nz = 1 instances and the
+// 12-value z products; the products of 5 2^a lengths), so the many short z
+// products of thin films are sized for neither the larger schedules'
+// registers nor the long y products' LDS; tasks are ordered longest
+// transform first.  At most 8 launches per stage, 7 without 5 2^a lengths.
+// Grouped: one launch
 // per (pass kind, transform length), each group with its own tuned tile in
 // the default radix orders.
 #include <algorithm>
@@ -146,16 +148,22 @@ template <int T, int L, int KIND> constexpr int bm_lp2()
 }
 
 // Launch slots of the merged mode: the x and y passes one launch each; the
-// product passes two: A the z products of schedules with at most 8 values
-// per thread, B the y products (nz = 1) and the z products of 12 values per
-// thread.  Small-length z products (the bulk of the tasks of thin films)
+// product passes by register class of their schedules: A the z products of
+// at most 8 values per thread, B the y products (nz = 1) and the z products
+// of 12 (3 2^a lengths), C every product of a 5 2^a length (20 values per
+// thread).  Small-length z products (the bulk of the tasks of thin films)
 // then share neither the larger schedules' registers nor the long y
-// products' LDS.
-enum { MS_XFWD = 0, MS_YFWD = 1, MS_CONV_A = 2, MS_CONV_B = 3, MS_YINV = 4, MS_XINV = 5, MS_COUNT = 6 };
-template <int L> constexpr int bm_class() { return bm_alt<L>() ? 1 : 0; }  // 12 values per thread
+// products' LDS, and slot C is empty unless a grid pads to 5 2^a.
+enum {
+    MS_XFWD = 0, MS_YFWD = 1, MS_CONV_A = 2, MS_CONV_B = 3, MS_CONV_C = 4, MS_YINV = 5, MS_XINV = 6, MS_COUNT = 7
+};
+template <int L> constexpr bool bm_five() { return L % 5 == 0; }
+// product slot of a length: 0 (A), 1 (B), 2 (C); y products use B or C
+template <int L> constexpr int bm_class() { return bm_five<L>() ? 2 : (bm_e<L, 2>() > 8 ? 1 : 0); }
+__host__ __device__ constexpr bool bm_conv(int slot) { return slot == MS_CONV_A || slot == MS_CONV_B || slot == MS_CONV_C; }
 __host__ __device__ constexpr int bm_threads(int slot)
 {
-    return slot == MS_CONV_A ? 128 : (slot == MS_CONV_B ? 256 : 512);
+    return slot == MS_CONV_A ? 128 : (bm_conv(slot) ? 256 : 512);
 }
 constexpr int BM_YCONV = 1 << 16;  // task flag: product along y (nz = 1)
 constexpr int BM_EDGE = 1 << 17;   // task flag: edge workgroup (the last kx column, column_of)
@@ -166,7 +174,7 @@ constexpr int BM_LEN = (1 << 16) - 1;
 template <int SLOT, int L>
 __device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
 {
-    constexpr int KIND = (SLOT == MS_CONV_A || SLOT == MS_CONV_B) ? 2 : ((SLOT == MS_YFWD || SLOT == MS_YINV) ? 1 : 0);
+    constexpr int KIND = bm_conv(SLOT) ? 2 : ((SLOT == MS_YFWD || SLOT == MS_YINV) ? 1 : 0);
     constexpr int V = bm_v<L, KIND>(), lp2 = bm_lp2<bm_threads(SLOT), L, KIND>();
     static_assert((1 << lp2) * (L / bm_e<L, KIND>()) == bm_threads(SLOT), "P transforms fill the workgroup exactly");
     if constexpr (SLOT == MS_XFWD) xfwd_body<L, V>(bsel(I, sel), I.X1, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
@@ -176,11 +184,11 @@ __device__ __forceinline__ void bm_run(const BInst &I, const int4 &t, int sel)
         yinv_body<L, V>(I.X2, I.X1, I.Lx / 2 + 1, I.ny, lp2, I.tw1, t.y, t.z, (t.w & BM_EDGE) ? 3 * I.nz : 0);
     else if constexpr (SLOT == MS_XINV) xinv_body<L, V>(I.X1, I.Hout, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
     else {
-        // product slots: A the z products of the smaller schedules, B the
-        // y products (nz = 1) and the z products of 12 values per thread
+        // product slots (bm_class): y products in B or C, z products in
+        // the slot of their class
         constexpr int O = bm_o1<L, 2>() ? 1 : 0;
         const bool y = (t.w & BM_YCONV) != 0;
-        if constexpr (SLOT == MS_CONV_B) {
+        if constexpr ((SLOT == MS_CONV_B && bm_class<L>() < 2) || (SLOT == MS_CONV_C && bm_class<L>() == 2)) {
             if (y) conv_reg3_body<L, false, O>(I.X1, I.Kt, I.Lx / 2 + 1, I.Ly / 2, I.ny, lp2, I.tw1, t.y, 0);
         }
         if constexpr (bm_class<L>() == SLOT - MS_CONV_A) {
@@ -219,7 +227,7 @@ static int bm_P(int slot, int L)
 #define MMK_CASE(LEN) \
     case LEN:                                                                  \
         return slot == MS_CONV_A   ? (1 << bm_lp2<bm_threads(MS_CONV_A), LEN, 2>())                   \
-               : slot == MS_CONV_B ? (1 << bm_lp2<bm_threads(MS_CONV_B), LEN, 2>())                   \
+               : bm_conv(slot)     ? (1 << bm_lp2<bm_threads(MS_CONV_B), LEN, 2>())                   \
                : (slot == MS_YFWD || slot == MS_YINV) ? (1 << bm_lp2<bm_threads(MS_YFWD), LEN, 1>()) \
                                    : (1 << bm_lp2<bm_threads(MS_XFWD), LEN, 0>());
         MMK_BM_LENGTHS(MMK_CASE)
@@ -371,7 +379,7 @@ static void make_merged(BatchImpl &b, int slot)
     BGroup &g = b.mg[slot];
     g.tasks.clear();
     g.lds = 0;
-    const bool conv = slot == MS_CONV_A || slot == MS_CONV_B;
+    const bool conv = bm_conv(slot);
     auto pass_of = [&](const BInst &I) {
         switch (slot) {
         case MS_XFWD: return (int)MM_PASS_XFWD;
@@ -384,7 +392,11 @@ static void make_merged(BatchImpl &b, int slot)
     auto len_of = [&](const BInst &I) {
         const int L = pass_len_of(I, pass_of(I));
         // z products by register class; every y product in slot B
-        if (conv && L && (I.nz > 1 ? bm_class_of(L) : 1) != slot - MS_CONV_A) return 0;
+        if (conv && L) {
+            const int cls = bm_class_of(L);
+            const int want = I.nz > 1 ? cls : (cls == 2 ? 2 : 1);  // y products: B, or C for 5 2^a
+            if (want != slot - MS_CONV_A) return 0;
+        }
         return L;
     };
     std::vector<int> order;
@@ -522,6 +534,7 @@ static int merged_launch(const BatchImpl &b, int slot, const BInst *table, int s
     case MS_YFWD: hipLaunchKernelGGL(kb_merged<MS_YFWD>, grid, block, g.lds, s, table, g.d, sel); break;
     case MS_CONV_A: hipLaunchKernelGGL(kb_merged<MS_CONV_A>, grid, block, g.lds, s, table, g.d, sel); break;
     case MS_CONV_B: hipLaunchKernelGGL(kb_merged<MS_CONV_B>, grid, block, g.lds, s, table, g.d, sel); break;
+    case MS_CONV_C: hipLaunchKernelGGL(kb_merged<MS_CONV_C>, grid, block, g.lds, s, table, g.d, sel); break;
     case MS_YINV: hipLaunchKernelGGL(kb_merged<MS_YINV>, grid, block, g.lds, s, table, g.d, sel); break;
     case MS_XINV: hipLaunchKernelGGL(kb_merged<MS_XINV>, grid, block, g.lds, s, table, g.d, sel); break;
     default: break;
@@ -602,7 +615,8 @@ static void raise_merged_lds(BatchImpl &b)
 {
     const void *k[MS_COUNT] = {(const void *)kb_merged<MS_XFWD>,   (const void *)kb_merged<MS_YFWD>,
                                (const void *)kb_merged<MS_CONV_A>, (const void *)kb_merged<MS_CONV_B>,
-                               (const void *)kb_merged<MS_YINV>,   (const void *)kb_merged<MS_XINV>};
+                               (const void *)kb_merged<MS_CONV_C>, (const void *)kb_merged<MS_YINV>,
+                               (const void *)kb_merged<MS_XINV>};
     for (int slot = 0; slot < MS_COUNT; ++slot)
         if (b.mg[slot].lds > 65536)
             (void)hipFuncSetAttribute(k[slot], hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.mg[slot].lds);

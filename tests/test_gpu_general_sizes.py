@@ -141,8 +141,10 @@ def test_steps_match_oracle_any_size(grid, integrator):
 
 def test_batch_with_general_sizes_matches_oracle():
     from paper_1406_7459_amd import mm
-    shapes = [(10, 6, 2), (7, 5, 1), (16, 8, 4), (13, 3, 3)]
-    cells = [(2e-9, 2e-9, 2e-9), (4e-9, 4e-9, 3e-9), (2e-9, 3e-9, 2e-9), (1e-9, 1e-9, 1e-9)]
+    # (7, 5, 1): a y product of length 10; (6, 4, 5): a z product of length
+    # 10 (the merged launches' slot of 5 2^a products)
+    shapes = [(10, 6, 2), (7, 5, 1), (16, 8, 4), (13, 3, 3), (6, 4, 5)]
+    cells = [(2e-9, 2e-9, 2e-9), (4e-9, 4e-9, 3e-9), (2e-9, 3e-9, 2e-9), (1e-9, 1e-9, 1e-9), (2e-9, 2e-9, 3e-9)]
     b = mm.Batch(shapes, cells)
     Ms = [to_dev(8e5 * W.random_unit(*s, seed=70 + i)) for i, s in enumerate(shapes)]
     Hs = b.demag(Ms)
