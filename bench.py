@@ -26,6 +26,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
+ORDER_NAMES = {0: "default radix order", 1: "radix order 1 (radix 16 first; radix 3 then 4s)",
+               2: "radix order 2 (radix 4 only)"}
+
+
+def describe_tiles(tiles):
+    """The launch configuration of every pass in words, from the tile codes
+    (P + 256 * variant; the stage kernel's vector width; the fused stage
+    pass's P + 256 * log2 W, 0 = the unfused path)."""
+    out = {}
+    for name, t in tiles.items():
+        if not t:
+            continue
+        P, v = t & 255, t >> 8
+        if name == "stage":
+            out[name] = "%d cells per thread" % t
+        elif name == "xstage":
+            out[name] = "fused x inverse + stage + x forward, %d row pairs per workgroup, %d cells per stage task" % (
+                P, 1 << v) if t else "unfused (x inverse, stage kernel, x forward)"
+        elif name in ("zconv", "yconv"):
+            kind = {0: "three components in registers, " + ORDER_NAMES[0],
+                    1: "component split, default values per thread", 2: "component split, twice the values per thread",
+                    3: "three components in registers, " + ORDER_NAMES[1],
+                    4: "three components in registers, " + ORDER_NAMES[2]}.get(v, "variant %d" % v)
+            out[name] = "%d columns per workgroup, %s" % (P, kind)
+        elif name != "reduce":
+            kind = {0: ORDER_NAMES[0], 1: ORDER_NAMES[0] + ", twice the values per thread",
+                    2: ORDER_NAMES[1], 3: ORDER_NAMES[2]}.get(v, "variant %d" % v)
+            unit = "row pairs" if name in ("xfwd", "xinv") else "columns"
+            out[name] = "%d %s per workgroup, %s" % (P, unit, kind)
+    return out
+
+
 def pass_bytes(nx, ny, nz):
     """Algorithmic bytes per launch of each kernel kind (compulsory reads and
     writes of the pruned five-pass schedule; neighbour re-reads not counted)."""
@@ -947,6 +979,7 @@ def main():
         "state_after": {"E_tot_J": st["E_tot"], "m_avg": st["m_avg"], "nonfinite": st["nonfinite"]},
         "kernels": kern,
         "tiles": tiles,
+        "tile_schedules": describe_tiles(tiles),
         "setup_s": setup_s,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
