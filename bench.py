@@ -575,14 +575,17 @@ def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
     err = float((Ms_ - Me).norm() / Me.norm())
     x = torch.randn((3, nz, ny, nx), device="cuda")
     y = torch.empty_like(x)
-    for _ in range(3):
+    # device time of one network evaluation (input normalisation included):
+    # events around 200 back-to-back evaluations on the current stream
+    for _ in range(30):
         sur.forward(x, y, normalize=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(20):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(200):
         sur.forward(x, y, normalize=True)
+    e1.record()
     torch.cuda.synchronize()
-    inf = (time.perf_counter() - t1) / 20
+    inf = e0.elapsed_time(e1) / 200 * 1e-3
     sur.close()
     plan.close()
     return {"workload": "film256 (256x256x4, 4 nm, alpha 0.1, in-plane |mu0 H| <= 50 mT); pairs from the solver",
@@ -620,12 +623,29 @@ def surrogate_profile(torch, mm):
     sur.close()
 
 
+def _demangle_mmk(name):
+    """mmk::name<int/bool template arguments> from an Itanium-mangled kernel
+    name of the library's namespace that the trace left mangled (the bf16
+    parameter type stops some demanglers); other names pass unchanged."""
+    import re
+    m = re.match(r"_ZN3mmk(\d+)", name)
+    if not m:
+        return name
+    n = int(m.group(1))
+    base, rest = name[m.end():m.end() + n], name[m.end() + n:]
+    args = []
+    if rest.startswith("I"):
+        for kind, val in re.findall(r"L([ib])(\d+)E", rest[1:rest.find("EE") + 1]):
+            args.append(val if kind == "i" else ("true" if val == "1" else "false"))
+    return "mmk::" + base + ("<%s>" % ", ".join(args) if args else "")
+
+
 def summarize_surrogate(db):
     """Text of profiles/surrogate_film256.txt from a rocprofv3 --kernel-trace
     database of bench.py --surrogate-profile: per kernel, the dispatch count
     and durations; for the convolutions the rate of the 32 x 32-channel
     3x3x3 product they compute (2*27*32*32 flop per cell, the last layer's 16
-    computed output rows: half of that)."""
+    computed output rows: half of that; the packed first layer 2*28*8*32)."""
     import re
     import sqlite3
     import statistics
@@ -633,21 +653,25 @@ def summarize_surrogate(db):
     con = sqlite3.connect(db)
     groups = {}
     for name, dur in con.execute("select name, duration from kernels"):
-        k = re.sub(r"\(.*", "", name).replace("void ", "")
+        k = re.sub(r"\(.*", "", _demangle_mmk(name)).replace("void ", "")
         groups.setdefault(k, []).append(dur / 1e3)
     tot = sum(sum(v) for v in groups.values())
     out = ["# kernel trace of the learned form, film256 (256x256x4 cells), rocprofv3 --kernel-trace",
            "# command (from /tmp on the GPU, REPO = repository root, OUT = an output folder):", *SURROGATE_PROFILE_CMD,
            "# 20 network evaluations, then 10 training steps; durations in microseconds",
            "# k_conv<E, lo, hi>: E = 3 inference hidden layer, 1 last layer, 0 training forward, 2 input",
-           "# gradient (GELU derivative fused); TFLOP/s of the computed 32x32-channel product (BF16 peak 2500)",
+           "# gradient (GELU derivative fused); TFLOP/s of the computed 32x32-channel product (BF16 peak 2500);",
+           "# k_conv_in<E>: the first layer, 4 taps x 8 channels per K step (28 x 8 x 32 computed per cell)",
            "%-44s %6s %9s %9s %7s %8s" % ("kernel", "calls", "median", "mean", "share", "TFLOP/s")]
     for k in sorted(groups, key=lambda k: -sum(groups[k])):
         v = groups[k]
         med = statistics.median(v)
         rate = ""
         m = re.match(r"mmk::k_conv<(\d)", k)
-        if m:
+        if k.startswith("mmk::k_conv_in<"):
+            # packed first layer: 7 K steps of 4 taps x 8 channels, 32 outputs
+            rate = "%.0f" % (2 * 28 * 8 * 32 * N / (med * 1e-6) / 1e12)
+        elif m:
             fl = 2 * 27 * 32 * 32 * N * (0.5 if m.group(1) == "1" else 1.0)
             rate = "%.0f" % (fl / (med * 1e-6) / 1e12)
         elif k.startswith("mmk::k_conv_dw"):

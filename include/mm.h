@@ -356,14 +356,16 @@ typedef struct {
     double last_residual, max_residual, sum_residual;  /* |H_s - H_d| / |H_d| */
 } mm_sur_stats;
 
-/* Describe a network for an nx x ny x nz grid of at most 2^25 cells
- * (MM_EINVAL otherwise, before any device work).  Allocates no device
+/* Describe a network for an nx x ny x nz grid of at most 2^25 cells whose
+ * zero-padded x-y plane, (ny + 1) * roundup(nx + 1, 8) positions, is below
+ * 2^27 (MM_EINVAL otherwise, before any device work).  Allocates no device
  * memory: bind a workspace before any other call.                          */
 int mm_sur_create(int nx, int ny, int nz, mm_sur *out);
 
 /* Device bytes of the network's weights, Adam state, activations and
- * training buffers (BF16 activations [N][32] per layer, padded
- * channel-major copies for the weight gradient, FP32 scratch fields).      */
+ * training buffers (the zero-padded 8-channel BF16 network input, BF16
+ * activations [N][32] of the later layers, padded channel-major copies for
+ * the weight gradient, FP32 scratch fields).                               */
 int mm_sur_workspace_bytes(mm_sur sur, size_t *bytes);
 
 /* Bind a caller-allocated device workspace (>= the size above, 256-byte

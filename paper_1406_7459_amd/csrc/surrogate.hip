@@ -41,14 +41,17 @@ static const int CH[NLAYER + 1] = {3, 32, 32, 32, 32, 32, 3};
 // GELU, tanh form: 0.5 x (1 + tanh(u)) with u = sqrt(2/pi) (x + 0.044715 x^3),
 // evaluated as x * s with s = 1 / (1 + e^(-2u)) (the same function; one
 // exponential and one reciprocal instead of a tanh), and its derivative
-// s + 2 x s (1 - s) u'.
+// s + 2 x s (1 - s) u'.  e^(-2u) = 2^(x (k1 + k3 x^2)) with the constants
+// folded (k1 = -2 sqrt(2/pi) log2(e), k3 = 0.044715 k1): one multiply, one
+// fma and one multiply before the base-2 exponential.
 __device__ __forceinline__ float gelu_s(float x, float &du)
 {
-    const float c = 0.7978845608028654f;  // sqrt(2/pi)
+    constexpr float c = 0.7978845608028654f;  // sqrt(2/pi)
+    constexpr float k1 = (float)(-2.0 * 0.7978845608028654 * 1.4426950408889634);
+    constexpr float k3 = (float)(0.044715 * -2.0 * 0.7978845608028654 * 1.4426950408889634);
     const float x2 = x * x;
     du = c * (1.f + 3.f * 0.044715f * x2);
-    const float u = c * x * (1.f + 0.044715f * x2);
-    return __builtin_amdgcn_rcpf(1.f + __expf(-2.f * u));
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(x * __builtin_fmaf(k3, x2, k1)));
 }
 __device__ __forceinline__ float gelu_f(float x)
 {
@@ -119,6 +122,44 @@ __device__ __forceinline__ long long pad_at(const PadGeom &g, int x, int y, int 
     return g.f + (long long)(z + 1) * g.pl + (long long)y * g.xp + x;
 }
 
+// Epilogue of a hidden layer at one cell c = (x, y, z): lane group kq holds
+// the accumulators of output channels 4 kq + r (a0) and 16 + 4 kq + r (a1),
+// b0/b1 their biases.  Xn = bf16(gelu(acc + b)); EPI 0 (training) also
+// writes the bf16 pre-activations Zh and the channel-major copy Xt of Xn.
+template <int EPI>
+__device__ __forceinline__ void hidden_out(const f4 &a0, const f4 &a1, const f4 &b0, const f4 &b1, long long c,
+                                           int kq, __bf16 *__restrict__ Zh, __bf16 *__restrict__ Xn,
+                                           __bf16 *__restrict__ Xt, const PadGeom &pg, int x, int y, int z)
+{
+    f4 z0v, z1v;
+    bf4 g0, g1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        z0v[r] = a0[r] + b0[r];
+        z1v[r] = a1[r] + b1[r];
+        g0[r] = (__bf16)gelu_f(z0v[r]);
+        g1[r] = (__bf16)gelu_f(z1v[r]);
+    }
+    if constexpr (EPI == 0) {
+        bf4 h0, h1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            h0[r] = (__bf16)z0v[r];
+            h1[r] = (__bf16)z1v[r];
+        }
+        *reinterpret_cast<bf4 *>(Zh + c * SC + 4 * kq) = h0;
+        *reinterpret_cast<bf4 *>(Zh + c * SC + 16 + 4 * kq) = h1;
+        const long long pc = pad_at(pg, x, y, z);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Xt[(long long)(4 * kq + r) * pg.G + pc] = g0[r];
+            Xt[(long long)(16 + 4 * kq + r) * pg.G + pc] = g1[r];
+        }
+    }
+    *reinterpret_cast<bf4 *>(Xn + c * SC + 4 * kq) = g0;
+    *reinterpret_cast<bf4 *>(Xn + c * SC + 16 + 4 * kq) = g1;
+}
+
 // One launch covers the z blocks zb0 .. zb0+nzbr-1 of one kind: ZLO (the
 // block starts at z = 0) and ZHI (it reaches the top level).
 template <int EPI, bool ZLO, bool ZHI>
@@ -163,9 +204,9 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
     const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<__bf16 *>(X), 0, (int)((long long)nx * ny * nz * SC * 2), 0x00020000);
     const unsigned OUT_OF_RANGE = 0x80000000u;
-    // inference forms: the lane's biases are loaded once, ahead of the tasks
+    // the lane's biases are loaded once, ahead of the tasks
     f4 bia0 = {0.f, 0.f, 0.f, 0.f}, bia1 = {0.f, 0.f, 0.f, 0.f};
-    if constexpr (EPI == 3) {
+    if constexpr (EPI == 0 || EPI == 3) {
         bia0 = *reinterpret_cast<const f4 *>(bias + 4 * kq);
         bia1 = *reinterpret_cast<const f4 *>(bias + 16 + 4 * kq);
     } else if constexpr (EPI == 1) {
@@ -256,33 +297,7 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
             if (z0 + u >= nz) break;
             const long long c = ((long long)(z0 + u) * ny + y) * nx + x;
             if constexpr (EPI == 0 || EPI == 3) {
-                f4 z0v, z1v;
-                bf4 g0, g1;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    z0v[r] = acc0[u][r] + (EPI == 3 ? bia0[r] : bias[4 * kq + r]);
-                    z1v[r] = acc1[u][r] + (EPI == 3 ? bia1[r] : bias[16 + 4 * kq + r]);
-                    g0[r] = (__bf16)gelu_f(z0v[r]);
-                    g1[r] = (__bf16)gelu_f(z1v[r]);
-                }
-                if constexpr (EPI == 0) {  // training: pre-activations and the channel-major copy
-                    bf4 h0, h1;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        h0[r] = (__bf16)z0v[r];
-                        h1[r] = (__bf16)z1v[r];
-                    }
-                    *reinterpret_cast<bf4 *>(Zh + c * SC + 4 * kq) = h0;
-                    *reinterpret_cast<bf4 *>(Zh + c * SC + 16 + 4 * kq) = h1;
-                    const long long pc = pad_at(pg, x, y, z0 + u);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        Xt[(long long)(4 * kq + r) * pg.G + pc] = g0[r];
-                        Xt[(long long)(16 + 4 * kq + r) * pg.G + pc] = g1[r];
-                    }
-                }
-                *reinterpret_cast<bf4 *>(Xn + c * SC + 4 * kq) = g0;
-                *reinterpret_cast<bf4 *>(Xn + c * SC + 16 + 4 * kq) = g1;
+                hidden_out<EPI>(acc0[u], acc1[u], bia0, bia1, c, kq, Zh, Xn, Xt, pg, x, y, z0 + u);
             } else if constexpr (EPI == 1) {
                 if (kq == 0) {
                     const long long N = (long long)nx * ny * nz;
@@ -316,11 +331,99 @@ __global__ __launch_bounds__(64 * CONV_WAVES) __attribute__((amdgpu_waves_per_eu
     }
 }
 
+// First layer.  Its input has 3 live channels, so a K step of 32 channels
+// per tap would multiply 29 zeros; here K packs four taps of 8 channels
+// (channels 0..7 of the input, 3..7 zero): lane group kq takes tap 4 s + kq
+// in step s, so the 27 taps need 7 MFMA steps per output half instead of 27
+// (tap 27 carries zero weights).  The input is stored zero-padded (PadGeom
+// positions, 8 channels = 16 bytes each), so every neighbour of a cell,
+// inside the grid or not, is one unmasked load, and a lane's 7 tap offsets
+// are fixed for the whole kernel: a load is a scalar level base plus a
+// constant per-lane offset.  A wave keeps its 14 weight fragments in
+// registers and walks (16-cell x run, y, TZ-level block) tasks, level by
+// level, with the next level's 7 loads in flight during the current level's
+// 14 MFMAs.  Levels past the top of the grid (a ragged last block) reload the
+// top level and store nothing; x positions past the row's end read padding or
+// the next row and store nothing.
+constexpr int IN_CH = 8;                 // channels per position of the padded input
+constexpr int IN_KS = (NT + 3) / 4;      // K steps of the packed first layer
+constexpr int IN_WAVES = 4;
+
+template <int EPI>
+__global__ __launch_bounds__(64 * IN_WAVES) void k_conv_in(const __bf16 *__restrict__ Xin,
+                                                          const __bf16 *__restrict__ W,
+                                                          const float *__restrict__ bias, __bf16 *__restrict__ Zh,
+                                                          __bf16 *__restrict__ Xn, __bf16 *__restrict__ Xt, PadGeom pg,
+                                                          int nx, int ny, int nz)
+{
+    static_assert(EPI == 0 || EPI == 3, "the first layer is a hidden layer");
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int col = lane & 15, kq = lane >> 4;
+    const u4 zero = {0u, 0u, 0u, 0u};
+    // weight fragments W[co][t][0..7] of both output halves, and the byte
+    // offset of the tap's neighbour from the lane's cell, biased by
+    // pl + xp + 1 positions so that it is never negative
+    u4 wlo[IN_KS], whi[IN_KS];
+    unsigned vo[IN_KS];
+    const int bias_pos = pg.pl + pg.xp + 1;
+#pragma unroll
+    for (int st = 0; st < IN_KS; ++st) {
+        const int t = 4 * st + kq, tc = t < NT ? t : NT - 1;
+        const u4 a = *reinterpret_cast<const u4 *>(W + (long long)(col * NT + tc) * SC);
+        const u4 b = *reinterpret_cast<const u4 *>(W + (long long)((16 + col) * NT + tc) * SC);
+        wlo[st] = t < NT ? a : zero;
+        whi[st] = t < NT ? b : zero;
+        const int dz = tc / 9 - 1, dy = (tc % 9) / 3 - 1, dx = tc % 3 - 1;
+        const int d = t < NT ? dz * pg.pl + dy * pg.xp + dx : 0;
+        vo[st] = (unsigned)(col + d + bias_pos) * (unsigned)(IN_CH * 2);
+    }
+    const f4 bia0 = *reinterpret_cast<const f4 *>(bias + 4 * kq);
+    const f4 bia1 = *reinterpret_cast<const f4 *>(bias + 16 + 4 * kq);
+    // task indices fit 32 bits (at most one task per cell, 2^25 cells)
+    const unsigned nxt = (unsigned)(nx + 15) >> 4, nzb = (unsigned)(nz + TZ - 1) / TZ;
+    const unsigned ntask = nxt * (unsigned)ny * nzb;
+    const char *base = reinterpret_cast<const char *>(Xin);
+    for (unsigned task = xcd_block(blockIdx.x, gridDim.x) * IN_WAVES + wv; task < ntask;
+         task += gridDim.x * IN_WAVES) {
+        const int xt = (int)(task % nxt);
+        const unsigned rest = task / nxt;
+        const int y = (int)(rest % (unsigned)ny);
+        const int z0 = (int)(rest / (unsigned)ny) * TZ;
+        const int x = xt * 16 + col;
+        // the 7 fragments of level z0 + u (clamped to the grid), from the
+        // run's first position less the bias
+        auto fetch = [&](int u, u4 *b) {
+            const int zu = z0 + u < nz ? z0 + u : nz - 1;
+            const char *lv = base + (pad_at(pg, xt * 16, y, zu) - bias_pos) * (IN_CH * 2);
+#pragma unroll
+            for (int st = 0; st < IN_KS; ++st) b[st] = *reinterpret_cast<const u4 *>(lv + vo[st]);
+        };
+        u4 ring[2][IN_KS];
+        fetch(0, ring[0]);
+#pragma unroll
+        for (int u = 0; u < TZ; ++u) {
+            if (u + 1 < TZ) fetch(u + 1, ring[(u + 1) & 1]);
+            f4 a0 = {0.f, 0.f, 0.f, 0.f}, a1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < IN_KS; ++st) {
+                const bf8 bv = __builtin_bit_cast(bf8, ring[u & 1][st]);
+                a0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, wlo[st]), bv, a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, whi[st]), bv, a1, 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (x < nx && z0 + u < nz)
+                hidden_out<EPI>(a0, a1, bia0, bia1, ((long long)(z0 + u) * ny + y) * nx + x, kq, Zh, Xn, Xt, pg, x,
+                                y, z0 + u);
+        }
+    }
+}
+
 // sigma = sqrt(sum / count) from the nb FP64 partials of the sum of squares
 // (1 if the sum is 0 or normalisation is off), in a fixed order (a strided
 // sum per thread, then a tree; 256 threads), then dm [3][N] FP32 (SoA) *
-// (1/sigma) -> channels 0..7 of bf16 channel-last [N][32] (channels 3..7
-// zero; channels 8..31 are zeroed once at creation and never written).
+// (1/sigma) -> the first layer's zero-padded input, 8 bf16 channels at each
+// PadGeom position (channels 3..7 zero; the positions outside the grid are
+// zeroed once at creation and never written).
 // Every workgroup forms sigma itself (4 KB of partials from L2, no extra
 // launch); workgroup 0 stores sig = {sigma, 1/sigma} for the later kernels
 // (the step driver never synchronises for it).
@@ -357,9 +460,9 @@ __global__ __launch_bounds__(256) void k_to_cl_dev(const float *__restrict__ dm,
         v[0] = (__bf16)(dm[c] * inv);
         v[1] = (__bf16)(dm[N + c] * inv);
         v[2] = (__bf16)(dm[2 * N + c] * inv);
-        *reinterpret_cast<bf8 *>(X + c * SC) = v;
+        const long long pc = pad_at(pg, (int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long long)nx * ny)));
+        *reinterpret_cast<bf8 *>(X + pc * IN_CH) = v;
         if (Xt) {
-            const long long pc = pad_at(pg, (int)(c % nx), (int)((c / nx) % ny), (int)(c / ((long long)nx * ny)));
 #pragma unroll
             for (int r = 0; r < 3; ++r) Xt[r * pg.G + pc] = v[r];
         }
@@ -694,7 +797,8 @@ struct Sur {
     // FP32 masters and Adam moments, padded layout [co][t][ci] per layer, then 32 biases
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     __bf16 *wb = nullptr, *wt = nullptr;  // bf16 forward / mirrored-transposed copies
-    __bf16 *X[NLAYER] = {};               // layer inputs, [N][32]
+    __bf16 *Xin = nullptr;                // network input, zero-padded: [G][8] (PadGeom positions)
+    __bf16 *X[NLAYER] = {};               // inputs of layers 1.., [N][32] (X[0] unused)
     __bf16 *Zh[NLAYER - 1] = {};          // hidden pre-activations (training), [N][32]
     float *Zout = nullptr;                // last layer's output before the scale, [N][4] (channels 0-2)
     __bf16 *dZb[2] = {};                  // [N][32], this layer's dZ and the one below
@@ -731,8 +835,9 @@ static size_t sur_layout(Sur &s, char *base)
     take(&s.g, P * 4);
     take(&s.wb, (size_t)NLAYER * WSZ * 2);
     take(&s.wt, (size_t)NLAYER * WSZ * 2);
+    take(&s.Xin, (size_t)s.pg.G * IN_CH * 2);
     for (int l = 0; l < NLAYER; ++l) {
-        take(&s.X[l], (size_t)s.N * SC * 2);
+        if (l > 0) take(&s.X[l], (size_t)s.N * SC * 2);
         if (l < NLAYER - 1) take(&s.Zh[l], (size_t)s.N * SC * 2);
         take(&s.Xt[l], (size_t)s.pg.G * SC * 2);
     }
@@ -792,12 +897,26 @@ static void launch_conv(const Sur &s, hipStream_t st, const __bf16 *X, const __b
     go(k_conv<EPI, false, true>, nzb - 1, 1);
 }
 
-// forward of the whole stack on X[0] (already filled); last layer -> dh.
+// the packed first layer (k_conv_in) over the whole grid
+template <int EPI>
+static void launch_conv_in(const Sur &s, hipStream_t st, __bf16 *Zh, __bf16 *Xt)
+{
+    const long long tasks = (long long)((s.nx + 15) / 16) * s.ny * ((s.nz + TZ - 1) / TZ);
+    const unsigned gb = (unsigned)std::min<long long>((tasks + IN_WAVES - 1) / IN_WAVES, 8192);
+    hipLaunchKernelGGL(k_conv_in<EPI>, dim3(gb), dim3(64 * IN_WAVES), 0, st, s.Xin, s.wb, s.w + WSZ, Zh,
+                       s.X[1], Xt, s.pg, s.nx, s.ny, s.nz);
+}
+
+// forward of the whole stack on the padded input Xin (already filled); last layer -> dh.
 // keep_z: store the pre-activations Z of the hidden layers (needed by the
 // backward pass; inference skips them).
 static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool keep_z)
 {
-    for (int l = 0; l < NLAYER; ++l) {
+    if (keep_z)
+        launch_conv_in<0>(s, st, s.Zh[0], s.Xt[1]);
+    else
+        launch_conv_in<3>(s, st, nullptr, nullptr);
+    for (int l = 1; l < NLAYER; ++l) {
         const __bf16 *W = s.wb + (long long)l * WSZ;
         const float *b = s.w + l * layer_stride() + WSZ;
         if (l < NLAYER - 1 && keep_z)
@@ -810,7 +929,7 @@ static void sur_forward(Sur &s, float *dh, hipStream_t st, bool dev_scale, bool 
     }
 }
 
-// sigma of dm (normalize) into s.sig, and X[0] = bf16(dm / sigma)
+// sigma of dm (normalize) into s.sig, and Xin = bf16(dm / sigma)
 // (train: also the channel-major copy Xt[0] for the weight gradient)
 // (have_partials: the sum-of-squares partials of dm are already in s.dpart)
 static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st, bool train = false,
@@ -818,7 +937,7 @@ static void sur_input(Sur &s, const float *dm, int normalize, hipStream_t st, bo
 {
     if (!have_partials)
         hipLaunchKernelGGL(k_sumsq_diff, dim3(RED_B), dim3(256), 0, st, dm, nullptr, 1.f, nullptr, s.dpart, 3 * s.N);
-    hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.X[0], s.dpart, RED_B,
+    hipLaunchKernelGGL(k_to_cl_dev, dim3(grid_for(s.N)), dim3(256), 0, st, dm, s.Xin, s.dpart, RED_B,
                        (double)(3 * s.N), normalize, s.sig, s.N, train ? s.Xt[0] : nullptr, s.pg, s.nx, s.ny);
 }
 
@@ -944,6 +1063,12 @@ int mm_sur_create(int nx, int ny, int nz, mm_sur *out)
     s->nz = nz;
     s->N = (long long)nx * ny * nz;
     s->pg = pad_geom(nx, ny, nz);
+    // the first layer reaches its neighbours with 32-bit byte offsets spanning
+    // two padded planes
+    if ((2LL * s->pg.pl + 2LL * s->pg.xp + 32) * IN_CH * 2 >= (1LL << 32)) {
+        delete s;
+        return fail(MM_EINVAL, "surrogate grid: a padded x-y plane of more than 2^27 positions");
+    }
     s->bytes = sur_layout(*s, nullptr);
     *out = new mm_sur_s{s};
     return MM_OK;
@@ -967,14 +1092,13 @@ int mm_sur_bind_workspace(mm_sur sur, void *ws, size_t bytes)
     s.ws = nullptr;
     sur_layout(s, (char *)ws);
     const size_t P = (size_t)NLAYER * layer_stride();
-    // weights and Adam state zero; channels 8..31 of the network input stay
-    // zero (the input conversion writes channels 0..7 only); the padded
-    // copies are zero outside the grid's cells and stay so
+    // weights and Adam state zero; the padded input and the padded copies
+    // are zero outside the grid's cells and stay so
     MMK_HIP(hipMemset(s.w, 0, P * 4));
     MMK_HIP(hipMemset(s.m, 0, P * 4));
     MMK_HIP(hipMemset(s.v, 0, P * 4));
     MMK_HIP(hipMemset(s.g, 0, P * 4));
-    MMK_HIP(hipMemset(s.X[0], 0, (size_t)s.N * SC * 2));
+    MMK_HIP(hipMemset(s.Xin, 0, (size_t)s.pg.G * IN_CH * 2));
     for (int l = 0; l < NLAYER; ++l) MMK_HIP(hipMemset(s.Xt[l], 0, (size_t)s.pg.G * SC * 2));
     MMK_HIP(hipMemset(s.dZt, 0, (size_t)s.pg.G * SC * 2));
     MMK_HIP(hipMemset(s.dZtL, 0, (size_t)s.pg.G * SC * 2));

@@ -58,7 +58,9 @@ def test_setup_rejects_bad_grid_before_device_work(L, args):
     assert L.mm_last_error(buf, 256) > 0 and buf.value
 
 
-@pytest.mark.parametrize("grid", [(0, 4, 4), (4, 0, 4), (4, 4, -1), (512, 256, 257)])
+# (1, 2^24, 1): 2^24 cells, but a padded x-y plane of (2^24 + 1) * 8 positions,
+# beyond the first layer's 32-bit neighbour offsets
+@pytest.mark.parametrize("grid", [(0, 4, 4), (4, 0, 4), (4, 4, -1), (512, 256, 257), (1, 1 << 24, 1)])
 def test_surrogate_rejects_bad_grid_before_device_work(L, grid):
     from paper_1406_7459_amd import mm
     h = C.c_void_p(123)

@@ -75,3 +75,12 @@ def test_schedule_descriptions():
     assert d["stage"] == "4 cells per thread"
     assert d["xstage"].startswith("fused") and "2 row pairs" in d["xstage"]
     assert bench.describe_tiles({"xstage": 0}) == {}
+
+
+def test_mangled_kernel_names_are_shortened():
+    # the trace can leave a kernel with a bf16 parameter mangled
+    assert bench._demangle_mmk("_ZN3mmk9k_conv_inILi3EEEvPKDF16bS2_PKfPDF16bS5_S5_NS_7PadGeomEiii") == "mmk::k_conv_in<3>"
+    assert bench._demangle_mmk(
+        "_ZN3mmk6k_convILi0ELb1ELb0EEEvPKDF16bS2_PKfPfPDF16bS6_S5_fS4_iiiiiS6_NS_7PadGeomE") == "mmk::k_conv<0, true, false>"
+    assert bench._demangle_mmk("_ZN3mmk5k_mseEPKfS1_fPDF16bS2_NS_7PadGeomEPd") == "mmk::k_mse"
+    assert bench._demangle_mmk("void mmk::k_adam(float*)") == "void mmk::k_adam(float*)"

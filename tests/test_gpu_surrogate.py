@@ -44,7 +44,8 @@ def ref_params(seed):
     return out
 
 
-@pytest.mark.parametrize("grid", [(16, 12, 4), (10, 6, 3), (33, 5, 2), (20, 7, 9), (48, 3, 6)])
+@pytest.mark.parametrize("grid", [(16, 12, 4), (10, 6, 3), (33, 5, 2), (20, 7, 9), (48, 3, 6), (7, 5, 1), (1, 9, 5),
+                                  (17, 2, 4)])
 def test_forward_matches_reference(grid):
     from paper_1406_7459_amd import mm
     nx, ny, nz = grid
@@ -57,7 +58,10 @@ def test_forward_matches_reference(grid):
     ref, _ = S.forward(ps, dm, bf16_between=True)
     err = rel_l2(out, ref.numpy())
     say("forward", grid, "rel L2", err)
-    assert err < 1e-2
+    # the reference rounds to bf16 where the kernels store (layer inputs);
+    # FP32 accumulation in another order and the GELU's FP32 exponential flip
+    # a few of those roundings by one bf16 ulp: observed <= 2e-4 over these grids
+    assert err < 1e-3
     sur.close()
 
 
