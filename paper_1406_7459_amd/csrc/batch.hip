@@ -93,16 +93,19 @@ __global__ __launch_bounds__(1024) void kb_xinv(const BInst *__restrict__ B, con
     const BInst &I = B[t.x];
     xinv_body<L, V>(I.X1, I.Hout, I.nz * I.ny, I.nx, lp2, I.tw0, t.y);
 }
+// state of buffer ssel -> buffer osel, with the step's base state Mn in
+// buffer msel (M for the RK4 stages; the second step of an Euler pair starts
+// from Sa)
 template <int STAGE>
 __global__ __launch_bounds__(256) void kb_stage(const BInst *__restrict__ B, const int2 *__restrict__ T, int ssel,
-                                                int osel)
+                                                int osel, int msel)
 {
     const int2 t = T[blockIdx.x];
     const BInst &I = B[t.x];
-    stage_body<STAGE>(bsel(I, ssel), I.H, I.M, I.kacc, bsel(I, osel), I.nx, I.ny, I.nz, I.c,
+    stage_body<STAGE>(bsel(I, ssel), I.H, bsel(I, msel), I.kacc, bsel(I, osel), I.nx, I.ny, I.nz, I.c,
                       (unsigned)t.y * 256u + threadIdx.x);
 }
-// Euler: the new state, written to Sa, becomes M
+// single Euler step: the new state, written to Sa, becomes M
 __global__ __launch_bounds__(256) void kb_copy(const BInst *__restrict__ B, const int2 *__restrict__ T)
 {
     const int2 t = T[blockIdx.x];
@@ -563,18 +566,26 @@ static int batch_demag_enqueue(BatchImpl &b, const BInst *table, int sel, hipStr
 }
 
 template <int STAGE>
-static int batch_stage(BatchImpl &b, int ssel, int osel, hipStream_t s)
+static int batch_stage(BatchImpl &b, int ssel, int osel, hipStream_t s, int msel = 0)
 {
     hipLaunchKernelGGL(kb_stage<STAGE>, dim3((unsigned)b.stage_tasks.size()), dim3(256), 0, s, b.d_inst, b.d_stage,
-                       ssel, osel);
+                       ssel, osel, msel);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(MM_EHIP, std::string("batch stage: ") + hipGetErrorString(e));
     return MM_OK;
 }
 
-static int batch_step_enqueue(BatchImpl &b, int integrator, hipStream_t s)
+// One step, or (euler_pair) two Euler steps M -> Sa -> M, which alternate
+// between the two buffers and copy nothing.
+static int batch_step_enqueue(BatchImpl &b, int integrator, hipStream_t s, bool euler_pair = false)
 {
     int rc;
+    if (integrator == MM_EULER && euler_pair) {
+        if ((rc = batch_demag_enqueue(b, b.d_inst, 0, s)) != MM_OK) return rc;
+        if ((rc = batch_stage<0>(b, 0, 1, s)) != MM_OK) return rc;
+        if ((rc = batch_demag_enqueue(b, b.d_inst, 1, s)) != MM_OK) return rc;
+        return batch_stage<0>(b, 1, 0, s, 1);
+    }
     if (integrator == MM_EULER) {
         if ((rc = batch_demag_enqueue(b, b.d_inst, 0, s)) != MM_OK) return rc;
         if ((rc = batch_stage<0>(b, 0, 1, s)) != MM_OK) return rc;
@@ -832,12 +843,17 @@ int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M, 
         b.bound_params = pkey;
         drop_graph(b);
     }
+    // Euler: the graph holds a pair of steps (no copy); an odd count ends
+    // with one copying step launched directly
+    const bool pair = integrator == MM_EULER;
+    const int unit = pair ? 2 : 1;
+    if (nsteps < unit) return batch_step_enqueue(b, integrator, s);
     std::string key = std::to_string(integrator) + (b.merged ? "m" : "g");
     for (const BGroup &g : b.groups) key += "," + std::to_string(g.tile);
     if (!b.exec || b.key != key) {
         drop_graph(b);
         MMK_HIP(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
-        int rc = batch_step_enqueue(b, integrator, b.cap);
+        int rc = batch_step_enqueue(b, integrator, b.cap, pair);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(b.cap, &g);
         if (rc != MM_OK) {
@@ -854,7 +870,8 @@ int mm_batch_step(mm_batch batch, const mm_llg_params *params, float *const *M, 
         b.graph = g;
         b.key = key;
     }
-    for (int i = 0; i < nsteps; ++i) MMK_HIP(hipGraphLaunch(b.exec, s));
+    for (int i = 0; i + unit <= nsteps; i += unit) MMK_HIP(hipGraphLaunch(b.exec, s));
+    if (nsteps % unit) return batch_step_enqueue(b, integrator, s);
     return MM_OK;
 }
 
