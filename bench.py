@@ -573,6 +573,16 @@ def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
     torch.cuda.synchronize()
     ts = (time.perf_counter() - t1) / steps
     err = float((Ms_ - Me).norm() / Me.norm())
+    # the same steps with the residuals read back once per 10 steps
+    pg = mm.LLGParams.make(Ms=w.mat.Ms, A=w.mat.A, alpha=w.mat.alpha, gamma0=w.mat.gamma0, Hext=w.mat.Hext,
+                           dt=w.mat.dt, sur_check_every=10)
+    Mg = M0.clone()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stg = sur.step(plan, pg, Mg, steps, tol=1e-3)
+    torch.cuda.synchronize()
+    tg = (time.perf_counter() - t1) / steps
+    errg = float((Mg - Me).norm() / Me.norm())
     x = torch.randn((3, nz, ny, nx), device="cuda")
     y = torch.empty_like(x)
     # device time of one network evaluation (input normalisation included):
@@ -595,6 +605,14 @@ def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
             "gated_steps": steps, "tol": 1e-3, "stats": st,
             "exact_ms_per_step": te * 1e3, "surrogate_ms_per_step": ts * 1e3,
             "speedup_vs_plain_fp32": te / ts, "state_rel_l2_vs_exact": err,
+            "check_every_10": {"stats": stg, "surrogate_ms_per_step": tg * 1e3, "speedup_vs_plain_fp32": te / tg,
+                               "state_rel_l2_vs_exact": errg},
+            # a gated step is 4 network evaluations (3 stages and the judge)
+            # plus the rest (stages, the judge's exact demag, copies); the
+            # network time per evaluation at which it would equal the exact
+            # step (negative: the rest alone exceeds it)
+            "rest_ms_per_step": (tg - 4 * inf) * 1e3,
+            "breakeven_inference_ms": (te - (tg - 4 * inf)) / 4 * 1e3,
             "inference_ms": inf * 1e3, "inference_tflops": 6.07e10 / inf / 1e12,
             "inference_mfma_frac": 6.07e10 / inf / 2.5e15}
 

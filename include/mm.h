@@ -73,7 +73,11 @@ typedef struct mm_plan_s *mm_plan;
  *          learned increment attached with mm_sur_attach in RK stages 2-4)
  *  log_every  with a stats array, observables after every log_every steps
  *          (<= 0: only after the last step)
- *  sur_tol relative residual above which a surrogate step is redone exactly */
+ *  sur_tol relative residual above which a surrogate step is redone exactly
+ *  sur_check_every  surrogate steps run before the host reads their
+ *          residuals (they are judged on the device); <= 1: every step.
+ *          A group with a residual above sur_tol is redone from its first
+ *          state with exact demag.  At most MM_SUR_CHECK_MAX.             */
 typedef struct {
     double Ms, A, Ku;
     double axis[3];
@@ -85,7 +89,10 @@ typedef struct {
     int demag_mode;
     int log_every;
     double sur_tol;
+    int sur_check_every;
 } mm_llg_params;
+
+#define MM_SUR_CHECK_MAX 256
 
 /* Observables of a state (Sec. 2, eq. (1) with V = dx dy dz per cell):
  * energies in J, torque_max = max_i |M_i x H_eff,i| / Ms in A/m,
@@ -398,9 +405,15 @@ int mm_sur_train_step(mm_sur sur, const float *dm_dev, const float *dh_dev, floa
 
 /* nsteps RK4 steps of M_dev with the learned increment in stages 2-4 and
  * exact demag at stage 1.  Every accepted state is judged against its exact
- * field: if |H_s - H_d| / |H_d| > tol the step is redone with exact demag and
- * the surrogate is skipped for the next step (tol < 0: never redo; tol = 0:
- * always redo, i.e. the plain exact path).  Synchronises every step.       */
+ * field, r = |H_s - H_d| / |H_d|, on the device.  The steps run in groups of
+ * k = params->sur_check_every (1 if <= 1); the host reads a group's
+ * residuals once, after its last step.  If any r > tol the group is redone
+ * from its first state with exact demag and the surrogate is skipped for the
+ * next step (tol < 0: never redo; tol = 0: always redo, i.e. the plain
+ * exact path).  stats->checked counts judged steps, stats->fallbacks steps
+ * redone.  Synchronises once per group.
+ * Errors: MM_EINVAL (NULL, RK4 only, grids differ, k > MM_SUR_CHECK_MAX),
+ * MM_EHIP.                                                                 */
 int mm_llg_step_surrogate(mm_plan plan, mm_sur sur, const mm_llg_params *params, float *M_dev, int nsteps,
                           double tol, mm_sur_stats *stats, void *stream);
 

@@ -411,6 +411,7 @@ static int check_params(const mm_llg_params *q)
         return fail(MM_EINVAL, "non-finite parameter");
     if (q->integrator != MM_RK4 && q->integrator != MM_EULER) return fail(MM_EINVAL, "unknown integrator");
     if (q->demag_mode != MM_EXACT && q->demag_mode != MM_SURROGATE) return fail(MM_EINVAL, "unknown demag mode");
+    if (q->sur_check_every > MM_SUR_CHECK_MAX) return fail(MM_EINVAL, "sur_check_every above MM_SUR_CHECK_MAX");
     const double u2 = q->axis[0] * q->axis[0] + q->axis[1] * q->axis[1] + q->axis[2] * q->axis[2];
     if (q->Ku != 0.0 && !(std::fabs(u2 - 1.0) < 1e-6)) return fail(MM_EINVAL, "anisotropy axis must be a unit vector");
     return MM_OK;

@@ -19,6 +19,7 @@
 // every update, and every reduction runs in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -752,6 +753,31 @@ __global__ __launch_bounds__(256) void k_resid(const float *__restrict__ a, cons
     }
 }
 
+// r = sqrt(sum |a - b|^2 / sum |b|^2) (0 when the second sum is 0) from the
+// nb pairs of k_resid partials, in a fixed order (a strided sum per thread,
+// then a tree; 256 threads, one workgroup), into *r: the gate's residual
+// stays on the device until the host reads a group of them.
+__global__ __launch_bounds__(256) void k_resid_fin(const double *__restrict__ part, int nb, double *__restrict__ r)
+{
+    __shared__ double sh[2][256];
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        s0 += part[2 * i];
+        s1 += part[2 * i + 1];
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *r = sh[1][0] > 0.0 ? sqrt(sh[0][0] / sh[1][0]) : 0.0;
+}
+
 // Sum of squares (FP64 partials per workgroup) of d = (a - b) * s (b may be
 // NULL: d = a * s), and d itself into dout when given: the increment of the
 // state and its scale in one pass.
@@ -811,6 +837,8 @@ struct Sur {
     float *sig = nullptr;                 // device sigma, 1/sigma
     float *tmp = nullptr, *tmp2 = nullptr;  // [3][N] scratch
     float *H0 = nullptr, *Mprev = nullptr, *Hs = nullptr;  // step driver: anchor field, saved state, prediction
+    float *Mgroup = nullptr;              // step driver: first state of a group of gated steps
+    double *rlog = nullptr;               // step driver: residuals of a group, [MM_SUR_CHECK_MAX]
     int adam_t = 0;
     size_t bytes = 0;                     // workspace the buffers above live in
     char *ws = nullptr;                   // bound workspace (nullptr: unbound)
@@ -855,6 +883,8 @@ static size_t sur_layout(Sur &s, char *base)
     take(&s.H0, (size_t)3 * s.N * 4);
     take(&s.Mprev, (size_t)3 * s.N * 4);
     take(&s.Hs, (size_t)3 * s.N * 4);
+    take(&s.Mgroup, (size_t)3 * s.N * 4);
+    take(&s.rlog, (size_t)MM_SUR_CHECK_MAX * 8);
     return off;
 }
 
@@ -1014,19 +1044,11 @@ static int sur_ready(const Sur *s)
 }
 
 // residual of the surrogate against an exact field: |a-b|^2 / |b|^2
-static int resid(Sur &s, const float *a, const float *b, double *r, hipStream_t st)
+// relative residual |a - b| / |b| into the device double *r (no sync)
+static void resid_enqueue(Sur &s, const float *a, const float *b, double *r, hipStream_t st)
 {
     hipLaunchKernelGGL(k_resid, dim3(RED_B), dim3(256), 0, st, a, b, s.dpart, 3 * s.N);
-    std::vector<double> hp(2 * RED_B);
-    MMK_HIP(hipMemcpyAsync(hp.data(), s.dpart, sizeof(double) * 2 * RED_B, hipMemcpyDeviceToHost, st));
-    MMK_HIP(hipStreamSynchronize(st));
-    double n0 = 0, n1 = 0;
-    for (int i = 0; i < RED_B; ++i) {
-        n0 += hp[2 * i];
-        n1 += hp[2 * i + 1];
-    }
-    *r = n1 > 0 ? std::sqrt(n0 / n1) : 0.0;
-    return MM_OK;
+    hipLaunchKernelGGL(k_resid_fin, dim3(1), dim3(256), 0, st, s.dpart, RED_B, r);
 }
 
 // H = H0 + Ms * sigma * Net((Mstage - Mn) / (Ms sigma)) on stream st (no sync)
@@ -1251,9 +1273,11 @@ int mm_sur_zero(mm_sur sur)
 }
 
 // Steps with the learned increment in RK stages 2-4, exact demag at stage 1,
-// and the accepted state judged against the exact field of that state (the
-// next step's stage-1 field): relative residual above `tol` redoes the step
-// with exact demag everywhere and keeps the surrogate off for one step.
+// and every accepted state judged on the device against the exact field of
+// that state (the next step's stage-1 field).  The steps run in groups of
+// k = sur_check_every; after a group the host reads its k residuals, and one
+// above `tol` redoes the group from its first state with exact demag and
+// keeps the surrogate off for one step.
 int mm_llg_step_surrogate(mm_plan plan, mm_sur sur, const mm_llg_params *params, float *M, int nsteps, double tol,
                           mm_sur_stats *stats, void *stream)
 {
@@ -1262,52 +1286,68 @@ int mm_llg_step_surrogate(mm_plan plan, mm_sur sur, const mm_llg_params *params,
     if (!params || !M) return fail(MM_EINVAL, "NULL params or M");
     if (params->integrator != MM_RK4) return fail(MM_EINVAL, "surrogate stepping needs RK4");
     if (nsteps < 0) return fail(MM_EINVAL, "nsteps < 0");
+    if (params->sur_check_every > MM_SUR_CHECK_MAX) return fail(MM_EINVAL, "sur_check_every above MM_SUR_CHECK_MAX");
     Plan &p = *pp;
     Sur &s = *sur->s;
     if (s.N != p.cells()) return fail(MM_EINVAL, "surrogate and plan grids differ");
     hipStream_t st = (hipStream_t)stream;
     const StageCoef c = stage_coef(p, *params);
     const size_t bytes = sizeof(float) * 3 * (size_t)p.cells();
+    const int K = params->sur_check_every > 1 ? params->sur_check_every : 1;
     float *H0 = s.H0, *Mprev = s.Mprev, *Hs = s.Hs;
     mm_sur_stats acc{};
+    std::vector<double> r((size_t)K);
     bool use = true;
-    int rc = MM_OK;
     // exact field of the current state
-    rc = demag_enqueue(p, M, H0, st);
-    for (int n = 0; n < nsteps && rc == MM_OK; ++n) {
-        (void)hipMemcpyAsync(Mprev, M, bytes, hipMemcpyDeviceToDevice, st);
-        if (use) {
+    int rc = demag_enqueue(p, M, H0, st);
+    for (int n = 0; n < nsteps && rc == MM_OK;) {
+        if (!use) {  // the step after a redone group
+            rc = llg_enqueue_step(p, c, MM_RK4, M, st);
+            if (rc == MM_OK) rc = demag_enqueue(p, M, H0, st);
+            use = true;
+            acc.steps += 1;
+            n += 1;
+            continue;
+        }
+        const int k = std::min(K, nsteps - n);
+        // the group's first state (a one-step group has it in Mprev)
+        if (k > 1) (void)hipMemcpyAsync(s.Mgroup, M, bytes, hipMemcpyDeviceToDevice, st);
+        for (int j = 0; j < k && rc == MM_OK; ++j) {
+            (void)hipMemcpyAsync(Mprev, M, bytes, hipMemcpyDeviceToDevice, st);
             rc = llg_step_with_fields(p, c, M, H0, st, [&](int stage, const float *Sstate, float *Hout) {
                 (void)stage;
                 sur_field(s, Sstate, Mprev, H0, c.Ms, Hout, st);
                 return MM_OK;
             });
-            // judge the accepted state
-            if (rc == MM_OK) rc = demag_enqueue(p, M, p.H, st);  // exact H of M_{n+1}
-            if (rc == MM_OK) sur_field(s, M, Mprev, H0, c.Ms, Hs, st);
-            double r = 0.0;
-            if (rc == MM_OK) rc = resid(s, Hs, p.H, &r, st);
-            if (rc != MM_OK) break;
-            acc.last_residual = r;
-            acc.max_residual = r > acc.max_residual ? r : acc.max_residual;
-            acc.sum_residual += r;
-            acc.checked += 1;
-            if (tol >= 0.0 && !(r <= tol)) {
-                // redo with exact demag from the saved state
-                acc.fallbacks += 1;
-                (void)hipMemcpyAsync(M, Mprev, bytes, hipMemcpyDeviceToDevice, st);
-                rc = llg_enqueue_step(p, c, MM_RK4, M, st);
-                if (rc == MM_OK) rc = demag_enqueue(p, M, H0, st);
-                use = false;
-            } else {
+            // judge the accepted state: exact H of M_{n+1} against the network's
+            if (rc == MM_OK) rc = demag_enqueue(p, M, p.H, st);
+            if (rc == MM_OK) {
+                sur_field(s, M, Mprev, H0, c.Ms, Hs, st);
+                resid_enqueue(s, Hs, p.H, s.rlog + j, st);
                 (void)hipMemcpyAsync(H0, p.H, bytes, hipMemcpyDeviceToDevice, st);
             }
-        } else {
-            rc = llg_enqueue_step(p, c, MM_RK4, M, st);
-            if (rc == MM_OK) rc = demag_enqueue(p, M, H0, st);
-            use = true;
         }
-        acc.steps += 1;
+        if (rc != MM_OK) break;
+        MMK_HIP(hipMemcpyAsync(r.data(), s.rlog, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+        MMK_HIP(hipStreamSynchronize(st));
+        bool redo = false;
+        for (int j = 0; j < k; ++j) {
+            acc.last_residual = r[j];
+            acc.max_residual = r[j] > acc.max_residual ? r[j] : acc.max_residual;
+            acc.sum_residual += r[j];
+            acc.checked += 1;
+            if (tol >= 0.0 && !(r[j] <= tol)) redo = true;
+        }
+        if (redo) {
+            // the whole group again with exact demag from its first state
+            acc.fallbacks += k;
+            (void)hipMemcpyAsync(M, k > 1 ? s.Mgroup : Mprev, bytes, hipMemcpyDeviceToDevice, st);
+            for (int j = 0; j < k && rc == MM_OK; ++j) rc = llg_enqueue_step(p, c, MM_RK4, M, st);
+            if (rc == MM_OK) rc = demag_enqueue(p, M, H0, st);
+            use = false;
+        }
+        acc.steps += k;
+        n += k;
     }
     if (stats) *stats = acc;
     if (rc == MM_OK) {

@@ -20,6 +20,7 @@ MM_OK, MM_EINVAL, MM_ENOMEM, MM_ENODEV, MM_EHIP, MM_ENONFINITE, MM_ETUNE, MM_EUN
     0, -1, -2, -3, -4, -5, -6, -7
 MM_RK4, MM_EULER = 0, 1
 MM_EXACT, MM_SURROGATE = 0, 1
+MM_SUR_CHECK_MAX = 256  # most surrogate steps per residual read-back
 PASSES = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "yconv", "stage", "reduce", "xstage")
 NPASS = len(PASSES)
 PASS_INDEX = {n: i for i, n in enumerate(PASSES)}
@@ -59,17 +60,17 @@ class LLGParams(C.Structure):
                 ("axis", C.c_double * 3), ("alpha", C.c_double), ("gamma0", C.c_double),
                 ("Hext", C.c_double * 3), ("dt", C.c_double), ("integrator", C.c_int),
                 ("renorm", C.c_int), ("demag_mode", C.c_int), ("log_every", C.c_int),
-                ("sur_tol", C.c_double)]
+                ("sur_tol", C.c_double), ("sur_check_every", C.c_int)]
 
     @classmethod
     def make(cls, Ms, A, Ku=0.0, axis=(1.0, 0.0, 0.0), alpha=0.5, gamma0=2.211e5,
              Hext=(0.0, 0.0, 0.0), dt=1e-14, integrator="rk4", renorm=True, demag="exact",
-             log_every=0, sur_tol=1e-3):
+             log_every=0, sur_tol=1e-3, sur_check_every=1):
         return cls(float(Ms), float(A), float(Ku), (C.c_double * 3)(*map(float, axis)),
                    float(alpha), float(gamma0), (C.c_double * 3)(*map(float, Hext)), float(dt),
                    MM_EULER if integrator == "euler" else MM_RK4, 1 if renorm else 0,
                    MM_SURROGATE if demag == "surrogate" else MM_EXACT, int(log_every),
-                   float(sur_tol))
+                   float(sur_tol), int(sur_check_every))
 
 
 class Stats(C.Structure):

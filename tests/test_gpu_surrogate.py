@@ -155,6 +155,39 @@ def test_gate_at_zero_tolerance_is_the_exact_path():
     assert np.isfinite(to_host(c)).all()
 
 
+def test_grouped_gate_matches_per_step_gate():
+    """Residuals judged on the device and read back once per group of 4
+    steps: with nothing redone the state and the residual statistics equal
+    those of per-step read-back bitwise; at tol = 0 every group is redone
+    from its first state and the state is the exact path's; a group longer
+    than MM_SUR_CHECK_MAX is refused."""
+    from paper_1406_7459_amd import mm
+    nx, ny, nz = 32, 16, 4
+    d = (4e-9, 4e-9, 4e-9)
+    plan = mm.Plan(nx, ny, nz, *d)
+    sur = mm.Surrogate(nx, ny, nz)
+    sur.set_params(flat(S.init_params(9)))
+    kw = dict(Ms=8e5, A=1.3e-11, alpha=0.1, dt=1e-14, Hext=(1e4, 0, 0))
+    p1 = mm.LLGParams.make(**kw)
+    p4 = mm.LLGParams.make(**kw, sur_check_every=4)
+    M0 = to_dev(8e5 * W.random_unit(nx, ny, nz, 12))
+    a, b = M0.clone(), M0.clone()
+    sa = sur.step(plan, p1, a, 10, tol=-1.0)
+    sb = sur.step(plan, p4, b, 10, tol=-1.0)  # groups of 4, 4 and 2 steps
+    assert np.array_equal(to_host(a), to_host(b))
+    assert sa == sb and sb["checked"] == 10 and sb["fallbacks"] == 0
+    c, e = M0.clone(), M0.clone()
+    sc = sur.step(plan, p4, c, 10, tol=0.0)
+    plan.step(p1, e, 10)
+    assert np.array_equal(to_host(c), to_host(e))
+    # a group of 4 redone, one exact step, a group of 4 redone, one exact step
+    assert sc["steps"] == 10 and sc["checked"] == 8 and sc["fallbacks"] == 8
+    with pytest.raises(Exception):
+        sur.step(plan, mm.LLGParams.make(**kw, sur_check_every=mm.MM_SUR_CHECK_MAX + 1), M0.clone(), 2, tol=1.0)
+    sur.close()
+    plan.close()
+
+
 def test_trained_network_beats_no_network_at_the_gate():
     """Train online on solver pairs of a 64x64x4 film (a few hundred Adam
     steps), then step a held-out trajectory through the gate: the residual of
