@@ -699,6 +699,64 @@ def summarize_surrogate(db):
     return "\n".join(out) + "\n"
 
 
+SUR_SQ_SETS = {
+    "sq_A": ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_WAVE_CYCLES",
+             "SQ_BUSY_CYCLES", "SQ_VALU_MFMA_BUSY_CYCLES"),
+    "sq_B": SQ_SETS["sq_B"],
+}
+
+
+def summarize_surrogate_counters(pmc_dir):
+    """Text of profiles/sq_surrogate_film256.txt from the two rocprofv3 --pmc
+    runs (SUR_SQ_SETS) of bench.py --surrogate-profile under pmc_dir: per
+    convolution kernel the median per dispatch of each counter (summed over
+    the chip), per-wave instruction counts, the matrix cores' busy time per
+    SIMD, and ratios of counters in the same units."""
+    import glob
+    import re
+    import sqlite3
+    import statistics
+    per = {}
+    for kind in SUR_SQ_SETS:
+        db = glob.glob(os.path.join(pmc_dir, kind, "**", "*.db"), recursive=True)[0]
+        con = sqlite3.connect(db)
+        rows = {}
+        for disp, kname, cname, v in con.execute(
+                "select dispatch_id, kernel_name, counter_name, value from counters_collection"):
+            c = rows.setdefault((disp, kname), {})
+            c[cname] = c.get(cname, 0.0) + v
+        for (disp, kname), cs in rows.items():
+            k = re.sub(r"\(.*", "", _demangle_mmk(kname)).replace("void ", "")
+            for c, v in cs.items():
+                per.setdefault(k, {}).setdefault(c, []).append(v)
+    cmd = ["#   rocprofv3 --pmc %s -d $OUT/sq_sur/%s -o %s -- python3 $REPO/bench.py --surrogate-profile"
+           % (" ".join(cs), kind, kind) for kind, cs in SUR_SQ_SETS.items()]
+    out = ["# SQ counters per launch of the learned form's convolutions, film256 (256x256x4 cells), rocprofv3 --pmc",
+           "# commands (from /tmp on the GPU, REPO = repository root, OUT = an output folder):", *cmd,
+           "#   python3 bench.py --summarize-surrogate-counters $OUT/sq_sur",
+           "# columns: waves; VALU, MFMA, LDS, VMEM-read instructions per wave; mfma_us = SQ_VALU_MFMA_BUSY_CYCLES",
+           "# / (1024 SIMDs x 2.4 GHz), the matrix cores' busy time per SIMD (a launch's duration is in",
+           "# surrogate_film256.txt); lds_conf = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS; wait =",
+           "# SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; w_any = SQ_WAIT_ANY / SQ_WAVE_CYCLES; act =",
+           "# SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES",
+           "%-30s %6s %6s %5s %5s %6s %8s %8s %6s %6s %6s" % ("kernel", "waves", "valu", "mfma", "lds", "vmem", "mfma_us",
+                                                          "lds_conf", "wait", "w_any", "act")]
+    for k in sorted(per):
+        if not k.startswith("mmk::k_conv"):
+            continue
+        m = {c: statistics.median(v) for c, v in per[k].items()}
+        w = m.get("SQ_WAVES") or 1.0
+        wc = m.get("SQ_WAVE_CYCLES") or 1.0
+        lds = m.get("SQ_ACTIVE_INST_LDS", 0.0)
+        out.append("%-30s %6d %6.0f %5.0f %5.0f %6.1f %8.2f %8s %6.3f %6.3f %6.3f" % (
+            k[:30], w, m.get("SQ_INSTS_VALU", 0.0) / w, m.get("SQ_INSTS_MFMA", 0.0) / w,
+            m.get("SQ_INSTS_LDS", 0.0) / w, m.get("SQ_INSTS_VMEM_RD", 0.0) / w,
+            m.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / 1024 / 2400.0,
+            "%.3f" % (m.get("SQ_LDS_BANK_CONFLICT", 0.0) / lds) if lds else "-",
+            m.get("SQ_WAIT_INST_ANY", 0.0) / wc, m.get("SQ_WAIT_ANY", 0.0) / wc, m.get("SQ_ACTIVE_INST_ANY", 0.0) / wc))
+    return "\n".join(out) + "\n"
+
+
 def table1_euler(torch, mm, W):
     """Per-step time with explicit Euler on N^3 cubes, N = 8 ... 128 (the shape
     of the paper's Table 1; material of the cube workload)."""
@@ -814,6 +872,8 @@ def main():
                     help="run only the learned form's profiled launches (for rocprofv3)")
     ap.add_argument("--summarize-surrogate", metavar="DB",
                     help="print profiles/surrogate_film256.txt from a kernel-trace database")
+    ap.add_argument("--summarize-surrogate-counters", metavar="PMC_DIR",
+                    help="print profiles/sq_surrogate_film256.txt from the two --pmc runs under PMC_DIR")
     ap.add_argument("--sweep-tiles", action="store_true",
                     help="run only five demag evaluations with every valid tile of every pass "
                          "(for per-tile hardware counters)")
@@ -826,6 +886,9 @@ def main():
         return
     if args.summarize_surrogate:
         sys.stdout.write(summarize_surrogate(args.summarize_surrogate))
+        return
+    if args.summarize_surrogate_counters:
+        sys.stdout.write(summarize_surrogate_counters(args.summarize_surrogate_counters))
         return
     if args.summarize_trace:
         sys.stdout.write(summarize_trace(*args.summarize_trace))

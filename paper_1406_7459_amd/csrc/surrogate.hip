@@ -824,7 +824,7 @@ struct Sur {
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     __bf16 *wb = nullptr, *wt = nullptr;  // bf16 forward / mirrored-transposed copies
     __bf16 *Xin = nullptr;                // network input, zero-padded: [G][8] (PadGeom positions)
-    __bf16 *X[NLAYER] = {};               // inputs of layers 1.., [N][32] (X[0] unused)
+    __bf16 *X[NLAYER] = {};               // X[l]: input of layer l >= 1, [N][32] (layer 0 reads Xin)
     __bf16 *Zh[NLAYER - 1] = {};          // hidden pre-activations (training), [N][32]
     float *Zout = nullptr;                // last layer's output before the scale, [N][4] (channels 0-2)
     __bf16 *dZb[2] = {};                  // [N][32], this layer's dZ and the one below
