@@ -167,11 +167,12 @@ __device__ __forceinline__ void yfwd_body(const float2 *__restrict__ X1, float2 
 {
     constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
+    static_assert((Q & (Q - 1)) == 0, "threads per transform: a power of two");
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int P = 1 << lp2;
     const int t = threadIdx.x;
-    const int p = t & (P - 1), q = t >> lp2;
+    const int p = t & (P - 1), q = (t >> lp2) & (Q - 1);  // t < P Q: the mask only states q < Q
     int kx, plane;
     const bool ok = column_of(nxc, P, p, bx, slot, nedge, kx, plane);
     const int xp = x_pitch(nxc);
@@ -249,10 +250,11 @@ __device__ __forceinline__ void conv_reg3_body(float2 *__restrict__ X, const flo
                                                int nedge = 0)
 {
     constexpr int E = Factors<L, O>::E, Q = L / E, NH = L / 2;
+    static_assert((Q & (Q - 1)) == 0, "threads per transform: a power of two");
     extern __shared__ float2 lds[];
     const int P = 1 << lp2;
     const int t = threadIdx.x;
-    const int p = t & (P - 1), q = t >> lp2;
+    const int p = t & (P - 1), q = (t >> lp2) & (Q - 1);  // t < P Q: the mask only states q < Q
     int kx, ky;
     const bool ok = column_of(nxc, P, p, bx, slot, nedge, kx, ky);
     const int xp = x_pitch(nxc);
@@ -343,12 +345,13 @@ __device__ __forceinline__ void conv_split_body(float2 *__restrict__ X, const fl
                                                 int nlive, int lp2, const float2 *__restrict__ tw, int bx, int ky)
 {
     constexpr int E = ept<L, V>(), Q = L / E, NH = L / 2;
+    static_assert((Q & (Q - 1)) == 0, "threads per transform: a power of two");
     extern __shared__ float2 lds[];
     const int P = 1 << lp2;
     const int PQ = P * Q;
     const int g = threadIdx.x / PQ;
     const int t = threadIdx.x - g * PQ;
-    const int p = t & (P - 1), q = t >> lp2;
+    const int p = t & (P - 1), q = (t >> lp2) & (Q - 1);  // t < P Q: the mask only states q < Q
     const int kx = bx * P + p;
     const bool ok = kx < nxc;
     const int xp = x_pitch(nxc);
@@ -450,11 +453,12 @@ __device__ __forceinline__ void yinv_body(const float2 *__restrict__ X2, float2 
 {
     constexpr int OV = order_of_v<V>();
     constexpr int E = ept<L, V>(), Q = L / E, NY = L / 2;
+    static_assert((Q & (Q - 1)) == 0, "threads per transform: a power of two");
     extern __shared__ float2 lds[];
     const float2 *twl = stage_twiddles<L>(lds, tw);
     const int P = 1 << lp2;
     const int t = threadIdx.x;
-    const int p = t & (P - 1), q = t >> lp2;
+    const int p = t & (P - 1), q = (t >> lp2) & (Q - 1);  // t < P Q: the mask only states q < Q
     int kx, plane;
     const bool ok = column_of(nxc, P, p, bx, slot, nedge, kx, plane);
     const int xp = x_pitch(nxc);
