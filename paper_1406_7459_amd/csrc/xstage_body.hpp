@@ -60,8 +60,8 @@ __device__ __forceinline__ void xstage_body(float2 *__restrict__ X1, const float
     const int PQ = P * Q;
     const int t = threadIdx.x;
     const int g = t / PQ;  // component of this thread's transforms
-    const int tt = t - g * PQ;
-    const int q = tt % Q, p = tt / Q;
+    const unsigned tt = (unsigned)(t - g * PQ);  // in [0, PQ): unsigned, so the compiler sees q < Q
+    const int q = (int)(tt % Q), p = (int)(tt / Q);
     const int ncr = nz * ny;  // cell rows per component
     const int r0 = bx * 2 * P;
     const int ra = r0 + 2 * p, rb = ra + 1;
