@@ -555,34 +555,33 @@ def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
                           dt=w.mat.dt)
     M0 = torch.from_numpy((w.mat.Ms * w.initial_unit()).astype("float32")).cuda()
     plan.step(p, M0, 20)
-    Me = M0.clone()
-    plan.step(p, Me, 2)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.step(p, Me, steps)
-    torch.cuda.synchronize()
-    te = (time.perf_counter() - t1) / steps
-    Me = M0.clone()
-    plan.step(p, Me, steps)
-    Ms_ = M0.clone()
-    sur.step(plan, p, Ms_, 2, tol=1e-3)
-    Ms_ = M0.clone()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = sur.step(plan, p, Ms_, steps, tol=1e-3)
-    torch.cuda.synchronize()
-    ts = (time.perf_counter() - t1) / steps
-    err = float((Ms_ - Me).norm() / Me.norm())
+    # each driver: one warm-up call, then the best per-step time of five runs
+    # of `steps` steps from M0 in one buffer (the exact path's step graph is
+    # keyed by the state's address)
+    Mx = M0.clone()
+
+    def best_of(run, reps=5):
+        best, r = float("inf"), None
+        for _ in range(reps):
+            Mx.copy_(M0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = run()
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t1) / steps)
+        return best, r
+
+    plan.step(p, Mx, 2)
+    te, _ = best_of(lambda: plan.step(p, Mx, steps))
+    Me = Mx.clone()
+    sur.step(plan, p, Mx, 2, tol=1e-3)
+    ts, st = best_of(lambda: sur.step(plan, p, Mx, steps, tol=1e-3))
+    err = float((Mx - Me).norm() / Me.norm())
     # the same steps with the residuals read back once per 10 steps
     pg = mm.LLGParams.make(Ms=w.mat.Ms, A=w.mat.A, alpha=w.mat.alpha, gamma0=w.mat.gamma0, Hext=w.mat.Hext,
                            dt=w.mat.dt, sur_check_every=10)
-    Mg = M0.clone()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stg = sur.step(plan, pg, Mg, steps, tol=1e-3)
-    torch.cuda.synchronize()
-    tg = (time.perf_counter() - t1) / steps
-    errg = float((Mg - Me).norm() / Me.norm())
+    tg, stg = best_of(lambda: sur.step(plan, pg, Mx, steps, tol=1e-3))
+    errg = float((Mx - Me).norm() / Me.norm())
     x = torch.randn((3, nz, ny, nx), device="cuda")
     y = torch.empty_like(x)
     # device time of one network evaluation (input normalisation included):
