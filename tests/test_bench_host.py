@@ -84,3 +84,37 @@ def test_mangled_kernel_names_are_shortened():
         "_ZN3mmk6k_convILi0ELb1ELb0EEEvPKDF16bS2_PKfPfPDF16bS6_S5_fS4_iiiiiS6_NS_7PadGeomE") == "mmk::k_conv<0, true, false>"
     assert bench._demangle_mmk("_ZN3mmk5k_mseEPKfS1_fPDF16bS2_NS_7PadGeomEPd") == "mmk::k_mse"
     assert bench._demangle_mmk("void mmk::k_adam(float*)") == "void mmk::k_adam(float*)"
+
+
+def test_surrogate_counter_summary_from_synthetic_databases(tmp_path):
+    # two counter databases in the layout rocprofv3 writes (one row per
+    # dispatch, kernel and counter, per shader engine here: summed), one
+    # convolution with two dispatches and one other kernel that is left out
+    import sqlite3
+    vals = {"SQ_WAVES": 4096, "SQ_INSTS_VALU": 4096 * 680, "SQ_INSTS_MFMA": 4096 * 180, "SQ_INSTS_LDS": 4096 * 61,
+            "SQ_INSTS_VMEM_RD": 4096 * 45, "SQ_WAVE_CYCLES": 1000000, "SQ_BUSY_CYCLES": 50000,
+            "SQ_VALU_MFMA_BUSY_CYCLES": 1024 * 2400 * 4.8, "SQ_ACTIVE_INST_VALU": 1, "SQ_ACTIVE_INST_LDS": 400,
+            "SQ_LDS_BANK_CONFLICT": 1000, "SQ_WAIT_INST_ANY": 300000, "SQ_WAIT_ANY": 500000,
+            "SQ_ACTIVE_INST_ANY": 200000}
+    conv = "_ZN3mmk6k_convILi3ELb1ELb1EEEvPKDF16bS2_PKfPfPDF16bS6_S5_fS4_iiiiiS6_NS_7PadGeomE"
+    for kind, names in bench.SUR_SQ_SETS.items():
+        d = tmp_path / kind / "host"
+        d.mkdir(parents=True)
+        con = sqlite3.connect(str(d / "x_results.db"))
+        con.execute("create table counters_collection (dispatch_id int, kernel_name text, counter_name text, "
+                    "value real)")
+        for disp in (1, 2):
+            for c in names:
+                for se in range(2):  # two halves that the summary adds up
+                    con.execute("insert into counters_collection values (?, ?, ?, ?)", (disp, conv, c, vals[c] / 2))
+        con.execute("insert into counters_collection values (3, 'void mmk::k_adam(float*)', 'SQ_WAVES', 4)")
+        con.commit()
+        con.close()
+    text = bench.summarize_surrogate_counters(str(tmp_path))
+    rows = [ln for ln in text.splitlines() if ln.startswith("mmk::")]
+    assert len(rows) == 1 and rows[0].startswith("mmk::k_conv<3, true, true>")
+    f = rows[0][30:].split()
+    assert f[:5] == ["4096", "680", "180", "61", "45.0"]
+    assert f[5] == "4.80" and f[6] == "2.500"
+    assert f[7:] == ["0.300", "0.500", "0.200"]
+    assert "--summarize-surrogate-counters" in text
