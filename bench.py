@@ -606,8 +606,8 @@ def surrogate_measure(torch, mm, W, train_s=20.0, steps=20):
             "speedup_vs_plain_fp32": te / ts, "state_rel_l2_vs_exact": err,
             "check_every_10": {"stats": stg, "surrogate_ms_per_step": tg * 1e3, "speedup_vs_plain_fp32": te / tg,
                                "state_rel_l2_vs_exact": errg},
-            # a gated step is 4 network evaluations (3 stages and the judge)
-            # plus the rest (stages, the judge's exact demag, copies); the
+            # a gated step is 4 network evaluations (3 stages and the gate's check)
+            # plus the rest (stages, the gate's exact demag, copies); the
             # network time per evaluation at which it would equal the exact
             # step (negative: the rest alone exceeds it)
             "rest_ms_per_step": (tg - 4 * inf) * 1e3,
